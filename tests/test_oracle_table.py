@@ -1,0 +1,157 @@
+"""Pins of the oracle's dispersion analysis and weight table (CPU only).
+
+Each test checks the oracle against something other than itself: another
+equation of the paper, a textbook special case, a property every minimiser of
+the regularised problem has, or a qualitative statement the paper makes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import table as T
+
+
+@pytest.fixture(scope="module")
+def table():
+    Gs, W = T.build_table(3.0, 20.0, 0.05, 1e-3)
+    return Gs, W
+
+
+def test_rows_match_phase_velocity_equation():
+    """sum_l H_l w_l - g equals (2 pi^2/G^2) J (v~^2 - 1) for arbitrary weights:
+    the linear system of Sec. 2.2 is v~ = 1 rearranged.  A wrong constant in any
+    row (as in the printed H_2) breaks it."""
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        G = rng.uniform(2.5, 40.0)
+        th = rng.uniform(0, np.pi / 2)
+        ph = rng.uniform(0, np.pi / 4)
+        w5 = rng.uniform(-0.5, 1.0, 5)
+        w7 = T.complete_weights(w5)
+        H, g = T.dispersion_rows(G, th, ph)
+        A, B, C = T.abc(G, th, ph)
+        J = w7[3] + 2 * w7[4] * C + 4 * w7[5] * B + 8 * w7[6] * A
+        if J <= 0:
+            continue
+        v = T.phase_velocity(G, th, ph, w7)
+        lhs = float(H @ w5 - g)
+        rhs = 2 * np.pi ** 2 / G ** 2 * J * (v ** 2 - 1.0)
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+def test_printed_h2_differs_by_constant_half():
+    """The printed H_2 lacks the constant: H_2(derived) - H_2(printed) = 1/2."""
+    for G in (3.0, 7.3, 20.0):
+        H, _ = T.dispersion_rows(G, 0.3, 0.2)
+        A, B, C = T.abc(G, 0.3, 0.2)
+        printed = 0.5 * (3 * A - 5 * B / 3 + C / 3)
+        assert abs(H[1] - printed - 0.5) < 1e-14
+
+
+def test_seven_point_textbook_dispersion():
+    """w_s1 = 1 with lumped mass (w_m0 = 1) is the classical 7-point stencil;
+    along an axis its phase velocity is (G/pi) sin(pi/G) (textbook
+    second-order dispersion)."""
+    w7 = np.array([1, 0, 0, 1, 0, 0, 0], float)
+    for G in (3.0, 4.0, 10.0, 25.0):
+        v = T.phase_velocity(G, 0.0, 0.0, w7)
+        assert abs(v - G / math.pi * math.sin(math.pi / G)) < 1e-14
+
+
+def test_consistency_large_G():
+    """Any weights obeying the two sum constraints give v~ -> 1 as G -> inf."""
+    rng = np.random.default_rng(2)
+    w7 = T.complete_weights(rng.uniform(0, 0.5, 5))
+    v = T.phase_velocity(1e4, 0.4, 0.3, w7)
+    assert abs(v - 1) < 1e-6
+
+
+def test_table_shape_and_grid(table):
+    Gs, W = table
+    assert W.shape == (341, 5)
+    assert Gs[0] == 3.0 and abs(Gs[-1] - 20.0) < 1e-12
+    assert np.all(np.diff(Gs) > 0)
+
+
+def test_table_normal_equations(table):
+    """A minimiser of ||Hw-g||^2 + lambda ||DPw||^2 satisfies the normal
+    equations (H^T H + lambda L^T L) w = H^T g."""
+    Gs, W = table
+    assert T.table_normal_residual(Gs, W, 1e-3) < 1e-9
+
+
+def test_table_constraints(table):
+    """sum w_s = 1 and w_m0 + 6 w_m1 + 12 w_m2 + 8 w_m3 = 1 on every row."""
+    _, W = table
+    w7 = T.complete_weights(W)
+    assert np.allclose(w7[:, :3].sum(1), 1.0, atol=1e-14)
+    assert np.allclose(w7[:, 3] + 6 * w7[:, 4] + 12 * w7[:, 5] + 8 * w7[:, 6], 1.0, atol=1e-14)
+
+
+def test_adaptive_table_is_accurate(table):
+    """The adaptive weights reduce dispersion very significantly over the whole
+    G range (Sec. 2.2): worst |v~ - 1| over G in [3, 20] and all angles stays
+    below 5e-4 (the fixed G4 weights reach ~3e-2 there)."""
+    Gs, W = table
+    err = T.worst_phase_error(Gs, W)
+    assert err < 5e-4
+    w4 = T.fit_fixed([4.0])
+    err4 = T.worst_phase_error(Gs, np.broadcast_to(w4, W.shape))
+    assert err4 > 20 * err
+
+
+def test_table_is_smooth(table):
+    """Tikhonov smoothing: successive rows differ by small amounts."""
+    _, W = table
+    assert np.max(np.abs(np.diff(W, axis=0))) < 5e-3
+
+
+def test_lambda_large_limit():
+    """lambda -> infinity forces one weight vector for all G."""
+    Gs, W = T.build_table(3.0, 6.0, 0.5, 1e8)
+    assert np.max(np.ptp(W, axis=0)) < 1e-4
+
+
+def test_lambda_small_fits_each_G_better():
+    """A smaller lambda never increases the data misfit."""
+    th, ph = T.angle_grid()
+
+    def misfit(Gs, W):
+        return sum(float(np.sum((T.dispersion_rows(g, th, ph)[0] @ w - T.dispersion_rows(g, th, ph)[1]) ** 2))
+                   for g, w in zip(Gs, W))
+
+    Gs, Wa = T.build_table(3.0, 8.0, 0.25, 1e-1)
+    _, Wb = T.build_table(3.0, 8.0, 0.25, 1e-5)
+    assert misfit(Gs, Wb) <= misfit(Gs, Wa) * (1 + 1e-9)
+
+
+def test_g4_worst_error_near_5p5():
+    """Weights fitted for G = 4 only: accurate at 4, worst for G > 4 at
+    G ~ 5.5 (Sec. 2.2)."""
+    w7 = T.complete_weights(T.fit_fixed([4.0]))
+    th, ph = T.angle_grid()
+    Gf = np.linspace(4.2, 20.0, 791)
+    e = np.array([np.max(np.abs(T.phase_velocity(g, th, ph, w7) - 1)) for g in Gf])
+    gworst = Gf[np.argmax(e)]
+    assert 5.0 <= gworst <= 6.0
+    e4 = np.max(np.abs(T.phase_velocity(4.0, th, ph, w7) - 1))
+    assert e4 < 1e-4
+
+
+def test_gm_trades_accuracy_at_g4():
+    """Weights fitted jointly for G = 4, 6, 8, 10 are less accurate at G = 4
+    than the G4 weights but better balanced over 4..10 (Sec. 2.2)."""
+    th, ph = T.angle_grid()
+    w4 = T.complete_weights(T.fit_fixed([4.0]))
+    wm = T.complete_weights(T.fit_fixed([4.0, 6.0, 8.0, 10.0]))
+    err = lambda w, g: np.max(np.abs(T.phase_velocity(g, th, ph, w) - 1))  # noqa: E731
+    assert err(wm, 4.0) > err(w4, 4.0)
+    Gr = np.linspace(4, 10, 61)
+    assert max(err(wm, g) for g in Gr) < max(err(w4, g) for g in Gr)
+
+
+def test_g_grid_direct():
+    Gs = T.g_grid(3.0, 20.0, 0.05)
+    assert len(Gs) == 341
+    assert Gs[140] == 3.0 + 140 * 0.05
