@@ -1,0 +1,231 @@
+/*
+ * helm27 -- wavelength-adaptive 27-point frequency-domain Helmholtz operator
+ * and solver for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Aghamiry, Gholami, Combe, Operto, "Accurate 3D frequency-domain
+ * seismic wave modeling with the wavelength-adaptive 27-point finite-difference
+ * stencil"):
+ *   - a table of stencil weights over G (grid points per wavelength), each
+ *     entry minimising numerical dispersion for its G, smoothed along G by a
+ *     Tikhonov term (Sec. 2.2);
+ *   - an impedance matrix [M + S] whose every row uses the weights of its local
+ *     G = c / (f h) (Sec. 3.1, "GA"), with a 27-point weighted stiffness
+ *     (Sec. 2.1, weighted sum over the Cartesian, 45-degree-rotated and
+ *     cube-diagonal stencils), a consistent mass (Sec. 2.1, second form:
+ *     bulk modulus at the collocation point) and PML by complex coordinate
+ *     stretching (Sec. 2.1);
+ *   - solutions for point sources (Sec. 3.1).  The paper factorises the matrix
+ *     with a sparse direct solver; this library solves it matrix-free with
+ *     restarted GMRES preconditioned by a complex-shifted-Laplacian multigrid
+ *     whose smoother is the same stencil kernel, with FP64 iterative refinement
+ *     around complex-FP32 inner iterations.
+ *
+ * Conventions
+ *   - Grid order: x fastest, lin = i + nx * (j + ny * k).  A multi-vector of
+ *     nrhs right-hand sides is [nrhs][nz][ny][nx], contiguous.
+ *   - Complex data are interleaved (re, im): HELM27_C64 = 2 x float,
+ *     HELM27_C128 = 2 x double.
+ *   - Time convention exp(-i omega t); outgoing waves decay in the PML.
+ *   - Every call returns an int status: HELM27_OK (0) or a negative code
+ *     below; helm27_strerror() names it.  No exception crosses this boundary.
+ *   - Ownership: the caller owns every buffer it passes (host or device
+ *     pointers as stated per argument); the library owns everything behind
+ *     its handles and frees it in the matching *_destroy call.
+ *   - Threading: a context and the objects made from it may be used by one
+ *     host thread at a time; the serving calls are internally synchronised.
+ *   - Streams: a NULL stream means the default (null) stream of the device.
+ */
+#ifndef HELM27_H
+#define HELM27_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define HELM27_OK         0
+#define HELM27_EINVAL    -1   /* bad argument (null pointer, bad size, bad flag) */
+#define HELM27_ENOMEM    -2   /* device or host allocation failed */
+#define HELM27_EADMIT    -3   /* request larger than the context's HBM budget */
+#define HELM27_ENOCONV   -4   /* iteration limit reached before the tolerance */
+#define HELM27_ENUMERIC  -5   /* NaN / Inf in the data or a Krylov breakdown */
+#define HELM27_EDEVICE   -6   /* a HIP call failed */
+#define HELM27_ERANGE    -7   /* a source outside the grid or inside the PML */
+#define HELM27_ENOTFOUND -8   /* unknown serving ticket */
+#define HELM27_EAGAIN    -9   /* serving result not ready yet */
+
+/* ---- dtypes, variants, flags -------------------------------------------- */
+#define HELM27_C64   1        /* complex float  (2 x fp32) */
+#define HELM27_C128  2        /* complex double (2 x fp64) */
+
+#define HELM27_RECOMPUTE 0    /* apply: coefficients rebuilt from table index + velocity */
+#define HELM27_STORED    1    /* apply: 27 stored complex coefficients per point */
+
+/* assembly flags (helm27_assemble) */
+#define HELM27_WEIGHTS_GA     0x0   /* per-row table entry of the row's own G (Sec. 3.1 "GA") */
+#define HELM27_WEIGHTS_FIXED  0x1   /* table entry 0 on every row ("G4" / "Gm", Sec. 3.1) */
+#define HELM27_WEIGHTS_GAM    0x2   /* mean of the 27 stencil points' entries (Sec. 3.1 "GAm") */
+#define HELM27_STORE_C64      0x10  /* also keep 27 stored complex-float coefficients per point */
+#define HELM27_STORE_C128     0x20  /* also keep 27 stored complex-double coefficients per point */
+
+/* ---- opaque handles ----------------------------------------------------- */
+typedef struct helm27_ctx   helm27_ctx;
+typedef struct helm27_table helm27_table;
+typedef struct helm27_op    helm27_op;
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` bounds the
+ * device memory that serving admits at once (0 = 90% of the free memory).
+ * Errors: EINVAL (bad device), EDEVICE. */
+int  helm27_create(helm27_ctx** out, int device, size_t hbm_budget_bytes);
+void helm27_destroy(helm27_ctx* ctx);
+const char* helm27_strerror(int status);
+
+/* ---- (a0) weight table ---------------------------------------------------
+ * Options of the dispersion fit (Sec. 2.2).  NULL selects the defaults:
+ * theta and phi both on 0, 10, 20, 30, 40 degrees; first-difference smoother. */
+typedef struct {
+    int    n_angles;        /* angles per axis (default 5) */
+    double angle_step_deg;  /* spacing (default 10) */
+    int    diff_order;      /* 1 = first difference (default), 2 = second */
+} helm27_table_opts;
+
+/* Build the adaptive table on the host in FP64 (Sec. 2.2): for
+ * G_i = g_min + i dg (i = 0 .. round((g_max - g_min)/dg)), solve
+ *     min ||H w - g||^2 + lambda ||D P w||^2
+ * over the five free weights of every G_i by banded Givens QR of the stacked
+ * matrix [H; sqrt(lambda) D P] (unknowns in G-major order, so the stacked
+ * matrix has bandwidth 10).  The rows of H are the v~ = 1 equations of the
+ * dispersion analysis with w_s3 and the last mass weight eliminated (H_2
+ * including its constant 1/2, as the elimination gives).
+ * lambda = 0 decouples the G values; each is then solved for its minimum-norm
+ * least-squares weights (one-sided Jacobi SVD), since alone it is rank deficient.
+ * Errors: EINVAL (g_min <= 0, dg <= 0, g_max < g_min, lambda < 0, more than
+ * 65535 entries), ENUMERIC, ENOMEM. */
+int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, double dg, double lambda,
+                       const helm27_table_opts* opts, helm27_table** out);
+
+/* A table from caller-given weights: `w5` is host memory [n_g][5] holding
+ * (w_s1, w_s2, w_m0, w_m1, w_m2) per entry, the rest following from
+ * sum w_s = 1 and w_m0 + 6 w_m1 + 12 w_m2 + 8 w_m3 = 1.  n_g = 1 gives fixed
+ * weights.  The data are copied.  Errors: EINVAL. */
+int helm27_table_from_weights(helm27_ctx* ctx, double g_min, double dg, int n_g,
+                              const double* w5, helm27_table** out);
+
+/* Non-adaptive weights (Sec. 2.2, joint misfit over several G with one weight
+ * vector, e.g. G = 4 for "G4" and G = 4, 6, 8, 10 for "Gm"): the minimum-norm
+ * least-squares solution (the system is rank deficient), computed by one-sided
+ * Jacobi SVD in FP64 on the host.  Returns a one-entry table to be assembled
+ * with HELM27_WEIGHTS_FIXED.  g_list: host [n_list].  Errors: EINVAL,
+ * ENUMERIC, ENOMEM. */
+int helm27_fit_fixed(helm27_ctx* ctx, const double* g_list, int n_list, const helm27_table_opts* opts,
+                     helm27_table** out);
+
+/* Copy the table out: w7 (host, caller-owned, [n_g][7] or NULL) receives
+ * (w_s1, w_s2, w_s3, w_m0, w_m1, w_m2, w_m3) per entry (per-point mass
+ * weights); n_g, g_min, dg may be NULL.  Errors: EINVAL. */
+int helm27_table_weights(const helm27_table* t, double* w7, int* n_g, double* g_min, double* dg);
+void helm27_table_destroy(helm27_table* t);
+
+/* ---- (a1) assembly ------------------------------------------------------- */
+typedef struct {
+    int    npml[3];   /* PML layer width in nodes along x, y, z (both faces); 0 = none */
+    double R;         /* theoretical reflection coefficient (default 1e-3 if <= 0) */
+    double c_ref;     /* velocity used for the damping strength; <= 0: max of the model */
+} helm27_pml;
+
+typedef struct {
+    int      nx, ny, nz;
+    double   h, freq, omega;
+    int      n_g;
+    int64_t  n_clamped;     /* points whose G fell outside the table (clamped) */
+    double   g_min_model;   /* smallest / largest G = c/(f h) of the model */
+    double   g_max_model;
+    size_t   device_bytes;  /* device memory held by the operator */
+} helm27_op_desc;
+
+/* Build the operator for velocity `vel` (float32 [nz][ny][nx], host or device
+ * pointer, copied), grid step h (m), frequency freq (Hz), PML `pml` (NULL: 8
+ * nodes, R = 1e-3) and `flags` (HELM27_WEIGHTS_*, HELM27_STORE_*).
+ * Per point it stores the table index
+ *     idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, N_G - 1)
+ * (binary64, no contraction; bit-identical to the same formula on any IEEE
+ * machine) and keeps the velocity; the coefficients are rebuilt from them by
+ * the recompute kernels.  Errors: EINVAL (dims < 3, h or freq <= 0, npml too
+ * large for the grid, non-positive velocity), ENOMEM, EDEVICE. */
+int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const float* vel,
+                    int nx, int ny, int nz, double h, double freq,
+                    const helm27_pml* pml, int flags, helm27_op** out);
+int helm27_op_info(const helm27_op* op, helm27_op_desc* out);
+void helm27_op_destroy(helm27_op* op);
+
+/* Test hooks.  helm27_export_index copies the table index of every point to
+ * host memory `idx` [N] (uint16).  helm27_export_csr writes the matrix in
+ * CSR form to host memory: indptr [N+1], indices [nnz] (ascending columns,
+ * nnz = prod(3 n_a - 2)), vals [2 nnz] interleaved complex128; the values
+ * are evaluated on the device in FP64.  Pass NULL for indptr to get only
+ * the nnz in *nnz_out.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int helm27_export_index(const helm27_op* op, uint16_t* idx);
+int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t* indptr,
+                      int64_t* indices, double* vals);
+
+/* ---- (b) apply ------------------------------------------------------------
+ * y = A u for nrhs right-hand sides (Sec. 2.1, [M + S] p); u and y are device
+ * pointers to [nrhs][N] complex values of `dtype` (HELM27_C64: FP32 with FP32
+ * accumulation; HELM27_C128: FP64), u and y must not overlap.  `variant`
+ * selects HELM27_RECOMPUTE or HELM27_STORED (needs the matching STORE flag at
+ * assembly).  Enqueued on `stream` (hipStream_t; NULL = null stream);
+ * returns without synchronising.  Errors: EINVAL, EDEVICE. */
+int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int variant,
+                 void* stream);
+
+/* ---- (c) solve ------------------------------------------------------------ */
+typedef struct {
+    double tol;          /* relative residual ||b - A u|| / ||b|| per RHS (default 1e-6) */
+    int    restart;      /* GMRES(m) restart length (default 20) */
+    int    max_inner;    /* Arnoldi steps per refinement step (default 400) */
+    int    max_outer;    /* FP64 refinement steps (default 20) */
+    double inner_tol;    /* relative reduction asked of each inner solve (default 1e-3) */
+    int    precision;    /* HELM27_C64: FP32 inner + FP64 refinement (default);
+                            HELM27_C128: everything in FP64 */
+    int    mg_levels;    /* multigrid levels (default 4; 0 = no preconditioner) */
+    double mg_shift;     /* complex shift beta of the preconditioner (default 0.5) */
+    int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
+    double mg_omega;     /* Jacobi damping (default 0.8) */
+    int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 20) */
+    int    use_graph;    /* capture each restart cycle in a hipGraph (default 1) */
+    int    verbose;
+} helm27_solve_opts;
+
+typedef struct {
+    int    outer_iters;
+    int    inner_iters;      /* total Arnoldi steps (all refinement steps) */
+    int    converged;        /* 1 if every RHS reached tol */
+    double max_relres;       /* max over RHS of the FP64 relative residual */
+    double seconds;          /* wall time of the call */
+} helm27_solve_stats;
+
+/* Fill `opts` with the defaults above. */
+void helm27_solve_opts_default(helm27_solve_opts* opts);
+
+/* Solve A u = b for point sources (Sec. 3.1: s = delta(x - x_s), i.e.
+ * amp / h^3 at the source node).  `src` is host memory [nrhs][5] doubles
+ * (i, j, k, amp_re, amp_im); every source must lie inside the grid and outside
+ * the PML (else ERANGE).  `u` is a device pointer to [nrhs][N] complex128 that
+ * receives the solution (its input value is ignored).  On ENOCONV u holds the
+ * best iterate and stats says how far it got.  Synchronises `stream` before
+ * returning.  Errors: EINVAL, ERANGE, ENOCONV, ENUMERIC, ENOMEM, EDEVICE. */
+int helm27_solve(helm27_op* op, const double* src, void* u, int nrhs,
+                 const helm27_solve_opts* opts, helm27_solve_stats* stats, void* stream);
+
+/* Same with a general right-hand side: `b` device pointer [nrhs][N]
+ * complex128 (the Xi-scaled system's right-hand side). */
+int helm27_solve_rhs(helm27_op* op, const void* b, void* u, int nrhs,
+                     const helm27_solve_opts* opts, helm27_solve_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM27_H */

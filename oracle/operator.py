@@ -235,3 +235,51 @@ def assemble_csr(c, f, h, npml, w_rows, **kw):
 
 def csr_matrix(indptr, indices, data, shape):
     return sp.csr_matrix((data, indices, indptr), shape=shape)
+
+
+def _row_vec(M, r):
+    """Row r of a sparse matrix as a 1 x n CSR matrix."""
+    return sp.csr_matrix(M.getrow(r))
+
+
+def assemble_rows(c, f, h, npml, w_rows, rows, omega=None, c_ref=None, R=1e-3, shift=0.0):
+    """Selected rows of the same A as ``assemble`` (second mass form), for
+    grids too large to assemble whole: row (i, j, k) of a Kronecker product
+    kron(Z, kron(Y, X)) is kron(Z[k], kron(Y[j], X[i])), so each row is the
+    weighted sum of the Kronecker products of the 1D factors' rows.
+    ``w_rows`` are the weights of the selected rows, (len(rows), 7).
+    Returns a len(rows) x N CSR matrix."""
+    c = np.asarray(c, dtype=np.float32)
+    nz, ny, nx = c.shape
+    if omega is None:
+        omega = 2.0 * math.pi * f
+    if c_ref is None:
+        c_ref = float(c.astype(np.float64).max())
+    if np.isscalar(npml):
+        npml = (int(npml),) * 3
+    fac = []
+    for n, p in zip((nx, ny, nz), npml):
+        xn, xh = pml_profile(n, p, h, omega, c_ref, R)
+        fac.append(_1d_factors(xn, xh, h))
+    (Tx, Ux, Xx), (Ty, Uy, Xy), (Tz, Uz, Xz) = fac
+    out = []
+    cflat = c.reshape(-1).astype(np.float64)
+    for r, w in zip(rows, np.asarray(w_rows, np.float64)):
+        i, j, k = r % nx, (r // nx) % ny, r // (nx * ny)
+        tx, ux, xx = _row_vec(Tx, i), _row_vec(Ux, i), _row_vec(Xx, i)
+        ty, uy, xy = _row_vec(Ty, j), _row_vec(Uy, j), _row_vec(Xy, j)
+        tz, uz, xz = _row_vec(Tz, k), _row_vec(Uz, k), _row_vec(Xz, k)
+        s1 = _k3(xz, xy, tx) + _k3(xz, ty, xx) + _k3(tz, xy, xx)
+        p2 = _k3(xz, ty, tx) + _k3(tz, xy, tx) + _k3(tz, ty, xx)
+        p3 = _k3(tz, ty, tx)
+        s2 = s1 + (h * h / 6.0) * p2
+        s3 = s1 + (h * h / 2.0) * p2 + (3.0 * h ** 4 / 8.0) * p3
+        m0 = _k3(xz, xy, xx)
+        m1 = 2.0 * (_k3(xz, xy, ux) + _k3(xz, uy, xx) + _k3(uz, xy, xx))
+        m2 = 4.0 * (_k3(xz, uy, ux) + _k3(uz, xy, ux) + _k3(uz, uy, xx))
+        m3 = 8.0 * _k3(uz, uy, ux)
+        k2 = (omega / cflat[r]) ** 2 * (1.0 + 1j * shift)
+        row = (w[0] * s1 + w[1] * s2 + w[2] * s3
+               + k2 * (w[3] * m0 + w[4] * m1 + w[5] * m2 + w[6] * m3))
+        out.append(row)
+    return sp.vstack(out).tocsr()

@@ -169,6 +169,9 @@ def build_table(gmin=3.0, gmax=20.0, dg=0.05, lam=1e-3, theta=None, phi=None,
     if theta is None:
         theta, phi = angle_grid()
     Gs = g_grid(gmin, gmax, dg)
+    if lam == 0:
+        # no coupling: every G is its own (rank-deficient) fit
+        return Gs, np.stack([fit_fixed([G], theta, phi) for G in Gs])
     H, g = _stack_H(Gs, theta, phi)
     L = _smoothing_operator(len(Gs), diff)
     K = sp.vstack([H, np.sqrt(lam) * L]).toarray()
@@ -193,8 +196,9 @@ def table_normal_residual(Gs, W, lam, theta=None, phi=None, diff="first"):
 def fit_fixed(G_list, theta=None, phi=None):
     """Non-adaptive weights (Sec. 2.2, joint misfit over several G with one
     weight vector): N_G = 1 with G = 4 gives "G4", G = 4, 6, 8, 10 gives "Gm".
-    Minimum-norm least-squares solution (the N_G = 1 problem is rank 4).
-    Returns the five free weights."""
+    Minimum-norm least-squares solution (the N_G = 1 problem is rank 4): the
+    pseudo-inverse with singular values below 1e-10 of the largest taken as
+    zero.  Returns the five free weights."""
     if theta is None:
         theta, phi = angle_grid()
     Hs, gs = [], []
@@ -204,7 +208,7 @@ def fit_fixed(G_list, theta=None, phi=None):
         gs.append(g)
     H = np.vstack(Hs)
     g = np.concatenate(gs)
-    w, *_ = scipy.linalg.lstsq(H, g, lapack_driver="gelsd")
+    w, *_ = scipy.linalg.lstsq(H, g, cond=1e-10, lapack_driver="gelsd")
     return w
 
 

@@ -1,0 +1,236 @@
+"""Thin Python binding over the helm27 C ABI (marshalling only).
+
+Every step of the path runs in libhelm27 (host C++ and HIP kernels); PyTorch
+only provides device memory and the stream handle.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Iterable, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+_WEIGHTS = {"GA": L.WEIGHTS_GA, "fixed": L.WEIGHTS_FIXED, "GAm": L.WEIGHTS_GAM}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    if stream is None:
+        torch = _torch()
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Table:
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def weights(self):
+        """(w7 [n_g, 7], g_min, dg)."""
+        n = C.c_int()
+        g0 = C.c_double()
+        dg = C.c_double()
+        L.check(L.lib.helm27_table_weights(self._h, None, C.byref(n), C.byref(g0), C.byref(dg)), "table_weights")
+        w = np.zeros((n.value, 7), np.float64)
+        L.check(L.lib.helm27_table_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_double)), None, None, None))
+        return w, g0.value, dg.value
+
+    def close(self):
+        if self._h:
+            L.lib.helm27_table_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    def __init__(self, handle, ctx):
+        self._h = handle
+        self._ctx = ctx     # keep the context alive
+        d = L.OpDesc()
+        L.check(L.lib.helm27_op_info(handle, C.byref(d)), "op_info")
+        self.nx, self.ny, self.nz = d.nx, d.ny, d.nz
+        self.N = d.nx * d.ny * d.nz
+        self.h, self.freq = d.h, d.freq
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        d = L.OpDesc()
+        L.check(L.lib.helm27_op_info(self._h, C.byref(d)), "op_info")
+        return {f: getattr(d, f) for f, _ in L.OpDesc._fields_}
+
+    def index(self):
+        out = np.zeros(self.N, np.uint16)
+        L.check(L.lib.helm27_export_index(self._h, out.ctypes.data_as(C.c_void_p)), "export_index")
+        return out
+
+    def csr(self):
+        nnz = C.c_int64()
+        L.check(L.lib.helm27_export_csr(self._h, C.byref(nnz), None, None, None), "export_csr")
+        indptr = np.zeros(self.N + 1, np.int64)
+        indices = np.zeros(nnz.value, np.int64)
+        vals = np.zeros(nnz.value, np.complex128)
+        L.check(L.lib.helm27_export_csr(self._h, C.byref(nnz), indptr.ctypes.data_as(C.c_void_p),
+                                        indices.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p)),
+                "export_csr")
+        return indptr, indices, vals
+
+    def apply(self, u, y=None, variant="recompute", stream=None):
+        """y = A u for a device tensor u of shape [nrhs, N] (or [N]), complex64 or
+        complex128."""
+        torch = _torch()
+        if u.dim() == 1:
+            u = u.view(1, -1)
+        assert u.is_cuda and u.is_contiguous() and u.shape[1] == self.N
+        if u.dtype == torch.complex64:
+            dt = L.C64
+        elif u.dtype == torch.complex128:
+            dt = L.C128
+        else:
+            raise TypeError(u.dtype)
+        if y is None:
+            y = torch.empty_like(u)
+        var = L.RECOMPUTE if variant == "recompute" else L.STORED
+        L.check(L.lib.helm27_apply(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(y.data_ptr()), u.shape[0], dt,
+                                   var, _stream_handle(stream)), "apply")
+        return y
+
+    def solve(self, sources: Sequence[Sequence[int]], amps=None, out=None, stream=None, **opts):
+        """Solve for point sources (i, j, k); returns (u [nrhs, N] complex128
+        device tensor, stats dict)."""
+        torch = _torch()
+        n = len(sources)
+        src = np.zeros((n, 5), np.float64)
+        for s, p in enumerate(sources):
+            src[s, :3] = p
+            a = 1.0 if amps is None else amps[s]
+            src[s, 3] = np.real(a)
+            src[s, 4] = np.imag(a)
+        if out is None:
+            out = torch.empty((n, self.N), dtype=torch.complex128, device="cuda")
+        o = solve_opts(**opts)
+        st = L.SolveStats()
+        status = L.lib.helm27_solve(self._h, src.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(out.data_ptr()),
+                                    n, C.byref(o), C.byref(st), _stream_handle(stream))
+        stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_}
+        stats["status"] = status
+        if status not in (L.OK, L.ENOCONV):
+            L.check(status, "solve")
+        return out, stats
+
+    def solve_rhs(self, b, out=None, stream=None, **opts):
+        torch = _torch()
+        if b.dim() == 1:
+            b = b.view(1, -1)
+        assert b.is_cuda and b.dtype == torch.complex128 and b.is_contiguous()
+        if out is None:
+            out = torch.empty_like(b)
+        o = solve_opts(**opts)
+        st = L.SolveStats()
+        status = L.lib.helm27_solve_rhs(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(out.data_ptr()), b.shape[0],
+                                        C.byref(o), C.byref(st), _stream_handle(stream))
+        stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_}
+        stats["status"] = status
+        if status not in (L.OK, L.ENOCONV):
+            L.check(status, "solve_rhs")
+        return out, stats
+
+    def close(self):
+        if self._h:
+            L.lib.helm27_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_opts(**kw):
+    o = L.SolveOpts()
+    L.lib.helm27_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision":
+            v = {"mixed": L.C64, "fp64": L.C128, L.C64: L.C64, L.C128: L.C128}[v]
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = C.c_void_p()
+        L.check(L.lib.helm27_create(C.byref(h), device, hbm_budget), "create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build_table(self, g_min=3.0, g_max=20.0, dg=0.05, lam=1e-3, n_angles=5, angle_step_deg=10.0,
+                    diff_order=1) -> Table:
+        opts = L.TableOpts(n_angles, angle_step_deg, diff_order)
+        h = C.c_void_p()
+        L.check(L.lib.helm27_build_table(self._h, g_min, g_max, dg, lam, C.byref(opts), C.byref(h)), "build_table")
+        return Table(h)
+
+    def table_from_weights(self, g_min, dg, w5) -> Table:
+        w5 = np.ascontiguousarray(np.asarray(w5, np.float64).reshape(-1, 5))
+        h = C.c_void_p()
+        L.check(L.lib.helm27_table_from_weights(self._h, g_min, dg, w5.shape[0],
+                                                w5.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)),
+                "table_from_weights")
+        return Table(h)
+
+    def assemble(self, table: Table, vel, h: float, freq: float, npml=8, R=1e-3, c_ref=0.0,
+                 weights="GA", store: Iterable[str] = ()) -> Operator:
+        """vel: numpy float32 [nz, ny, nx] or a device tensor of that shape."""
+        if hasattr(vel, "data_ptr"):
+            nz, ny, nx = vel.shape
+            ptr = C.c_void_p(vel.data_ptr())
+            keep = vel
+        else:
+            keep = np.ascontiguousarray(vel, dtype=np.float32)
+            nz, ny, nx = keep.shape
+            ptr = keep.ctypes.data_as(C.c_void_p)
+        if np.isscalar(npml):
+            npml = (int(npml),) * 3
+        p = L.Pml((C.c_int * 3)(*npml), R, c_ref)
+        flags = _WEIGHTS[weights]
+        for s in store:
+            flags |= {"c64": L.STORE_C64, "c128": L.STORE_C128}[s]
+        hnd = C.c_void_p()
+        L.check(L.lib.helm27_assemble(self._h, table.handle, ptr, nx, ny, nz, h, freq, C.byref(p), flags,
+                                      C.byref(hnd)), "assemble")
+        del keep
+        return Operator(hnd, self)
+
+    def close(self):
+        if self._h:
+            L.lib.helm27_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

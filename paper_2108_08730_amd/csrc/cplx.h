@@ -1,0 +1,50 @@
+// Small complex helpers for the device code (interleaved re/im pairs).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace h27 {
+
+template <typename R> struct V2;
+template <> struct V2<float>  { using T = float2; };
+template <> struct V2<double> { using T = double2; };
+
+template <typename R>
+struct Cx {
+    R re, im;
+};
+
+template <typename R> __device__ __forceinline__ Cx<R> mk(R re, R im) { return Cx<R>{re, im}; }
+template <typename R> __device__ __forceinline__ Cx<R> zero() { return Cx<R>{R(0), R(0)}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator-(Cx<R> a) { return {-a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ Cx<R> operator*(Cx<R> a, Cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+// acc += a * b (complex)
+template <typename R> __device__ __forceinline__ void cmac(Cx<R>& acc, Cx<R> a, Cx<R> b) {
+    acc.re += a.re * b.re - a.im * b.im;
+    acc.im += a.re * b.im + a.im * b.re;
+}
+// acc += s * b (real s)
+template <typename R> __device__ __forceinline__ void rmac(Cx<R>& acc, R s, Cx<R> b) {
+    acc.re += s * b.re;
+    acc.im += s * b.im;
+}
+template <typename R> __device__ __forceinline__ Cx<R> cinv(Cx<R> a) {
+    R d = R(1) / (a.re * a.re + a.im * a.im);
+    return {a.re * d, -a.im * d};
+}
+template <typename R> __device__ __forceinline__ Cx<R> ld(const typename V2<R>::T* p) {
+    typename V2<R>::T v = *p;
+    return {v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void st(typename V2<R>::T* p, Cx<R> a) {
+    typename V2<R>::T v;
+    v.x = a.re;
+    v.y = a.im;
+    *p = v;
+}
+
+}  // namespace h27

@@ -1,0 +1,156 @@
+// Internal declarations shared by the host sources of libhelm27.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "helm27.h"
+
+#define H27_CHECK_HIP(expr)                                                        \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            std::fprintf(stderr, "helm27: %s failed: %s (%s:%d)\n", #expr,         \
+                         hipGetErrorString(e_), __FILE__, __LINE__);               \
+            return HELM27_EDEVICE;                                                 \
+        }                                                                          \
+    } while (0)
+
+namespace h27 {
+
+// Per-table-entry coefficients used by the kernels (all dimensionless).
+// s0..s3: interior stiffness class values (centre, face, edge, corner) times h^2;
+// beta2, beta3: weights of the pairwise / triple products of 1D second
+// differences in the tensor form of the stiffness;
+// m0..m3: per-point mass weights (centre, face, edge, corner).
+template <typename R>
+struct EntryCoef {
+    R s0, s1, s2, s3;
+    R beta2, beta3;
+    R m0, m1, m2, m3;
+    R pad0, pad1;   // 12 values: 48 B (fp32) / 96 B (fp64), aligned loads
+};
+
+// Per-node PML data along one axis (complex values as re/im pairs):
+// xi = stretch at the node, tm/tp = 1/xi at the half nodes i-1/2, i+1/2,
+// um/up = xi at those half nodes / 2.  plain = 1 when all five are the
+// unstretched values (xi = 1 at the node and both half nodes).
+template <typename R>
+struct AxisNode {
+    R xi_re, xi_im;
+    R tm_re, tm_im, tp_re, tp_im;
+    R um_re, um_im, up_re, up_im;
+    int plain;
+    int pad;
+};
+
+struct Rect { int x0, y0, w, h; };
+
+// Column tiling of one grid for the stencil kernels: the plain box (x and y
+// both unstretched) in wide tiles, the frame around it in square tiles.
+struct Tiling {
+    int plain_x0 = 0, plain_y0 = 0, plain_w = 0, plain_h = 0;
+    int n_plain_tiles_x = 0, n_plain_tiles_y = 0;
+    Rect frame[4];
+    int frame_tiles_x[4], frame_tiles_y[4];
+    int n_plain_blocks = 0;     // per z chunk
+    int n_frame_blocks = 0;     // per z chunk
+    int zchunk = 8, n_zchunks = 1;
+};
+
+struct Level;  // multigrid level (solver.cpp)
+
+}  // namespace h27
+
+struct helm27_ctx {
+    int device = 0;
+    size_t hbm_budget = 0;
+    std::mutex mu;
+    void* serve = nullptr;   // serving state (serve.cpp)
+};
+
+struct helm27_table {
+    double g_min = 0, dg = 0;
+    int n_g = 0;
+    std::vector<double> w7;   // [n_g][7]
+};
+
+namespace h27 {
+
+// Everything the stencil kernels need about one grid (the fine operator or a
+// multigrid level).  Device pointers are owned by the object that made it.
+struct GridOp {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t N = 0;
+    double h = 0, omega = 0;
+    int npml[3] = {0, 0, 0};
+    double R = 1e-3, c_ref = 0;
+    float* d_c = nullptr;                      // velocity [N]
+    uint16_t* d_idx = nullptr;                 // table index [N]
+    int n_g = 0;
+    int fixed = 0;                             // entry 0 on every row
+    EntryCoef<float>* d_entry_f = nullptr;     // [n_g]
+    EntryCoef<double>* d_entry_d = nullptr;
+    EntryCoef<float>* d_row_f = nullptr;       // GAm: per-row averaged entries [N]
+    EntryCoef<double>* d_row_d = nullptr;
+    AxisNode<float>* d_ax_f[3] = {nullptr, nullptr, nullptr};
+    AxisNode<double>* d_ax_d[3] = {nullptr, nullptr, nullptr};
+    Tiling tiling;
+    size_t bytes = 0;
+};
+
+// Free every device buffer of a GridOp.
+void grid_free(GridOp* g);
+
+}  // namespace h27
+
+struct helm27_op {
+    helm27_ctx* ctx = nullptr;
+    h27::GridOp g;
+    double freq = 0;
+    int flags = 0;
+    int64_t n_clamped = 0;
+    double g_min_model = 0, g_max_model = 0;
+    void* d_coef_f = nullptr;        // stored: float2[27][N]
+    void* d_coef_d = nullptr;        // stored: double2[27][N]
+    std::vector<double> w7;          // table weights [n_g][7] (host copy)
+    double table_gmin = 0, table_dg = 0;
+    void* solver = nullptr;          // solver workspace (solver.cpp)
+};
+
+namespace h27 {
+
+// table.cpp
+void dispersion_rows(double G, double theta, double phi, double H[5], double* g);
+void complete_weights(const double w5[5], double w7[7]);
+
+// op.cpp
+int op_build(helm27_ctx* ctx, const double* w7, int n_g, double g_min, double dg,
+             const float* vel, int nx, int ny, int nz, double h, double freq, double omega_shift,
+             const helm27_pml* pml, int flags, helm27_op** out);
+void make_tiling(int nx, int ny, const int plain_lo[2], const int plain_hi[2], Tiling* t, int zchunk, int nz);
+void axis_nodes(int n, int npml, double h, double omega, double c_ref, double R,
+                std::vector<AxisNode<double>>* out);
+
+// kernels (kernels_*.hip): host-side launchers
+int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
+                        int n_g, unsigned long long* d_nclamp, hipStream_t s);
+// y = A u (MODE_APPLY), y = b - A u (MODE_RESID) or y = u + omega_j D^-1 (b - A u)
+// (MODE_JACOBI) with A's mass scaled by (1 + i shift).  R = float | double.
+template <typename R>
+int launch_stencil(const GridOp& g, int mode, double shift, const void* u, void* y, const void* b,
+                   double omega_j, int nrhs, hipStream_t s);
+template <typename R>
+int launch_fill_stored(const GridOp& g, void* coef, double shift, hipStream_t s);
+template <typename R>
+int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* y, int nrhs,
+                        hipStream_t s);
+template <typename R>
+int launch_gam_average(const GridOp& g, EntryCoef<R>* rowcoef, hipStream_t s);
+
+}  // namespace h27

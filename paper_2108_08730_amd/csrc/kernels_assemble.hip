@@ -1,0 +1,271 @@
+// Assembly kernels: per-point table index, stored 27-coefficient operator,
+// "GAm" neighbourhood-averaged weights, and the stored-coefficient apply.
+//
+// This file is compiled with -ffp-contract=off: the table index must be the
+// same binary64 result as the same formula evaluated anywhere else.
+#include "stencil.h"
+
+namespace h27 {
+
+// idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, n_g - 1)   (paper Sec. 3.1:
+// every row picks the table entry of its local G = c/(f h); nearest entry,
+// ties upwards).  Counts clamped points and invalid velocities.
+__global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __restrict__ idx, int64_t N,
+                                    double fh, double gmin, double dg, int n_g,
+                                    unsigned long long* __restrict__ counts) {
+    __shared__ unsigned long long red[2][kBlock / 64];
+    unsigned long long ncl = 0, nbad = 0;
+    const double top = static_cast<double>(n_g - 1);
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const float cv = c[i];
+        if (!(cv > 0.0f) || !isfinite(cv)) ++nbad;
+        const double G = static_cast<double>(cv) / fh;
+        const double t = (G - gmin) / dg;
+        const double raw = floor(t + 0.5);
+        int k;
+        if (!(raw >= 0.0)) {
+            k = 0;
+            ++ncl;
+        } else if (raw > top) {
+            k = n_g - 1;
+            ++ncl;
+        } else {
+            k = static_cast<int>(raw);
+        }
+        idx[i] = static_cast<uint16_t>(k);
+    }
+    // wavefront reduction, then one atomic per block
+    for (int off = 32; off > 0; off >>= 1) {
+        ncl += __shfl_down(ncl, off, 64);
+        nbad += __shfl_down(nbad, off, 64);
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        red[0][w] = ncl;
+        red[1][w] = nbad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        if (a) atomicAdd(counts, a);
+        if (b) atomicAdd(counts + 1, b);
+    }
+}
+
+int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
+                        int n_g, unsigned long long* d_counts, hipStream_t s) {
+    int64_t blocks = (N + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(select_index_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, c, idx, N,
+                       fh, gmin, dg, n_g, d_counts);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 27 coefficients of one row, written to coef[s * N + i] (s = (dz+1)*9 +
+// (dy+1)*3 + (dx+1)); zero where the neighbour lies outside the grid.
+template <typename R>
+__global__ void fill_stored_kernel(GridData<R> g, typename V2<R>::T* __restrict__ coef) {
+    const int64_t N = g.N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(i % g.nx);
+        const int y = static_cast<int>((i / g.nx) % g.ny);
+        const int z = static_cast<int>(i / g.plane);
+        const AxisNode<R>* nodes[3] = {g.ax + x, g.ay + y, g.az + z};
+        const int pos[3] = {x, y, z};
+        const int ext[3] = {g.nx, g.ny, g.nz};
+        Cx<R> T[3][3], X[3][3], U[3][3];
+        for (int a = 0; a < 3; ++a) {
+            const AxisNode<R> n = *nodes[a];
+            const Cx<R> tm = mk(n.tm_re, n.tm_im), tp = mk(n.tp_re, n.tp_im);
+            T[a][0] = tm;
+            T[a][1] = -(tm + tp);
+            T[a][2] = tp;
+            X[a][0] = zero<R>();
+            X[a][1] = mk(n.xi_re, n.xi_im);
+            X[a][2] = zero<R>();
+            U[a][0] = mk(n.um_re, n.um_im);
+            U[a][1] = zero<R>();
+            U[a][2] = mk(n.up_re, n.up_im);
+        }
+        EntryCoef<R> E;
+        if (g.rowcoef) E = g.rowcoef[i];
+        else E = g.entry[g.fixed ? 0 : g.idx[i]];
+        const R cv = static_cast<R>(g.c[i]);
+        const R kap = g.omega2 / (cv * cv);
+        const Cx<R> kc = mk(kap, kap * g.shift);
+        const R sig = g.inv_h2;
+        for (int dz = 0; dz < 3; ++dz)
+            for (int dy = 0; dy < 3; ++dy)
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int s = dz * 9 + dy * 3 + dx;
+                    const int d[3] = {dx, dy, dz};
+                    bool inside = true;
+                    for (int a = 0; a < 3; ++a) {
+                        const int p = pos[a] + d[a] - 1;
+                        inside = inside && p >= 0 && p < ext[a];
+                    }
+                    Cx<R> val = zero<R>();
+                    if (inside) {
+                        const Cx<R> tx = T[0][dx], ty = T[1][dy], tz = T[2][dz];
+                        const Cx<R> xx = X[0][dx], xy = X[1][dy], xz = X[2][dz];
+                        const Cx<R> ux = U[0][dx], uy = U[1][dy], uz = U[2][dz];
+                        Cx<R> stiff = tx * xy * xz + xx * ty * xz + xx * xy * tz;
+                        stiff = stiff + E.beta2 * (tx * ty * xz + tx * xy * tz + xx * ty * tz);
+                        stiff = stiff + E.beta3 * (tx * ty * tz);
+                        Cx<R> mass = E.m0 * (xx * xy * xz);
+                        mass = mass + (R(2) * E.m1) * (ux * xy * xz + xx * uy * xz + xx * xy * uz);
+                        mass = mass + (R(4) * E.m2) * (ux * uy * xz + ux * xy * uz + xx * uy * uz);
+                        mass = mass + (R(8) * E.m3) * (ux * uy * uz);
+                        val = sig * stiff + kc * mass;
+                    }
+                    st<R>(coef + static_cast<int64_t>(s) * N + i, val);
+                }
+    }
+}
+
+template <typename R>
+static GridData<R> make_grid_data(const GridOp& g, double shift);
+
+template <>
+GridData<float> make_grid_data<float>(const GridOp& g, double shift) {
+    GridData<float> d;
+    d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+    d.plane = static_cast<int64_t>(g.nx) * g.ny;
+    d.N = g.N;
+    d.c = g.d_c; d.idx = g.d_idx; d.entry = g.d_entry_f; d.rowcoef = g.d_row_f; d.fixed = g.fixed;
+    d.ax = g.d_ax_f[0]; d.ay = g.d_ax_f[1]; d.az = g.d_ax_f[2];
+    d.omega2 = static_cast<float>(g.omega * g.omega);
+    d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
+    d.shift = static_cast<float>(shift);
+    return d;
+}
+
+template <>
+GridData<double> make_grid_data<double>(const GridOp& g, double shift) {
+    GridData<double> d;
+    d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+    d.plane = static_cast<int64_t>(g.nx) * g.ny;
+    d.N = g.N;
+    d.c = g.d_c; d.idx = g.d_idx; d.entry = g.d_entry_d; d.rowcoef = g.d_row_d; d.fixed = g.fixed;
+    d.ax = g.d_ax_d[0]; d.ay = g.d_ax_d[1]; d.az = g.d_ax_d[2];
+    d.omega2 = g.omega * g.omega;
+    d.inv_h2 = 1.0 / (g.h * g.h);
+    d.shift = shift;
+    return d;
+}
+
+template <typename R>
+int launch_fill_stored(const GridOp& g, void* coef, double shift, hipStream_t s) {
+    GridData<R> d = make_grid_data<R>(g, shift);
+    int64_t blocks = (g.N + kBlock - 1) / kBlock;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(fill_stored_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
+                       static_cast<typename V2<R>::T*>(coef));
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int launch_fill_stored<float>(const GridOp&, void*, double, hipStream_t);
+template int launch_fill_stored<double>(const GridOp&, void*, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Stored-coefficient apply: y_i = sum_s coef[s][i] u[i + off_s].  The 27
+// coefficients of a row are streamed once (coalesced, structure of arrays) and
+// reused for every right-hand side; u neighbours come through the caches.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void apply_stored_kernel(GridData<R> g, const typename V2<R>::T* __restrict__ coef,
+                                                              const typename V2<R>::T* __restrict__ u,
+                                                              typename V2<R>::T* __restrict__ y, int nrhs) {
+    const int64_t N = g.N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(i % g.nx);
+        const int yy = static_cast<int>((i / g.nx) % g.ny);
+        const int z = static_cast<int>(i / g.plane);
+        Cx<R> cf[27];
+#pragma unroll
+        for (int s = 0; s < 27; ++s) cf[s] = ld<R>(coef + static_cast<int64_t>(s) * N + i);
+        const bool xm = x > 0, xp = x < g.nx - 1, ym = yy > 0, yp = yy < g.ny - 1, zm = z > 0, zp = z < g.nz - 1;
+        for (int r = 0; r < nrhs; ++r) {
+            const typename V2<R>::T* ur = u + static_cast<int64_t>(r) * N;
+            Cx<R> acc = zero<R>();
+#pragma unroll
+            for (int s = 0; s < 27; ++s) {
+                const int dz = s / 9 - 1, dy = (s / 3) % 3 - 1, dx = s % 3 - 1;
+                const bool ok = (dx < 0 ? xm : (dx > 0 ? xp : true)) && (dy < 0 ? ym : (dy > 0 ? yp : true)) &&
+                                (dz < 0 ? zm : (dz > 0 ? zp : true));
+                if (ok) cmac(acc, cf[s], ld<R>(ur + i + dx + static_cast<int64_t>(g.nx) * dy + g.plane * dz));
+            }
+            st<R>(y + static_cast<int64_t>(r) * N + i, acc);
+        }
+    }
+}
+
+template <typename R>
+int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* y, int nrhs, hipStream_t s) {
+    GridData<R> d = make_grid_data<R>(g, 0.0);
+    const int64_t blocks = (g.N + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(apply_stored_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
+                       static_cast<const typename V2<R>::T*>(coef), static_cast<const typename V2<R>::T*>(u),
+                       static_cast<typename V2<R>::T*>(y), nrhs);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int launch_apply_stored<float>(const GridOp&, const void*, const void*, void*, int, hipStream_t);
+template int launch_apply_stored<double>(const GridOp&, const void*, const void*, void*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// "GAm": every row takes the mean of the table entries of its in-grid stencil
+// points (paper Sec. 3.1).  The entry coefficients are linear in the weights,
+// so averaging them equals deriving them from the averaged weights.
+template <typename R>
+__global__ void gam_average_kernel(GridData<R> g, EntryCoef<R>* __restrict__ out) {
+    const int64_t N = g.N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(i % g.nx);
+        const int y = static_cast<int>((i / g.nx) % g.ny);
+        const int z = static_cast<int>(i / g.plane);
+        R acc[12];
+        for (int k = 0; k < 12; ++k) acc[k] = R(0);
+        int cnt = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = x + dx, yy = y + dy, zz = z + dz;
+                    if (xx < 0 || xx >= g.nx || yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) continue;
+                    const int64_t j = i + dx + static_cast<int64_t>(g.nx) * dy + g.plane * dz;
+                    const EntryCoef<R> E = g.entry[g.idx[j]];
+                    const R* e = &E.s0;
+                    for (int k = 0; k < 12; ++k) acc[k] += e[k];
+                    ++cnt;
+                }
+        EntryCoef<R> o;
+        R* op = &o.s0;
+        for (int k = 0; k < 12; ++k) op[k] = acc[k] / static_cast<R>(cnt);
+        out[i] = o;
+    }
+}
+
+template <typename R>
+int launch_gam_average(const GridOp& g, EntryCoef<R>* rowcoef, hipStream_t s) {
+    GridData<R> d = make_grid_data<R>(g, 0.0);
+    d.rowcoef = nullptr;
+    int64_t blocks = (g.N + kBlock - 1) / kBlock;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(gam_average_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d, rowcoef);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int launch_gam_average<float>(const GridOp&, EntryCoef<float>*, hipStream_t);
+template int launch_gam_average<double>(const GridOp&, EntryCoef<double>*, hipStream_t);
+
+}  // namespace h27

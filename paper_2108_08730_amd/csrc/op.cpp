@@ -1,0 +1,431 @@
+// Operator construction (weights per row, PML profiles, tiling) and the apply /
+// export entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "stencil.h"
+
+namespace h27 {
+
+// PML stretching along one axis (paper Sec. 2.1: d/dx -> (1/xi) d/dx with
+// xi = 1 + i gamma/omega).  Profile: on each face a layer of npml nodes of
+// width L = npml h with gamma(d) = gamma_max (1 - cos(pi d / (2 L))) at depth d
+// into the layer and gamma_max = c_ref ln(1/R) / (2 L (1 - 2/pi)), which makes
+// exp(-(2/c_ref) int_0^L gamma) = R.  Evaluated at nodes and half nodes.
+static double pml_gamma(double x, int n, int npml, double h, double c_ref, double R) {
+    const double L = npml * h;
+    const double lo = npml * h, hi = (n - 1 - npml) * h;
+    double d = 0.0;
+    if (x < lo) d = lo - x;
+    if (x > hi) d = x - hi;
+    if (d <= 0.0) return 0.0;
+    const double pi = 3.14159265358979323846;
+    const double gmax = c_ref * std::log(1.0 / R) / (2.0 * L * (1.0 - 2.0 / pi));
+    return gmax * (1.0 - std::cos(pi * d / (2.0 * L)));
+}
+
+void axis_nodes(int n, int npml, double h, double omega, double c_ref, double R,
+                std::vector<AxisNode<double>>* out) {
+    out->assign(n, AxisNode<double>{});
+    for (int i = 0; i < n; ++i) {
+        double gn = 0, gm = 0, gp = 0;
+        if (npml > 0) {
+            gn = pml_gamma(i * h, n, npml, h, c_ref, R);
+            gm = pml_gamma((i - 0.5) * h, n, npml, h, c_ref, R);
+            gp = pml_gamma((i + 0.5) * h, n, npml, h, c_ref, R);
+        }
+        AxisNode<double>& a = (*out)[i];
+        a.xi_re = 1.0;
+        a.xi_im = gn / omega;
+        // 1 / (1 + i s) = (1 - i s) / (1 + s^2)
+        const double sm = gm / omega, sp = gp / omega;
+        a.tm_re = 1.0 / (1.0 + sm * sm);
+        a.tm_im = -sm / (1.0 + sm * sm);
+        a.tp_re = 1.0 / (1.0 + sp * sp);
+        a.tp_im = -sp / (1.0 + sp * sp);
+        a.um_re = 0.5;
+        a.um_im = 0.5 * sm;
+        a.up_re = 0.5;
+        a.up_im = 0.5 * sp;
+        a.plain = (gn == 0.0 && gm == 0.0 && gp == 0.0) ? 1 : 0;
+        a.pad = 0;
+    }
+}
+
+static void plain_range(const std::vector<AxisNode<double>>& a, int* lo, int* hi) {
+    const int n = static_cast<int>(a.size());
+    int l = 0;
+    while (l < n && !a[l].plain) ++l;
+    int h = l;
+    while (h < n && a[h].plain) ++h;
+    *lo = l;
+    *hi = h;
+}
+
+void make_tiling(int nx, int ny, const int plo[2], const int phi[2], Tiling* t, int zchunk, int nz) {
+    // plain tile height in rows: kPlainTY (4) threads x 2 rows
+    const int TW = kPlainTX, TH = kPlainTY * kRows, F = kFrameT;
+    Tiling T;
+    int px0 = plo[0], px1 = phi[0], py0 = plo[1], py1 = phi[1];
+    if (px1 <= px0 || py1 <= py0) {
+        px0 = px1 = py0 = py1 = 0;
+    }
+    T.plain_x0 = px0;
+    T.plain_y0 = py0;
+    T.plain_w = px1 - px0;
+    T.plain_h = py1 - py0;
+    T.n_plain_tiles_x = T.plain_w > 0 ? (T.plain_w + TW - 1) / TW : 0;
+    T.n_plain_tiles_y = T.plain_h > 0 ? (T.plain_h + TH - 1) / TH : 0;
+    T.n_plain_blocks = T.n_plain_tiles_x * T.n_plain_tiles_y;
+    Rect r[4];
+    if (T.plain_w == 0) {
+        r[0] = {0, 0, nx, ny};
+        r[1] = r[2] = r[3] = {0, 0, 0, 0};
+    } else {
+        r[0] = {0, 0, nx, py0};                 // bottom strip (y < py0)
+        r[1] = {0, py1, nx, ny - py1};          // top strip
+        r[2] = {0, py0, px0, py1 - py0};        // left strip
+        r[3] = {px1, py0, nx - px1, py1 - py0}; // right strip
+    }
+    T.n_frame_blocks = 0;
+    for (int k = 0; k < 4; ++k) {
+        T.frame[k] = r[k];
+        const bool empty = r[k].w <= 0 || r[k].h <= 0;
+        T.frame_tiles_x[k] = empty ? 0 : (r[k].w + F - 1) / F;
+        T.frame_tiles_y[k] = empty ? 0 : (r[k].h + F - 1) / F;
+        T.n_frame_blocks += T.frame_tiles_x[k] * T.frame_tiles_y[k];
+    }
+    if (zchunk <= 0) {
+        // enough blocks to fill 256 CUs a few times over, but long z marches
+        const int64_t cols = T.n_plain_blocks + T.n_frame_blocks;
+        int zc = static_cast<int>((cols * nz) / 2048);
+        zc = std::max(2, std::min(16, zc));
+        zchunk = zc;
+    }
+    T.zchunk = std::min(zchunk, nz);
+    T.n_zchunks = (nz + T.zchunk - 1) / T.zchunk;
+    *t = T;
+}
+
+void grid_free(GridOp* g) {
+    hipFree(g->d_c);
+    hipFree(g->d_idx);
+    hipFree(g->d_entry_f);
+    hipFree(g->d_entry_d);
+    hipFree(g->d_row_f);
+    hipFree(g->d_row_d);
+    for (int a = 0; a < 3; ++a) {
+        hipFree(g->d_ax_f[a]);
+        hipFree(g->d_ax_d[a]);
+    }
+    *g = GridOp{};
+}
+
+template <typename R>
+static EntryCoef<R> entry_from_w7(const double* w) {
+    // stiffness in tensor form: 1 * sum T + beta2 sum TT + beta3 TTT, with
+    // beta2 = w_s2/6 + w_s3/2 and beta3 = 3 w_s3 / 8 (the rotated families'
+    // symbols); the interior class values follow from them.
+    const double b2 = w[1] / 6.0 + w[2] / 2.0;
+    const double b3 = 3.0 * w[2] / 8.0;
+    EntryCoef<R> e;
+    e.s0 = static_cast<R>(-6.0 + 12.0 * b2 - 8.0 * b3);
+    e.s1 = static_cast<R>(1.0 - 4.0 * b2 + 4.0 * b3);
+    e.s2 = static_cast<R>(b2 - 2.0 * b3);
+    e.s3 = static_cast<R>(b3);
+    e.beta2 = static_cast<R>(b2);
+    e.beta3 = static_cast<R>(b3);
+    e.m0 = static_cast<R>(w[3]);
+    e.m1 = static_cast<R>(w[4]);
+    e.m2 = static_cast<R>(w[5]);
+    e.m3 = static_cast<R>(w[6]);
+    e.pad0 = e.pad1 = R(0);
+    return e;
+}
+
+template <typename T>
+static int upload(T** dptr, const T* host, size_t n, size_t* bytes) {
+    if (hipMalloc(reinterpret_cast<void**>(dptr), n * sizeof(T)) != hipSuccess) return HELM27_ENOMEM;
+    *bytes += n * sizeof(T);
+    H27_CHECK_HIP(hipMemcpy(*dptr, host, n * sizeof(T), hipMemcpyHostToDevice));
+    return HELM27_OK;
+}
+
+// Fill the weight tables, PML axes and tiling of a grid whose velocity is
+// already on the device (d_c) and whose index has been selected.
+int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
+    g->n_g = n_g;
+    g->fixed = fixed;
+    std::vector<EntryCoef<float>> ef(n_g);
+    std::vector<EntryCoef<double>> ed(n_g);
+    for (int i = 0; i < n_g; ++i) {
+        ef[i] = entry_from_w7<float>(w7 + 7 * i);
+        ed[i] = entry_from_w7<double>(w7 + 7 * i);
+    }
+    int st;
+    if ((st = upload(&g->d_entry_f, ef.data(), ef.size(), &g->bytes))) return st;
+    if ((st = upload(&g->d_entry_d, ed.data(), ed.size(), &g->bytes))) return st;
+    const int dims[3] = {g->nx, g->ny, g->nz};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        std::vector<AxisNode<double>> nd;
+        axis_nodes(dims[a], g->npml[a], g->h, g->omega, g->c_ref, g->R, &nd);
+        std::vector<AxisNode<float>> nf(nd.size());
+        for (size_t i = 0; i < nd.size(); ++i) {
+            const AxisNode<double>& s = nd[i];
+            nf[i] = AxisNode<float>{static_cast<float>(s.xi_re), static_cast<float>(s.xi_im),
+                                    static_cast<float>(s.tm_re), static_cast<float>(s.tm_im),
+                                    static_cast<float>(s.tp_re), static_cast<float>(s.tp_im),
+                                    static_cast<float>(s.um_re), static_cast<float>(s.um_im),
+                                    static_cast<float>(s.up_re), static_cast<float>(s.up_im), s.plain, 0};
+        }
+        if ((st = upload(&g->d_ax_d[a], nd.data(), nd.size(), &g->bytes))) return st;
+        if ((st = upload(&g->d_ax_f[a], nf.data(), nf.size(), &g->bytes))) return st;
+        plain_range(nd, &lo[a], &hi[a]);
+    }
+    make_tiling(g->nx, g->ny, lo, hi, &g->tiling, 0, g->nz);
+    return HELM27_OK;
+}
+
+}  // namespace h27
+
+using namespace h27;
+
+extern "C" int helm27_create(helm27_ctx** out, int device, size_t hbm_budget_bytes) {
+    if (!out) return HELM27_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return HELM27_EINVAL;
+    H27_CHECK_HIP(hipSetDevice(device));
+    helm27_ctx* c = new (std::nothrow) helm27_ctx;
+    if (!c) return HELM27_ENOMEM;
+    c->device = device;
+    if (hbm_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget_bytes = static_cast<size_t>(0.9 * fr);
+    }
+    c->hbm_budget = hbm_budget_bytes;
+    *out = c;
+    return HELM27_OK;
+}
+
+void helm27_serve_shutdown(helm27_ctx* ctx);  // serve.cpp
+
+extern "C" void helm27_destroy(helm27_ctx* ctx) {
+    if (!ctx) return;
+    helm27_serve_shutdown(ctx);
+    delete ctx;
+}
+
+extern "C" const char* helm27_strerror(int st) {
+    switch (st) {
+        case HELM27_OK: return "ok";
+        case HELM27_EINVAL: return "invalid argument";
+        case HELM27_ENOMEM: return "out of memory";
+        case HELM27_EADMIT: return "request exceeds the HBM budget";
+        case HELM27_ENOCONV: return "no convergence within the iteration limit";
+        case HELM27_ENUMERIC: return "NaN/Inf or breakdown";
+        case HELM27_EDEVICE: return "HIP device error";
+        case HELM27_ERANGE: return "source outside the grid or inside the PML";
+        case HELM27_ENOTFOUND: return "unknown ticket";
+        case HELM27_EAGAIN: return "not ready";
+        default: return "unknown status";
+    }
+}
+
+static bool is_device_ptr(const void* p) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, int ny, int nz,
+                               double h, double freq, const helm27_pml* pml, int flags, helm27_op** out) {
+    if (!ctx || !t || !vel || !out) return HELM27_EINVAL;
+    if (nx < 3 || ny < 3 || nz < 3 || !(h > 0) || !(freq > 0)) return HELM27_EINVAL;
+    const int wmode = flags & 0x3;
+    if (wmode == 3) return HELM27_EINVAL;
+    if (flags & ~(0x3 | HELM27_STORE_C64 | HELM27_STORE_C128)) return HELM27_EINVAL;
+    helm27_pml P{{8, 8, 8}, 1e-3, 0.0};
+    if (pml) P = *pml;
+    const int dims[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a)
+        if (P.npml[a] < 0 || 2 * P.npml[a] + 1 > dims[a]) return HELM27_EINVAL;
+    if (!(P.R > 0) || P.R >= 1) P.R = 1e-3;
+    H27_CHECK_HIP(hipSetDevice(ctx->device));
+
+    const int64_t N = static_cast<int64_t>(nx) * ny * nz;
+    std::vector<float> hc(N);
+    const bool dev = is_device_ptr(vel);
+    H27_CHECK_HIP(hipMemcpy(hc.data(), vel, N * sizeof(float), dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    float cmin = std::numeric_limits<float>::infinity(), cmax = 0.0f;
+    for (int64_t i = 0; i < N; ++i) {
+        const float v = hc[i];
+        if (!(v > 0.0f) || !std::isfinite(v)) return HELM27_EINVAL;
+        cmin = std::min(cmin, v);
+        cmax = std::max(cmax, v);
+    }
+    helm27_op* op = new (std::nothrow) helm27_op;
+    if (!op) return HELM27_ENOMEM;
+    op->ctx = ctx;
+    GridOp& g = op->g;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.N = N;
+    g.h = h;
+    g.omega = 2.0 * 3.14159265358979323846 * freq;
+    for (int a = 0; a < 3; ++a) g.npml[a] = P.npml[a];
+    g.R = P.R;
+    g.c_ref = P.c_ref > 0 ? P.c_ref : static_cast<double>(cmax);
+    op->freq = freq;
+    op->flags = flags;
+    op->w7 = t->w7;
+    op->table_gmin = t->g_min;
+    op->table_dg = t->dg;
+    const double fh = freq * h;
+    op->g_min_model = static_cast<double>(cmin) / fh;
+    op->g_max_model = static_cast<double>(cmax) / fh;
+
+    int st = HELM27_OK;
+    unsigned long long* d_cnt = nullptr;
+    auto fail = [&](int s) {
+        hipFree(d_cnt);
+        helm27_op_destroy(op);
+        return s;
+    };
+    if (hipMalloc(&g.d_c, N * sizeof(float)) != hipSuccess) return fail(HELM27_ENOMEM);
+    if (hipMalloc(&g.d_idx, N * sizeof(uint16_t)) != hipSuccess) return fail(HELM27_ENOMEM);
+    g.bytes += N * (sizeof(float) + sizeof(uint16_t));
+    if (hipMemcpy(g.d_c, hc.data(), N * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(HELM27_EDEVICE);
+    if (hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)) != hipSuccess) return fail(HELM27_ENOMEM);
+    if (hipMemset(d_cnt, 0, 2 * sizeof(unsigned long long)) != hipSuccess) return fail(HELM27_EDEVICE);
+    if ((st = launch_select_index(g.d_c, g.d_idx, N, fh, t->g_min, t->dg, t->n_g, d_cnt, nullptr)))
+        return fail(st);
+    unsigned long long cnt[2] = {0, 0};
+    if (hipMemcpy(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return fail(HELM27_EDEVICE);
+    hipFree(d_cnt);
+    d_cnt = nullptr;
+    if (cnt[1] != 0) return fail(HELM27_EINVAL);
+    op->n_clamped = static_cast<int64_t>(cnt[0]);
+
+    if ((st = grid_setup(&g, t->w7.data(), t->n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
+    if (wmode == HELM27_WEIGHTS_GAM) {
+        if (hipMalloc(&g.d_row_f, N * sizeof(EntryCoef<float>)) != hipSuccess) return fail(HELM27_ENOMEM);
+        if (hipMalloc(&g.d_row_d, N * sizeof(EntryCoef<double>)) != hipSuccess) return fail(HELM27_ENOMEM);
+        g.bytes += N * (sizeof(EntryCoef<float>) + sizeof(EntryCoef<double>));
+        if ((st = launch_gam_average<float>(g, g.d_row_f, nullptr))) return fail(st);
+        if ((st = launch_gam_average<double>(g, g.d_row_d, nullptr))) return fail(st);
+    }
+    if (flags & HELM27_STORE_C64) {
+        if (hipMalloc(&op->d_coef_f, 27 * N * sizeof(float2)) != hipSuccess) return fail(HELM27_ENOMEM);
+        g.bytes += 27 * N * sizeof(float2);
+        if ((st = launch_fill_stored<float>(g, op->d_coef_f, 0.0, nullptr))) return fail(st);
+    }
+    if (flags & HELM27_STORE_C128) {
+        if (hipMalloc(&op->d_coef_d, 27 * N * sizeof(double2)) != hipSuccess) return fail(HELM27_ENOMEM);
+        g.bytes += 27 * N * sizeof(double2);
+        if ((st = launch_fill_stored<double>(g, op->d_coef_d, 0.0, nullptr))) return fail(st);
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HELM27_EDEVICE);
+    *out = op;
+    return HELM27_OK;
+}
+
+void solver_free(helm27_op* op);  // solver.cpp
+
+extern "C" void helm27_op_destroy(helm27_op* op) {
+    if (!op) return;
+    solver_free(op);
+    grid_free(&op->g);
+    hipFree(op->d_coef_f);
+    hipFree(op->d_coef_d);
+    delete op;
+}
+
+extern "C" int helm27_op_info(const helm27_op* op, helm27_op_desc* o) {
+    if (!op || !o) return HELM27_EINVAL;
+    o->nx = op->g.nx;
+    o->ny = op->g.ny;
+    o->nz = op->g.nz;
+    o->h = op->g.h;
+    o->freq = op->freq;
+    o->omega = op->g.omega;
+    o->n_g = op->g.n_g;
+    o->n_clamped = op->n_clamped;
+    o->g_min_model = op->g_min_model;
+    o->g_max_model = op->g_max_model;
+    o->device_bytes = op->g.bytes;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_export_index(const helm27_op* op, uint16_t* idx) {
+    if (!op || !idx) return HELM27_EINVAL;
+    H27_CHECK_HIP(hipMemcpy(idx, op->g.d_idx, op->g.N * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    return HELM27_OK;
+}
+
+extern "C" int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t* indptr, int64_t* indices,
+                                 double* vals) {
+    if (!op) return HELM27_EINVAL;
+    const GridOp& g = op->g;
+    const int64_t nnz = static_cast<int64_t>(3 * g.nx - 2) * (3 * g.ny - 2) * (3 * g.nz - 2);
+    if (nnz_out) *nnz_out = nnz;
+    if (!indptr) return HELM27_OK;
+    if (!indices || !vals) return HELM27_EINVAL;
+    void* d_coef = nullptr;
+    if (hipMalloc(&d_coef, 27 * g.N * sizeof(double2)) != hipSuccess) return HELM27_ENOMEM;
+    int st = launch_fill_stored<double>(g, d_coef, 0.0, nullptr);
+    std::vector<double> hco;
+    if (st == HELM27_OK) {
+        hco.resize(static_cast<size_t>(27) * g.N * 2);
+        if (hipMemcpy(hco.data(), d_coef, hco.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            st = HELM27_EDEVICE;
+    }
+    hipFree(d_coef);
+    if (st) return st;
+    int64_t k = 0;
+    indptr[0] = 0;
+    const int64_t plane = static_cast<int64_t>(g.nx) * g.ny;
+    for (int64_t i = 0; i < g.N; ++i) {
+        const int x = static_cast<int>(i % g.nx), y = static_cast<int>((i / g.nx) % g.ny),
+                  z = static_cast<int>(i / plane);
+        for (int s = 0; s < 27; ++s) {
+            const int dz = s / 9 - 1, dy = (s / 3) % 3 - 1, dx = s % 3 - 1;
+            if (x + dx < 0 || x + dx >= g.nx || y + dy < 0 || y + dy >= g.ny || z + dz < 0 || z + dz >= g.nz)
+                continue;
+            indices[k] = i + dx + static_cast<int64_t>(g.nx) * dy + plane * dz;
+            vals[2 * k] = hco[2 * (static_cast<size_t>(s) * g.N + i)];
+            vals[2 * k + 1] = hco[2 * (static_cast<size_t>(s) * g.N + i) + 1];
+            ++k;
+        }
+        indptr[i + 1] = k;
+    }
+    return k == nnz ? HELM27_OK : HELM27_EDEVICE;
+}
+
+extern "C" int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int variant, void* stream) {
+    if (!op || !u || !y || nrhs <= 0) return HELM27_EINVAL;
+    if (u == y) return HELM27_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (variant == HELM27_RECOMPUTE) {
+        if (dtype == HELM27_C64) return launch_stencil<float>(op->g, 0, 0.0, u, y, nullptr, 0.0, nrhs, s);
+        if (dtype == HELM27_C128) return launch_stencil<double>(op->g, 0, 0.0, u, y, nullptr, 0.0, nrhs, s);
+        return HELM27_EINVAL;
+    }
+    if (variant == HELM27_STORED) {
+        if (dtype == HELM27_C64) {
+            if (!op->d_coef_f) return HELM27_EINVAL;
+            return launch_apply_stored<float>(op->g, op->d_coef_f, u, y, nrhs, s);
+        }
+        if (dtype == HELM27_C128) {
+            if (!op->d_coef_d) return HELM27_EINVAL;
+            return launch_apply_stored<double>(op->g, op->d_coef_d, u, y, nrhs, s);
+        }
+    }
+    return HELM27_EINVAL;
+}
