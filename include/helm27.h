@@ -181,22 +181,36 @@ int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t* indptr,
 int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int variant,
                  void* stream);
 
+/* Tuning of the recompute kernel's tile shape (output rows per wavefront in
+ * the unstretched box, 1..4; more rows reuse more loaded data, fewer rows
+ * leave registers for more wavefronts in flight).  helm27_set_tuning sets
+ * it for one precision; helm27_tune times every choice on the operator with
+ * nrhs zero right-hand sides (device scratch allocated and freed inside),
+ * keeps the fastest and returns it in *best_rows (may be NULL).  Every choice
+ * computes the same sums per output; the compiler may fuse multiply-adds
+ * differently per choice, so results agree to rounding (not bit for bit)
+ * across choices, and bit for bit across runs of one choice.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave);
+int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows);
+
 /* ---- (c) solve ------------------------------------------------------------ */
 typedef struct {
     double tol;          /* relative residual ||b - A u|| / ||b|| per RHS (default 1e-6) */
-    int    restart;      /* GMRES(m) restart length (default 20) */
-    int    max_inner;    /* Arnoldi steps per refinement step (default 400) */
-    int    max_outer;    /* FP64 refinement steps (default 20) */
-    double inner_tol;    /* relative reduction asked of each inner solve (default 1e-3) */
+    int    restart;      /* GMRES(m) restart length, 1..63 (default 30) */
+    int    max_inner;    /* Arnoldi steps per refinement step (default 600) */
+    int    max_outer;    /* FP64 refinement steps (default 10) */
+    double inner_tol;    /* relative reduction asked of each inner solve (default 1e-4) */
     int    precision;    /* HELM27_C64: FP32 inner + FP64 refinement (default);
                             HELM27_C128: everything in FP64 */
     int    mg_levels;    /* multigrid levels (default 4; 0 = no preconditioner) */
-    double mg_shift;     /* complex shift beta of the preconditioner (default 0.5) */
+    double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 1) */
     int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
-    double mg_omega;     /* Jacobi damping (default 0.8) */
+    double mg_omega;     /* Jacobi damping (default 0.6) */
     int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 20) */
-    int    use_graph;    /* capture each restart cycle in a hipGraph (default 1) */
+    int    use_graph;    /* capture the Arnoldi steps in hipGraphs (default 0) */
     int    verbose;
+    double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0.5) */
 } helm27_solve_opts;
 
 typedef struct {

@@ -39,7 +39,7 @@ class SolveOpts(C.Structure):
                 ("max_outer", C.c_int), ("inner_tol", C.c_double), ("precision", C.c_int),
                 ("mg_levels", C.c_int), ("mg_shift", C.c_double), ("mg_pre", C.c_int),
                 ("mg_post", C.c_int), ("mg_omega", C.c_double), ("mg_coarse_sweeps", C.c_int),
-                ("use_graph", C.c_int), ("verbose", C.c_int)]
+                ("use_graph", C.c_int), ("verbose", C.c_int), ("mg_shift_re", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -89,6 +89,8 @@ def _load():
         "helm27_export_index": (C.c_int, [P, C.c_void_p]),
         "helm27_export_csr": (C.c_int, [P, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p]),
         "helm27_apply": (C.c_int, [P, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+        "helm27_set_tuning": (C.c_int, [P, C.c_int, C.c_int]),
+        "helm27_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
         "helm27_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
         "helm27_solve": (C.c_int, [P, C.POINTER(C.c_double), C.c_void_p, C.c_int, C.POINTER(SolveOpts),
                                    C.POINTER(SolveStats), C.c_void_p]),

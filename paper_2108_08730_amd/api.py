@@ -114,6 +114,16 @@ class Operator:
                                    var, _stream_handle(stream)), "apply")
         return y
 
+    def set_tuning(self, dtype, rows_per_wave):
+        dt = L.C64 if dtype in ("c64", L.C64) else L.C128
+        L.check(L.lib.helm27_set_tuning(self._h, dt, rows_per_wave), "set_tuning")
+
+    def tune(self, nrhs=1, dtype="c64", stream=None):
+        dt = L.C64 if dtype in ("c64", L.C64) else L.C128
+        best = C.c_int()
+        L.check(L.lib.helm27_tune(self._h, nrhs, dt, _stream_handle(stream), C.byref(best)), "tune")
+        return best.value
+
     def solve(self, sources: Sequence[Sequence[int]], amps=None, out=None, stream=None, **opts):
         """Solve for point sources (i, j, k); returns (u [nrhs, N] complex128
         device tensor, stats dict)."""

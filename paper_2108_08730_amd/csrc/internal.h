@@ -90,9 +90,13 @@ struct GridOp {
     double h = 0, omega = 0;
     int npml[3] = {0, 0, 0};
     double R = 1e-3, c_ref = 0;
+    // PML layer in physical coordinates (node i at x = i h): unstretched for
+    // pml_lo[a] <= x <= pml_hi[a], layer width pml_L[a] (0 = no layer)
+    double pml_lo[3] = {0, 0, 0}, pml_hi[3] = {0, 0, 0}, pml_L[3] = {0, 0, 0};
     float* d_c = nullptr;                      // velocity [N]
     uint16_t* d_idx = nullptr;                 // table index [N]
     int n_g = 0;
+    int idx_lo = 0, idx_hi = 0;                // range of table indices in use
     int fixed = 0;                             // entry 0 on every row
     EntryCoef<float>* d_entry_f = nullptr;     // [n_g]
     EntryCoef<double>* d_entry_d = nullptr;
@@ -101,6 +105,8 @@ struct GridOp {
     AxisNode<float>* d_ax_f[3] = {nullptr, nullptr, nullptr};
     AxisNode<double>* d_ax_d[3] = {nullptr, nullptr, nullptr};
     Tiling tiling;
+    int plain_ry[2] = {2, 1};                  // plain-kernel rows per wave: [fp32, fp64] (1..4)
+    void* d_sink = nullptr;                    // 64 x 16 B target of masked-off lanes' stores
     size_t bytes = 0;
 };
 
@@ -114,6 +120,7 @@ struct helm27_op {
     h27::GridOp g;
     double freq = 0;
     int flags = 0;
+    float cmin = 0, cmax = 0;        // velocity range of the model
     int64_t n_clamped = 0;
     double g_min_model = 0, g_max_model = 0;
     void* d_coef_f = nullptr;        // stored: float2[27][N]
@@ -134,19 +141,22 @@ int op_build(helm27_ctx* ctx, const double* w7, int n_g, double g_min, double dg
              const float* vel, int nx, int ny, int nz, double h, double freq, double omega_shift,
              const helm27_pml* pml, int flags, helm27_op** out);
 void make_tiling(int nx, int ny, const int plain_lo[2], const int plain_hi[2], Tiling* t, int zchunk, int nz);
-void axis_nodes(int n, int npml, double h, double omega, double c_ref, double R,
+void axis_nodes(int n, double h, double x_lo, double x_hi, double L, double omega, double c_ref, double R,
                 std::vector<AxisNode<double>>* out);
+int grid_setup(GridOp* g, const double* w7, int n_g, int fixed);
+int host_index(float c, double fh, double gmin, double dg, int n_g);
 
 // kernels (kernels_*.hip): host-side launchers
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
                         int n_g, unsigned long long* d_nclamp, hipStream_t s);
 // y = A u (MODE_APPLY), y = b - A u (MODE_RESID) or y = u + omega_j D^-1 (b - A u)
-// (MODE_JACOBI) with A's mass scaled by (1 + i shift).  R = float | double.
+// (MODE_JACOBI) with A's mass scaled by (shift_re + i shift_im); (1, 0) is the
+// physical operator.  R = float | double.
 template <typename R>
-int launch_stencil(const GridOp& g, int mode, double shift, const void* u, void* y, const void* b,
-                   double omega_j, int nrhs, hipStream_t s);
+int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, const void* u, void* y,
+                   const void* b, double omega_j, int nrhs, hipStream_t s);
 template <typename R>
-int launch_fill_stored(const GridOp& g, void* coef, double shift, hipStream_t s);
+int launch_fill_stored(const GridOp& g, void* coef, double shift_re, double shift_im, hipStream_t s);
 template <typename R>
 int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* y, int nrhs,
                         hipStream_t s);

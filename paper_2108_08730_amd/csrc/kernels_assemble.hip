@@ -101,7 +101,7 @@ __global__ void fill_stored_kernel(GridData<R> g, typename V2<R>::T* __restrict_
         else E = g.entry[g.fixed ? 0 : g.idx[i]];
         const R cv = static_cast<R>(g.c[i]);
         const R kap = g.omega2 / (cv * cv);
-        const Cx<R> kc = mk(kap, kap * g.shift);
+        const Cx<R> kc = mk(kap * g.shift_re, kap * g.shift_im);
         const R sig = g.inv_h2;
         for (int dz = 0; dz < 3; ++dz)
             for (int dy = 0; dy < 3; ++dy)
@@ -133,10 +133,10 @@ __global__ void fill_stored_kernel(GridData<R> g, typename V2<R>::T* __restrict_
 }
 
 template <typename R>
-static GridData<R> make_grid_data(const GridOp& g, double shift);
+static GridData<R> make_grid_data(const GridOp& g, double shift_re, double shift_im);
 
 template <>
-GridData<float> make_grid_data<float>(const GridOp& g, double shift) {
+GridData<float> make_grid_data<float>(const GridOp& g, double shift_re, double shift_im) {
     GridData<float> d;
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
@@ -145,12 +145,13 @@ GridData<float> make_grid_data<float>(const GridOp& g, double shift) {
     d.ax = g.d_ax_f[0]; d.ay = g.d_ax_f[1]; d.az = g.d_ax_f[2];
     d.omega2 = static_cast<float>(g.omega * g.omega);
     d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
-    d.shift = static_cast<float>(shift);
+    d.shift_re = static_cast<float>(shift_re);
+    d.shift_im = static_cast<float>(shift_im);
     return d;
 }
 
 template <>
-GridData<double> make_grid_data<double>(const GridOp& g, double shift) {
+GridData<double> make_grid_data<double>(const GridOp& g, double shift_re, double shift_im) {
     GridData<double> d;
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
@@ -159,13 +160,14 @@ GridData<double> make_grid_data<double>(const GridOp& g, double shift) {
     d.ax = g.d_ax_d[0]; d.ay = g.d_ax_d[1]; d.az = g.d_ax_d[2];
     d.omega2 = g.omega * g.omega;
     d.inv_h2 = 1.0 / (g.h * g.h);
-    d.shift = shift;
+    d.shift_re = shift_re;
+    d.shift_im = shift_im;
     return d;
 }
 
 template <typename R>
-int launch_fill_stored(const GridOp& g, void* coef, double shift, hipStream_t s) {
-    GridData<R> d = make_grid_data<R>(g, shift);
+int launch_fill_stored(const GridOp& g, void* coef, double shift_re, double shift_im, hipStream_t s) {
+    GridData<R> d = make_grid_data<R>(g, shift_re, shift_im);
     int64_t blocks = (g.N + kBlock - 1) / kBlock;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(fill_stored_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
@@ -173,8 +175,8 @@ int launch_fill_stored(const GridOp& g, void* coef, double shift, hipStream_t s)
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
-template int launch_fill_stored<float>(const GridOp&, void*, double, hipStream_t);
-template int launch_fill_stored<double>(const GridOp&, void*, double, hipStream_t);
+template int launch_fill_stored<float>(const GridOp&, void*, double, double, hipStream_t);
+template int launch_fill_stored<double>(const GridOp&, void*, double, double, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Stored-coefficient apply: y_i = sum_s coef[s][i] u[i + off_s].  The 27
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void apply_stored_kernel(GridData<R> g, con
 
 template <typename R>
 int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* y, int nrhs, hipStream_t s) {
-    GridData<R> d = make_grid_data<R>(g, 0.0);
+    GridData<R> d = make_grid_data<R>(g, 1.0, 0.0);
     const int64_t blocks = (g.N + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(apply_stored_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
                        static_cast<const typename V2<R>::T*>(coef), static_cast<const typename V2<R>::T*>(u),
@@ -257,7 +259,7 @@ __global__ void gam_average_kernel(GridData<R> g, EntryCoef<R>* __restrict__ out
 
 template <typename R>
 int launch_gam_average(const GridOp& g, EntryCoef<R>* rowcoef, hipStream_t s) {
-    GridData<R> d = make_grid_data<R>(g, 0.0);
+    GridData<R> d = make_grid_data<R>(g, 1.0, 0.0);
     d.rowcoef = nullptr;
     int64_t blocks = (g.N + kBlock - 1) / kBlock;
     if (blocks > 16384) blocks = 16384;

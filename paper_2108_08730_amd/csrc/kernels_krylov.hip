@@ -1,2 +1,631 @@
-// placeholder for the Krylov / multigrid kernels
-#include "stencil.h"
+// Krylov, multigrid-transfer and precision-conversion kernels of the solver.
+//
+// Reductions (norms, multi-vector dot products) are two-stage and
+// deterministic: every block writes one partial per (right-hand side, basis
+// vector), reduced by a second kernel in a fixed order; no atomics.  Partial
+// sums are carried in FP64 (the vectors themselves are FP32 or FP64).
+// The GMRES Hessenberg / Givens / triangular-solve steps run on the device in
+// FP64, one thread per right-hand side.
+#include "krylov.h"
+
+namespace h27 {
+
+constexpr int kRedBlock = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block-wide sum of NV doubles per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][4] */) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k * 4 + w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = sh[k * 4 + 0] + sh[k * 4 + 1] + sh[k * 4 + 2] + sh[k * 4 + 3];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void fill_zero_kernel(T* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = T{};
+}
+
+static unsigned grid_for(int64_t n, int per_thread = 4) {
+    int64_t b = (n + static_cast<int64_t>(kRedBlock) * per_thread - 1) / (static_cast<int64_t>(kRedBlock) * per_thread);
+    if (b < 1) b = 1;
+    if (b > 65535) b = 65535;
+    return static_cast<unsigned>(b);
+}
+
+int fill_zero(void* p, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return HELM27_OK;
+    if (bytes % 16 == 0) {
+        const int64_t n = bytes / 16;
+        hipLaunchKernelGGL(fill_zero_kernel<double2>, dim3(grid_for(n)), dim3(kRedBlock), 0, s,
+                           static_cast<double2*>(p), n);
+    } else {
+        const int64_t n = bytes / 4;
+        hipLaunchKernelGGL(fill_zero_kernel<float>, dim3(grid_for(n)), dim3(kRedBlock), 0, s, static_cast<float*>(p),
+                           n);
+    }
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+// b[s][lin_s] = amp_s / h^3 (paper Sec. 3.1: delta source on a grid node)
+__global__ void inject_kernel(double2* __restrict__ b, int64_t N, const int64_t* __restrict__ lin,
+                              const double2* __restrict__ amp, int nsrc, double inv_h3) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nsrc) {
+        double2 v;
+        v.x = amp[s].x * inv_h3;
+        v.y = amp[s].y * inv_h3;
+        b[static_cast<int64_t>(s) * N + lin[s]] = v;
+    }
+}
+
+int inject_sources(double2* b, int64_t N, const int64_t* d_lin, const double2* d_amp, int nsrc, double h,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(inject_kernel, dim3((nsrc + 63) / 64), dim3(64), 0, s, b, N, d_lin, d_amp, nsrc,
+                       1.0 / (h * h * h));
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+// ---------------------------------------------------------------------------
+// partial[rhs][blk] = sum over the block's elements of |x|^2
+template <typename R>
+__global__ __launch_bounds__(kRedBlock) void norm2_partial_kernel(const typename V2<R>::T* __restrict__ x, int64_t N,
+                                                                  double* __restrict__ partial) {
+    __shared__ double sh[4];
+    const int rhs = blockIdx.y;
+    const typename V2<R>::T* xr = x + static_cast<int64_t>(rhs) * N;
+    double acc[1] = {0.0};
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        const typename V2<R>::T v = xr[i];
+        acc[0] += static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+    }
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(rhs) * gridDim.x + blockIdx.x] = acc[0];
+}
+
+// out[k] = sum_b partial[k][b], one block per k; optionally sqrt
+__global__ void reduce_rows_kernel(const double* __restrict__ partial, int nb, double* __restrict__ out, int take_sqrt) {
+    __shared__ double sh[4];
+    double acc[1] = {0.0};
+    const double* p = partial + static_cast<int64_t>(blockIdx.x) * nb;
+    for (int b = threadIdx.x; b < nb; b += kRedBlock) acc[0] += p[b];
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = take_sqrt ? sqrt(acc[0]) : acc[0];
+}
+
+template <typename R>
+int norms(const void* x, int64_t N, int nrhs, double* d_partial, int max_blocks, double* d_out, hipStream_t s) {
+    unsigned nb = grid_for(N);
+    if (nb > static_cast<unsigned>(max_blocks)) nb = max_blocks;
+    hipLaunchKernelGGL(norm2_partial_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<R>::T*>(x), N, d_partial);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(nrhs), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb), d_out,
+                       1);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int norms<float>(const void*, int64_t, int, double*, int, double*, hipStream_t);
+template int norms<double>(const void*, int64_t, int, double*, int, double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Multi-vector dot products h[rhs][j] = sum_i conj(V_j[rhs][i]) w[rhs][i] for
+// j in [j0, j0 + jn), jn <= 8.  V is [m+1][nrhs][N]; partial is
+// [nrhs][8][nb] (complex as 2 doubles).
+template <typename R>
+__global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
+                                                                 int j0, int jn, const typename V2<R>::T* __restrict__ w,
+                                                                 int64_t N, double* __restrict__ partial) {
+    __shared__ double sh[16 * 4];
+    const int rhs = blockIdx.y;
+    const typename V2<R>::T* wr = w + static_cast<int64_t>(rhs) * N;
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        const typename V2<R>::T wv = wr[i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < jn) {
+                const typename V2<R>::T v = V[static_cast<int64_t>(j0 + k) * vstride + static_cast<int64_t>(rhs) * N + i];
+                // conj(v) * w
+                acc[2 * k] += static_cast<double>(v.x) * wv.x + static_cast<double>(v.y) * wv.y;
+                acc[2 * k + 1] += static_cast<double>(v.x) * wv.y - static_cast<double>(v.y) * wv.x;
+            }
+        }
+    }
+    block_sum<16>(acc, sh);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < jn; ++k) {
+            double* p = partial + ((static_cast<int64_t>(rhs) * 8 + k) * gridDim.x + blockIdx.x) * 2;
+            p[0] = acc[2 * k];
+            p[1] = acc[2 * k + 1];
+        }
+    }
+}
+
+// h[rhs * ldh + j0 + k] (+)= sum_b partial[rhs][k][b]; one block per (rhs, k)
+__global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, int j0, int jn, double2* __restrict__ h,
+                                   int ldh, int accumulate) {
+    __shared__ double sh[8];
+    const int rhs = blockIdx.x / 8, k = blockIdx.x % 8;
+    if (k >= jn) return;
+    double acc[2] = {0.0, 0.0};
+    const double* p = partial + (static_cast<int64_t>(rhs) * 8 + k) * nb * 2;
+    for (int b = threadIdx.x; b < nb; b += kRedBlock) {
+        acc[0] += p[2 * b];
+        acc[1] += p[2 * b + 1];
+    }
+    block_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        double2* o = h + static_cast<int64_t>(rhs) * ldh + j0 + k;
+        if (accumulate) {
+            o->x += acc[0];
+            o->y += acc[1];
+        } else {
+            o->x = acc[0];
+            o->y = acc[1];
+        }
+    }
+}
+
+template <typename R>
+int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nrhs, double* d_partial, int max_blocks,
+         double2* d_h, int ldh, int accumulate, hipStream_t s) {
+    unsigned nb = grid_for(N);
+    if (nb > static_cast<unsigned>(max_blocks)) nb = max_blocks;
+    for (int j0 = 0; j0 < J; j0 += 8) {
+        const int jn = J - j0 < 8 ? J - j0 : 8;
+        hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
+                           static_cast<const typename V2<R>::T*>(V), vstride, j0, jn,
+                           static_cast<const typename V2<R>::T*>(w), N, d_partial);
+        hipLaunchKernelGGL(mdot_reduce_kernel, dim3(nrhs * 8), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb),
+                           j0, jn, d_h, ldh, accumulate);
+    }
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int mdot<float>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, int, int,
+                         hipStream_t);
+template int mdot<double>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, int, int,
+                          hipStream_t);
+
+// w[rhs] -= sum_{j < J} V_j[rhs] * hc[rhs][j] where hc are the coefficients of
+// the current pass (FP64 on the device, applied in the vector precision).
+template <typename R>
+__global__ __launch_bounds__(kRedBlock) void cgs_update_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
+                                                               int J, const double2* __restrict__ hc, int ldh,
+                                                               typename V2<R>::T* __restrict__ w, int64_t N) {
+    __shared__ R hs[2 * 64];
+    const int rhs = blockIdx.y;
+    for (int j = threadIdx.x; j < J; j += kRedBlock) {
+        const double2 c = hc[static_cast<int64_t>(rhs) * ldh + j];
+        hs[2 * j] = static_cast<R>(c.x);
+        hs[2 * j + 1] = static_cast<R>(c.y);
+    }
+    __syncthreads();
+    typename V2<R>::T* wr = w + static_cast<int64_t>(rhs) * N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        typename V2<R>::T acc = wr[i];
+        for (int j = 0; j < J; ++j) {
+            const typename V2<R>::T v = V[static_cast<int64_t>(j) * vstride + static_cast<int64_t>(rhs) * N + i];
+            const R hr = hs[2 * j], hi = hs[2 * j + 1];
+            acc.x -= v.x * hr - v.y * hi;
+            acc.y -= v.x * hi + v.y * hr;
+        }
+        wr[i] = acc;
+    }
+}
+
+template <typename R>
+int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int ldh, void* w, int64_t N, int nrhs,
+               hipStream_t s) {
+    if (J > 64) return HELM27_EINVAL;
+    hipLaunchKernelGGL(cgs_update_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<R>::T*>(V), vstride, J, d_hc, ldh,
+                       static_cast<typename V2<R>::T*>(w), N);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int cgs_update<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, hipStream_t);
+template int cgs_update<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, hipStream_t);
+
+// out[rhs] = x[rhs] * f(nrm[rhs]): mode 0 -> 1/nrm (0 if nrm == 0), mode 1 -> nrm
+template <typename Ri, typename Ro>
+__global__ void scale_kernel(const typename V2<Ri>::T* __restrict__ x, typename V2<Ro>::T* __restrict__ out, int64_t N,
+                             const double* __restrict__ nrm, int mode) {
+    const int rhs = blockIdx.y;
+    const double n = nrm[rhs];
+    const double f = mode == 0 ? (n > 0 ? 1.0 / n : 0.0) : n;
+    const typename V2<Ri>::T* xr = x + static_cast<int64_t>(rhs) * N;
+    typename V2<Ro>::T* orr = out + static_cast<int64_t>(rhs) * N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        const typename V2<Ri>::T v = xr[i];
+        typename V2<Ro>::T o;
+        o.x = static_cast<Ro>(static_cast<double>(v.x) * f);
+        o.y = static_cast<Ro>(static_cast<double>(v.y) * f);
+        orr[i] = o;
+    }
+}
+
+template <typename Ri, typename Ro>
+int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s) {
+    hipLaunchKernelGGL((scale_kernel<Ri, Ro>), dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<Ri>::T*>(x), static_cast<typename V2<Ro>::T*>(out), N, d_nrm,
+                       mode);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int scale_by_norm<float, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t);
+template int scale_by_norm<double, double>(const void*, void*, int64_t, int, const double*, int, hipStream_t);
+template int scale_by_norm<double, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t);
+
+// u64[rhs] += nrm[rhs] * e[rhs]  (refinement update, e in the inner precision)
+template <typename R>
+__global__ void refine_update_kernel(double2* __restrict__ u, const typename V2<R>::T* __restrict__ e, int64_t N,
+                                     const double* __restrict__ nrm) {
+    const int rhs = blockIdx.y;
+    const double f = nrm[rhs];
+    double2* ur = u + static_cast<int64_t>(rhs) * N;
+    const typename V2<R>::T* er = e + static_cast<int64_t>(rhs) * N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        const typename V2<R>::T v = er[i];
+        double2 a = ur[i];
+        a.x += f * static_cast<double>(v.x);
+        a.y += f * static_cast<double>(v.y);
+        ur[i] = a;
+    }
+}
+
+template <typename R>
+int refine_update(double2* u, const void* e, int64_t N, int nrhs, const double* d_nrm, hipStream_t s) {
+    hipLaunchKernelGGL(refine_update_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s, u,
+                       static_cast<const typename V2<R>::T*>(e), N, d_nrm);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int refine_update<float>(double2*, const void*, int64_t, int, const double*, hipStream_t);
+template int refine_update<double>(double2*, const void*, int64_t, int, const double*, hipStream_t);
+
+// x[rhs] (+)= sum_{j<k} V_j[rhs] * y[rhs][j]
+template <typename R>
+__global__ __launch_bounds__(kRedBlock) void combine_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride, int k,
+                                                            const double2* __restrict__ y, int ldy,
+                                                            typename V2<R>::T* __restrict__ x, int64_t N, int accumulate) {
+    __shared__ R ys[2 * 64];
+    const int rhs = blockIdx.y;
+    for (int j = threadIdx.x; j < k; j += kRedBlock) {
+        const double2 c = y[static_cast<int64_t>(rhs) * ldy + j];
+        ys[2 * j] = static_cast<R>(c.x);
+        ys[2 * j + 1] = static_cast<R>(c.y);
+    }
+    __syncthreads();
+    typename V2<R>::T* xr = x + static_cast<int64_t>(rhs) * N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        typename V2<R>::T acc;
+        if (accumulate) {
+            acc = xr[i];
+        } else {
+            acc.x = R(0);
+            acc.y = R(0);
+        }
+        for (int j = 0; j < k; ++j) {
+            const typename V2<R>::T v = V[static_cast<int64_t>(j) * vstride + static_cast<int64_t>(rhs) * N + i];
+            const R yr = ys[2 * j], yi = ys[2 * j + 1];
+            acc.x += v.x * yr - v.y * yi;
+            acc.y += v.x * yi + v.y * yr;
+        }
+        xr[i] = acc;
+    }
+}
+
+template <typename R>
+int combine(const void* V, int64_t vstride, int k, const double2* d_y, int ldy, void* x, int64_t N, int nrhs,
+            int accumulate, hipStream_t s) {
+    if (k > 64) return HELM27_EINVAL;
+    hipLaunchKernelGGL(combine_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<R>::T*>(V), vstride, k, d_y, ldy,
+                       static_cast<typename V2<R>::T*>(x), N, accumulate);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int combine<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, int, hipStream_t);
+template int combine<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, int, hipStream_t);
+
+// x[rhs] += y[rhs]
+template <typename R>
+__global__ void axpy1_kernel(typename V2<R>::T* __restrict__ x, const typename V2<R>::T* __restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+        typename V2<R>::T a = x[i];
+        const typename V2<R>::T b = y[i];
+        a.x += b.x;
+        a.y += b.y;
+        x[i] = a;
+    }
+}
+
+template <typename R>
+int add_inplace(void* x, const void* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpy1_kernel<R>, dim3(grid_for(n)), dim3(kRedBlock), 0, s, static_cast<typename V2<R>::T*>(x),
+                       static_cast<const typename V2<R>::T*>(y), n);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int add_inplace<float>(void*, const void*, int64_t, hipStream_t);
+template int add_inplace<double>(void*, const void*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// GMRES bookkeeping in FP64, one thread per right-hand side.
+// Layout per rhs: H [(m+1) x m] column-major (H[i + (m+1) j]), cs [m], sn [m]
+// (complex), g [m+1] (complex).  hcol[rhs][0..j] holds the orthogonalisation
+// coefficients of step j, nrm[rhs] = ||w|| = H(j+1, j).
+__global__ void givens_kernel(int j, int m, int nrhs, const double2* __restrict__ hcol, int ldh,
+                              const double* __restrict__ nrm, double2* __restrict__ H, double* __restrict__ cs,
+                              double2* __restrict__ sn, double2* __restrict__ g, double* __restrict__ est) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double2* Hr = H + static_cast<int64_t>(r) * (m + 1) * m;
+    double* c = cs + static_cast<int64_t>(r) * m;
+    double2* s = sn + static_cast<int64_t>(r) * m;
+    double2* gr = g + static_cast<int64_t>(r) * (m + 1);
+    double2* col = Hr + static_cast<int64_t>(j) * (m + 1);
+    for (int i = 0; i <= j; ++i) col[i] = hcol[static_cast<int64_t>(r) * ldh + i];
+    col[j + 1].x = nrm[r];
+    col[j + 1].y = 0.0;
+    // previous rotations: [a; b] <- [c a + s b; -conj(s) a + c b]
+    for (int i = 0; i < j; ++i) {
+        const double2 a = col[i], b = col[i + 1];
+        const double ci = c[i];
+        const double2 si = s[i];
+        double2 t;
+        t.x = ci * a.x + (si.x * b.x - si.y * b.y);
+        t.y = ci * a.y + (si.x * b.y + si.y * b.x);
+        double2 u;
+        u.x = -(si.x * a.x + si.y * a.y) + ci * b.x;
+        u.y = -(si.x * a.y - si.y * a.x) + ci * b.y;
+        col[i] = t;
+        col[i + 1] = u;
+    }
+    const double2 a = col[j], b = col[j + 1];
+    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+    const double rho = hypot(na, nb);
+    double cj;
+    double2 sj;
+    if (na == 0.0) {
+        cj = 0.0;
+        sj.x = 1.0;
+        sj.y = 0.0;
+    } else {
+        cj = na / rho;
+        // s = (a / |a|) conj(b) / rho
+        const double ax = a.x / na, ay = a.y / na;
+        sj.x = (ax * b.x + ay * b.y) / rho;
+        sj.y = (ay * b.x - ax * b.y) / rho;
+    }
+    c[j] = cj;
+    s[j] = sj;
+    double2 rj;
+    rj.x = cj * a.x + (sj.x * b.x - sj.y * b.y);
+    rj.y = cj * a.y + (sj.x * b.y + sj.y * b.x);
+    col[j] = rj;
+    col[j + 1].x = 0.0;
+    col[j + 1].y = 0.0;
+    const double2 gj = gr[j];
+    double2 g1;
+    g1.x = -(sj.x * gj.x + sj.y * gj.y);
+    g1.y = -(sj.x * gj.y - sj.y * gj.x);
+    gr[j + 1] = g1;
+    gr[j].x = cj * gj.x;
+    gr[j].y = cj * gj.y;
+    est[r] = hypot(g1.x, g1.y);
+}
+
+int givens_step(int j, int m, int nrhs, const double2* hcol, int ldh, const double* nrm, double2* H, double* cs,
+                double2* sn, double2* g, double* est, hipStream_t s) {
+    hipLaunchKernelGGL(givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, s, j, m, nrhs, hcol, ldh, nrm, H, cs, sn, g,
+                       est);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+// g[rhs][0] = beta[rhs], rest 0
+__global__ void ginit_kernel(double2* __restrict__ g, int m, int nrhs, const double* __restrict__ beta) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double2* gr = g + static_cast<int64_t>(r) * (m + 1);
+    for (int i = 0; i <= m; ++i) {
+        gr[i].x = 0.0;
+        gr[i].y = 0.0;
+    }
+    gr[0].x = beta[r];
+}
+
+int givens_init(double2* g, int m, int nrhs, const double* beta, hipStream_t s) {
+    hipLaunchKernelGGL(ginit_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, s, g, m, nrhs, beta);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+// y[rhs][0..k) = R_k^{-1} g_k (upper-triangular back substitution)
+__global__ void upper_solve_kernel(int k, int m, int nrhs, const double2* __restrict__ H, const double2* __restrict__ g,
+                                   double2* __restrict__ y, int ldy) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const double2* Hr = H + static_cast<int64_t>(r) * (m + 1) * m;
+    const double2* gr = g + static_cast<int64_t>(r) * (m + 1);
+    double2* yr = y + static_cast<int64_t>(r) * ldy;
+    for (int i = k - 1; i >= 0; --i) {
+        double sx = gr[i].x, sy = gr[i].y;
+        for (int jj = i + 1; jj < k; ++jj) {
+            const double2 h = Hr[i + static_cast<int64_t>(jj) * (m + 1)];
+            const double2 v = yr[jj];
+            sx -= h.x * v.x - h.y * v.y;
+            sy -= h.x * v.y + h.y * v.x;
+        }
+        const double2 d = Hr[i + static_cast<int64_t>(i) * (m + 1)];
+        const double dd = d.x * d.x + d.y * d.y;
+        double2 o;
+        if (dd > 0) {
+            o.x = (sx * d.x + sy * d.y) / dd;
+            o.y = (sy * d.x - sx * d.y) / dd;
+        } else {
+            o.x = 0.0;
+            o.y = 0.0;
+        }
+        yr[i] = o;
+    }
+}
+
+int upper_solve(int k, int m, int nrhs, const double2* H, const double2* g, double2* y, int ldy, hipStream_t s) {
+    hipLaunchKernelGGL(upper_solve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, s, k, m, nrhs, H, g, y, ldy);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid transfers between a grid (nx, ny, nz) and its coarse grid
+// ((nx+1)/2, ...): coarse node i sits on fine node 2i.  Full weighting
+// (1/4, 1/2, 1/4 per axis, fine nodes outside the grid count as zero) and its
+// adjoint up to a factor 8, trilinear interpolation.
+template <typename R>
+__global__ void restrict_kernel(const typename V2<R>::T* __restrict__ f, int nx, int ny, int nz,
+                                typename V2<R>::T* __restrict__ c, int cx, int cy, int cz, int nrhs) {
+    const int64_t Nc = static_cast<int64_t>(cx) * cy * cz, Nf = static_cast<int64_t>(nx) * ny * nz;
+    const int64_t total = Nc * nrhs;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int rhs = static_cast<int>(t / Nc);
+        const int64_t ic = t - static_cast<int64_t>(rhs) * Nc;
+        const int i = static_cast<int>(ic % cx), j = static_cast<int>((ic / cx) % cy), k = static_cast<int>(ic / (static_cast<int64_t>(cx) * cy));
+        const typename V2<R>::T* fr = f + static_cast<int64_t>(rhs) * Nf;
+        R sx = 0, sy = 0;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int z = 2 * k + dz;
+            if (z < 0 || z >= nz) continue;
+            const R wz = dz == 0 ? R(0.5) : R(0.25);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = 2 * j + dy;
+                if (y < 0 || y >= ny) continue;
+                const R wy = wz * (dy == 0 ? R(0.5) : R(0.25));
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = 2 * i + dx;
+                    if (x < 0 || x >= nx) continue;
+                    const R w = wy * (dx == 0 ? R(0.5) : R(0.25));
+                    const typename V2<R>::T v = fr[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)];
+                    sx += w * v.x;
+                    sy += w * v.y;
+                }
+            }
+        }
+        typename V2<R>::T o;
+        o.x = sx;
+        o.y = sy;
+        c[t] = o;
+    }
+}
+
+template <typename R>
+__global__ void prolong_add_kernel(const typename V2<R>::T* __restrict__ c, int cx, int cy, int cz,
+                                   typename V2<R>::T* __restrict__ f, int nx, int ny, int nz, int nrhs) {
+    const int64_t Nc = static_cast<int64_t>(cx) * cy * cz, Nf = static_cast<int64_t>(nx) * ny * nz;
+    const int64_t total = Nf * nrhs;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int rhs = static_cast<int>(t / Nf);
+        const int64_t iff = t - static_cast<int64_t>(rhs) * Nf;
+        const int x = static_cast<int>(iff % nx), y = static_cast<int>((iff / nx) % ny), z = static_cast<int>(iff / (static_cast<int64_t>(nx) * ny));
+        const typename V2<R>::T* cr = c + static_cast<int64_t>(rhs) * Nc;
+        // per axis: even -> one coarse node (weight 1), odd -> two (1/2 each)
+        int ix[2], iy[2], iz[2];
+        R wx[2], wy[2], wz[2];
+        int nxs, nys, nzs;
+        if (x % 2 == 0) { ix[0] = x / 2; wx[0] = 1; nxs = 1; } else { ix[0] = x / 2; ix[1] = x / 2 + 1; wx[0] = wx[1] = R(0.5); nxs = 2; }
+        if (y % 2 == 0) { iy[0] = y / 2; wy[0] = 1; nys = 1; } else { iy[0] = y / 2; iy[1] = y / 2 + 1; wy[0] = wy[1] = R(0.5); nys = 2; }
+        if (z % 2 == 0) { iz[0] = z / 2; wz[0] = 1; nzs = 1; } else { iz[0] = z / 2; iz[1] = z / 2 + 1; wz[0] = wz[1] = R(0.5); nzs = 2; }
+        R sx = 0, sy = 0;
+        for (int a = 0; a < nzs; ++a) {
+            if (iz[a] >= cz) continue;
+            for (int b = 0; b < nys; ++b) {
+                if (iy[b] >= cy) continue;
+                for (int e = 0; e < nxs; ++e) {
+                    if (ix[e] >= cx) continue;
+                    const R w = wz[a] * wy[b] * wx[e];
+                    const typename V2<R>::T v = cr[ix[e] + static_cast<int64_t>(cx) * (iy[b] + static_cast<int64_t>(cy) * iz[a])];
+                    sx += w * v.x;
+                    sy += w * v.y;
+                }
+            }
+        }
+        typename V2<R>::T o = f[t];
+        o.x += sx;
+        o.y += sy;
+        f[t] = o;
+    }
+}
+
+template <typename R>
+int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s) {
+    const int64_t total = static_cast<int64_t>(cx) * cy * cz * nrhs;
+    hipLaunchKernelGGL(restrict_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<R>::T*>(f), nx, ny, nz, static_cast<typename V2<R>::T*>(c), cx, cy,
+                       cz, nrhs);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template <typename R>
+int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int ny, int nz, int nrhs, hipStream_t s) {
+    const int64_t total = static_cast<int64_t>(nx) * ny * nz * nrhs;
+    hipLaunchKernelGGL(prolong_add_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<R>::T*>(c), cx, cy, cz, static_cast<typename V2<R>::T*>(f), nx, ny,
+                       nz, nrhs);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int mg_restrict<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
+template int mg_restrict<double>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
+template int mg_prolong_add<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
+template int mg_prolong_add<double>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
+
+// c_coarse[k][j][i] = c_fine[2k][2j][2i] (velocity injected to the coarse grid)
+__global__ void inject_velocity_kernel(const float* __restrict__ f, int nx, int ny, float* __restrict__ c, int cx, int cy,
+                                       int cz) {
+    const int64_t Nc = static_cast<int64_t>(cx) * cy * cz;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < Nc;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int i = static_cast<int>(t % cx), j = static_cast<int>((t / cx) % cy), k = static_cast<int>(t / (static_cast<int64_t>(cx) * cy));
+        c[t] = f[2 * i + static_cast<int64_t>(nx) * (2 * j + static_cast<int64_t>(ny) * 2 * k)];
+    }
+}
+
+int inject_velocity(const float* f, int nx, int ny, float* c, int cx, int cy, int cz, hipStream_t s) {
+    const int64_t total = static_cast<int64_t>(cx) * cy * cz;
+    hipLaunchKernelGGL(inject_velocity_kernel, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s, f, nx, ny, c, cx, cy, cz);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+
+}  // namespace h27

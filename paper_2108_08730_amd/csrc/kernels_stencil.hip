@@ -6,7 +6,8 @@
 //   A u = sigma * [ sum_a T_a + beta2 sum_{a<b} T_a T_b + beta3 T_x T_y T_z ] u
 //       + kappa * [ m0 XXX + 2 m1 sum UXX + 4 m2 sum UUX + 8 m3 UUU ] u
 //
-// with sigma = 1/h^2, kappa = k^2 (1 + i shift), 1D factors T (stretched second
+// with sigma = 1/h^2, kappa = k^2 (physical operator) or k^2 (a + i b) (the
+// complex-shifted operator of the preconditioner), 1D factors T (stretched second
 // difference), U (stretched neighbour half-sum), X (stretch at the node); an
 // axis absent from a product contributes X.  In the unstretched interior this
 // is exactly the weighted sum of the Cartesian, 45-degree-rotated and
@@ -25,6 +26,8 @@
 //   * frame tiles (x- or y-PML columns, 16 x 16): the separable contractions
 //     a = XX u, b = (TX + XT) u, c = TT u, d = (UX + XU) u, e = UU u with the
 //     column's complex 1D factors, then the same z combination.
+#include <algorithm>
+
 #include "stencil.h"
 
 namespace h27 {
@@ -147,9 +150,9 @@ __device__ __forceinline__ void plain_tile(const StencilArgs<R>& a, int tile, in
                 const R A0 = sig * E.s0 + kap * E.m0, A1 = sig * E.s1 + kap * E.m1;
                 const R A2 = sig * E.s2 + kap * E.m2, A3 = sig * E.s3 + kap * E.m3;
                 if (SHIFTED) {
-                    const R ks = kap * g.shift;
-                    const Cx<R> K0 = nd(A0, ks * E.m0), K1 = nd(A1, ks * E.m1);
-                    const Cx<R> K2 = nd(A2, ks * E.m2), K3 = nd(A3, ks * E.m3);
+                    const R kr = kap * (g.shift_re - R(1)), ks = kap * g.shift_im;
+                    const Cx<R> K0 = nd(A0 + kr * E.m0, ks * E.m0), K1 = nd(A1 + kr * E.m1, ks * E.m1);
+                    const Cx<R> K2 = nd(A2 + kr * E.m2, ks * E.m2), K3 = nd(A3 + kr * E.m3, ks * E.m3);
                     cmac(acc, K0, cB[r]);
                     cmac(acc, K1, Fc);
                     cmac(acc, K2, Ec);
@@ -167,7 +170,7 @@ __device__ __forceinline__ void plain_tile(const StencilArgs<R>& a, int tile, in
                 const Cx<R> t0 = -(tm + tp);
                 const Cx<R> xz = nd(Z.xi_re, Z.xi_im);
                 const Cx<R> um = nd(Z.um_re, Z.um_im), up = nd(Z.up_re, Z.up_im);
-                const Cx<R> kc = nd(kap, SHIFTED ? kap * g.shift : R(0));
+                const Cx<R> kc = SHIFTED ? nd(kap * g.shift_re, kap * g.shift_im) : nd(kap, R(0));
                 const Cx<R> kum = kc * um, kup = kc * up, kxz = kc * xz;
                 // planes zo -/+ 1: T_z (s1 c + s2 f + s3 e) sigma + U_z 2 (m1 c + m2 f + m3 e) kappa
                 const Cx<R> Kcm = (sig * E.s1) * tm + (R(2) * E.m1) * kum;
@@ -296,7 +299,7 @@ __device__ __forceinline__ void frame_tile(const StencilArgs<R>& a, int fb, int 
         const R cv = static_cast<R>(g.c[i]);
         const R kap = g.omega2 / (cv * cv);
         const R sig = g.inv_h2;
-        const Cx<R> kc = nd(kap, SHIFTED ? kap * g.shift : R(0));
+        const Cx<R> kc = SHIFTED ? nd(kap * g.shift_re, kap * g.shift_im) : nd(kap, R(0));
         const Cx<R> tzm = nd(Z.tm_re, Z.tm_im), tzp = nd(Z.tp_re, Z.tp_im);
         const Cx<R> tz0 = -(tzm + tzp);
         const Cx<R> xz = nd(Z.xi_re, Z.xi_im);
@@ -359,10 +362,10 @@ __global__ __launch_bounds__(kBlock) void stencil27_kernel(StencilArgs<R> a) {
 
 // ---------------------------------------------------------------------------
 template <typename R>
-static GridData<R> grid_data(const GridOp& g, double shift);
+static GridData<R> grid_data(const GridOp& g, double shift_re, double shift_im);
 
 template <>
-GridData<float> grid_data<float>(const GridOp& g, double shift) {
+GridData<float> grid_data<float>(const GridOp& g, double shift_re, double shift_im) {
     GridData<float> d;
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
@@ -371,12 +374,13 @@ GridData<float> grid_data<float>(const GridOp& g, double shift) {
     d.ax = g.d_ax_f[0]; d.ay = g.d_ax_f[1]; d.az = g.d_ax_f[2];
     d.omega2 = static_cast<float>(g.omega * g.omega);
     d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
-    d.shift = static_cast<float>(shift);
+    d.shift_re = static_cast<float>(shift_re);
+    d.shift_im = static_cast<float>(shift_im);
     return d;
 }
 
 template <>
-GridData<double> grid_data<double>(const GridOp& g, double shift) {
+GridData<double> grid_data<double>(const GridOp& g, double shift_re, double shift_im) {
     GridData<double> d;
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
@@ -385,7 +389,8 @@ GridData<double> grid_data<double>(const GridOp& g, double shift) {
     d.ax = g.d_ax_d[0]; d.ay = g.d_ax_d[1]; d.az = g.d_ax_d[2];
     d.omega2 = g.omega * g.omega;
     d.inv_h2 = 1.0 / (g.h * g.h);
-    d.shift = shift;
+    d.shift_re = shift_re;
+    d.shift_im = shift_im;
     return d;
 }
 
@@ -397,12 +402,13 @@ static int launch_mode(const StencilArgs<R>& args, dim3 grid, hipStream_t s) {
 }
 
 template <typename R>
-int launch_stencil(const GridOp& g, int mode, double shift, const void* u, void* y, const void* b,
+int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, const void* u, void* y, const void* b,
                    double omega_j, int nrhs, hipStream_t s) {
     if (nrhs <= 0) return HELM27_OK;
     const Tiling& t = g.tiling;
-    StencilArgs<R> a;
-    a.g = grid_data<R>(g, shift);
+    StencilArgs<R> a{};
+    a.g = grid_data<R>(g, shift_re, shift_im);
+    const bool shifted = !(shift_re == 1.0 && shift_im == 0.0);
     if (!a.g.entry || !a.g.ax || !a.g.ay || !a.g.az) return HELM27_EINVAL;
     a.px0 = t.plain_x0; a.py0 = t.plain_y0; a.pw = t.plain_w; a.ph = t.plain_h;
     a.ptx = t.n_plain_tiles_x > 0 ? t.n_plain_tiles_x : 1;
@@ -417,19 +423,56 @@ int launch_stencil(const GridOp& g, int mode, double shift, const void* u, void*
     a.fstart[4] = acc;
     a.n_plain_blocks = t.n_plain_blocks;
     a.zchunk = t.zchunk;
+    // The plain box goes to the wavefront-per-tile kernel when it can: table
+    // rows (not per-row averaged entries), a table slice that fits in LDS and
+    // 32-bit byte offsets for the buffer stores.
+    const int64_t vbytes = g.N * static_cast<int64_t>(sizeof(typename V2<R>::T));
+    const int n_tab = g.fixed ? 1 : g.idx_hi - g.idx_lo + 1;
+    (void)vbytes;
+    const bool use_plain = t.n_plain_blocks > 0 && !a.g.rowcoef && g.d_sink &&
+                           n_tab > 0 && static_cast<size_t>(n_tab) * 8 * sizeof(R) <= 64 * 1024;
+    if (use_plain) {
+        PlainArgs<R> p{};
+        p.g = a.g;
+        p.px0 = t.plain_x0; p.py0 = t.plain_y0; p.pw = t.plain_w; p.ph = t.plain_h;
+        const int RY = g.plain_ry[sizeof(R) == 8 ? 1 : 0];
+        p.ntx = (p.pw + kWaveCols - 1) / kWaveCols;
+        p.nty = (p.ph + RY - 1) / RY;
+        const int64_t tiles = static_cast<int64_t>(p.ntx) * p.nty * nrhs;
+        int64_t nzc = (4096 + tiles - 1) / tiles;
+        int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
+        zc = std::max(2, std::min(32, zc));
+        p.zchunk = std::min(zc, g.nz);
+        p.nzc = (g.nz + p.zchunk - 1) / p.zchunk;
+        p.nrhs = nrhs;
+        const int64_t items = tiles * p.nzc;
+        if (items > (int64_t(1) << 30)) return HELM27_EINVAL;
+        p.n_items = static_cast<int>(items);
+        p.tab_lo = g.fixed ? 0 : g.idx_lo;
+        p.n_tab = n_tab;
+        p.u = static_cast<const typename V2<R>::T*>(u);
+        p.y = static_cast<typename V2<R>::T*>(y);
+        p.b = static_cast<const typename V2<R>::T*>(b);
+        p.sink = static_cast<typename V2<R>::T*>(g.d_sink);
+        p.omega_j = static_cast<R>(omega_j);
+        const int st = launch_plain<R>(p, mode, shifted, RY, s);
+        if (st) return st;
+        a.n_plain_blocks = 0;
+    }
     a.nrhs = nrhs;
     a.u = static_cast<const typename V2<R>::T*>(u);
     a.y = static_cast<typename V2<R>::T*>(y);
     a.b = static_cast<const typename V2<R>::T*>(b);
     a.omega_j = static_cast<R>(omega_j);
-    const int nblk = t.n_plain_blocks + t.n_frame_blocks;
+    const int nblk = a.n_plain_blocks + t.n_frame_blocks;
+    if (nblk == 0) return HELM27_OK;
     const int per_rhs = nblk * t.n_zchunks;
     int groups = (4096 + per_rhs - 1) / per_rhs;
     if (groups > nrhs) groups = nrhs;
     if (groups < 1) groups = 1;
     if (groups > 65535) groups = 65535;
     dim3 grid(nblk, t.n_zchunks, groups);
-    const bool sh = shift != 0.0;
+    const bool sh = shifted;
     switch (mode) {
         case MODE_APPLY:
             return sh ? launch_mode<R, MODE_APPLY, true>(a, grid, s) : launch_mode<R, MODE_APPLY, false>(a, grid, s);
@@ -442,7 +485,7 @@ int launch_stencil(const GridOp& g, int mode, double shift, const void* u, void*
     }
 }
 
-template int launch_stencil<float>(const GridOp&, int, double, const void*, void*, const void*, double, int, hipStream_t);
-template int launch_stencil<double>(const GridOp&, int, double, const void*, void*, const void*, double, int, hipStream_t);
+template int launch_stencil<float>(const GridOp&, int, double, double, const void*, void*, const void*, double, int, hipStream_t);
+template int launch_stencil<double>(const GridOp&, int, double, double, const void*, void*, const void*, double, int, hipStream_t);
 
 }  // namespace h27

@@ -1,0 +1,40 @@
+// Host launchers of the Krylov / multigrid kernels (kernels_krylov.hip).
+#pragma once
+#include "stencil.h"
+
+namespace h27 {
+
+int fill_zero(void* p, int64_t bytes, hipStream_t s);
+int inject_sources(double2* b, int64_t N, const int64_t* d_lin, const double2* d_amp, int nsrc, double h,
+                   hipStream_t s);
+// d_out[rhs] = ||x[rhs]||_2 (FP64); d_partial holds nrhs * max_blocks doubles
+template <typename R>
+int norms(const void* x, int64_t N, int nrhs, double* d_partial, int max_blocks, double* d_out, hipStream_t s);
+// d_h[rhs * ldh + j] (+)= <V_j[rhs], w[rhs]> for j < J; d_partial holds nrhs * 8 * max_blocks * 2 doubles
+template <typename R>
+int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nrhs, double* d_partial, int max_blocks,
+         double2* d_h, int ldh, int accumulate, hipStream_t s);
+template <typename R>
+int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int ldh, void* w, int64_t N, int nrhs,
+               hipStream_t s);
+// out = x / nrm (mode 0) or x * nrm (mode 1), per right-hand side
+template <typename Ri, typename Ro>
+int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s);
+template <typename R>
+int refine_update(double2* u, const void* e, int64_t N, int nrhs, const double* d_nrm, hipStream_t s);
+template <typename R>
+int combine(const void* V, int64_t vstride, int k, const double2* d_y, int ldy, void* x, int64_t N, int nrhs,
+            int accumulate, hipStream_t s);
+template <typename R>
+int add_inplace(void* x, const void* y, int64_t n, hipStream_t s);
+int givens_init(double2* g, int m, int nrhs, const double* beta, hipStream_t s);
+int givens_step(int j, int m, int nrhs, const double2* hcol, int ldh, const double* nrm, double2* H, double* cs,
+                double2* sn, double2* g, double* est, hipStream_t s);
+int upper_solve(int k, int m, int nrhs, const double2* H, const double2* g, double2* y, int ldy, hipStream_t s);
+template <typename R>
+int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s);
+template <typename R>
+int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int ny, int nz, int nrhs, hipStream_t s);
+int inject_velocity(const float* f, int nx, int ny, float* c, int cx, int cy, int cz, hipStream_t s);
+
+}  // namespace h27

@@ -12,32 +12,29 @@
 namespace h27 {
 
 // PML stretching along one axis (paper Sec. 2.1: d/dx -> (1/xi) d/dx with
-// xi = 1 + i gamma/omega).  Profile: on each face a layer of npml nodes of
-// width L = npml h with gamma(d) = gamma_max (1 - cos(pi d / (2 L))) at depth d
-// into the layer and gamma_max = c_ref ln(1/R) / (2 L (1 - 2/pi)), which makes
-// exp(-(2/c_ref) int_0^L gamma) = R.  Evaluated at nodes and half nodes.
-static double pml_gamma(double x, int n, int npml, double h, double c_ref, double R) {
-    const double L = npml * h;
-    const double lo = npml * h, hi = (n - 1 - npml) * h;
+// xi = 1 + i gamma/omega).  Profile: a layer of width L beyond [x_lo, x_hi]
+// with gamma(d) = gamma_max (1 - cos(pi d / (2 L))) at depth d into the layer
+// and gamma_max = c_ref ln(1/R) / (2 L (1 - 2/pi)), which makes
+// exp(-(2/c_ref) int_0^L gamma) = R; the same formula holds beyond the last
+// node.  Evaluated at nodes x = i h and half nodes (i +- 1/2) h, so every
+// multigrid level samples the same physical stretching.
+static double pml_gamma(double x, double x_lo, double x_hi, double L, double c_ref, double R) {
     double d = 0.0;
-    if (x < lo) d = lo - x;
-    if (x > hi) d = x - hi;
-    if (d <= 0.0) return 0.0;
+    if (x < x_lo) d = x_lo - x;
+    if (x > x_hi) d = x - x_hi;
+    if (d <= 0.0 || L <= 0.0) return 0.0;
     const double pi = 3.14159265358979323846;
     const double gmax = c_ref * std::log(1.0 / R) / (2.0 * L * (1.0 - 2.0 / pi));
     return gmax * (1.0 - std::cos(pi * d / (2.0 * L)));
 }
 
-void axis_nodes(int n, int npml, double h, double omega, double c_ref, double R,
+void axis_nodes(int n, double h, double x_lo, double x_hi, double L, double omega, double c_ref, double R,
                 std::vector<AxisNode<double>>* out) {
     out->assign(n, AxisNode<double>{});
     for (int i = 0; i < n; ++i) {
-        double gn = 0, gm = 0, gp = 0;
-        if (npml > 0) {
-            gn = pml_gamma(i * h, n, npml, h, c_ref, R);
-            gm = pml_gamma((i - 0.5) * h, n, npml, h, c_ref, R);
-            gp = pml_gamma((i + 0.5) * h, n, npml, h, c_ref, R);
-        }
+        const double gn = pml_gamma(i * h, x_lo, x_hi, L, c_ref, R);
+        const double gm = pml_gamma((i - 0.5) * h, x_lo, x_hi, L, c_ref, R);
+        const double gp = pml_gamma((i + 0.5) * h, x_lo, x_hi, L, c_ref, R);
         AxisNode<double>& a = (*out)[i];
         a.xi_re = 1.0;
         a.xi_im = gn / omega;
@@ -118,6 +115,7 @@ void grid_free(GridOp* g) {
     hipFree(g->d_entry_d);
     hipFree(g->d_row_f);
     hipFree(g->d_row_d);
+    hipFree(g->d_sink);
     for (int a = 0; a < 3; ++a) {
         hipFree(g->d_ax_f[a]);
         hipFree(g->d_ax_d[a]);
@@ -155,6 +153,16 @@ static int upload(T** dptr, const T* host, size_t n, size_t* bytes) {
     return HELM27_OK;
 }
 
+// The same binary64 formula as the device index selection.
+int host_index(float c, double fh, double gmin, double dg, int n_g) {
+    const double G = static_cast<double>(c) / fh;
+    const double t = (G - gmin) / dg;
+    const double raw = std::floor(t + 0.5);
+    if (!(raw >= 0.0)) return 0;
+    if (raw > static_cast<double>(n_g - 1)) return n_g - 1;
+    return static_cast<int>(raw);
+}
+
 // Fill the weight tables, PML axes and tiling of a grid whose velocity is
 // already on the device (d_c) and whose index has been selected.
 int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
@@ -173,7 +181,7 @@ int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
         std::vector<AxisNode<double>> nd;
-        axis_nodes(dims[a], g->npml[a], g->h, g->omega, g->c_ref, g->R, &nd);
+        axis_nodes(dims[a], g->h, g->pml_lo[a], g->pml_hi[a], g->pml_L[a], g->omega, g->c_ref, g->R, &nd);
         std::vector<AxisNode<float>> nf(nd.size());
         for (size_t i = 0; i < nd.size(); ++i) {
             const AxisNode<double>& s = nd[i];
@@ -188,6 +196,8 @@ int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
         plain_range(nd, &lo[a], &hi[a]);
     }
     make_tiling(g->nx, g->ny, lo, hi, &g->tiling, 0, g->nz);
+    if (hipMalloc(&g->d_sink, 64 * 16) != hipSuccess) return HELM27_ENOMEM;
+    g->bytes += 64 * 16;
     return HELM27_OK;
 }
 
@@ -278,7 +288,12 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
     g.nx = nx; g.ny = ny; g.nz = nz; g.N = N;
     g.h = h;
     g.omega = 2.0 * 3.14159265358979323846 * freq;
-    for (int a = 0; a < 3; ++a) g.npml[a] = P.npml[a];
+    for (int a = 0; a < 3; ++a) {
+        g.npml[a] = P.npml[a];
+        g.pml_L[a] = P.npml[a] * h;
+        g.pml_lo[a] = P.npml[a] * h;
+        g.pml_hi[a] = (dims[a] - 1 - P.npml[a]) * h;
+    }
     g.R = P.R;
     g.c_ref = P.c_ref > 0 ? P.c_ref : static_cast<double>(cmax);
     op->freq = freq;
@@ -287,6 +302,8 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
     op->table_gmin = t->g_min;
     op->table_dg = t->dg;
     const double fh = freq * h;
+    op->cmin = cmin;
+    op->cmax = cmax;
     op->g_min_model = static_cast<double>(cmin) / fh;
     op->g_max_model = static_cast<double>(cmax) / fh;
 
@@ -314,6 +331,9 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
     op->n_clamped = static_cast<int64_t>(cnt[0]);
 
     if ((st = grid_setup(&g, t->w7.data(), t->n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
+    // idx is non-decreasing in c, so the smallest / largest velocities give its range
+    g.idx_lo = host_index(cmin, fh, t->g_min, t->dg, t->n_g);
+    g.idx_hi = host_index(cmax, fh, t->g_min, t->dg, t->n_g);
     if (wmode == HELM27_WEIGHTS_GAM) {
         if (hipMalloc(&g.d_row_f, N * sizeof(EntryCoef<float>)) != hipSuccess) return fail(HELM27_ENOMEM);
         if (hipMalloc(&g.d_row_d, N * sizeof(EntryCoef<double>)) != hipSuccess) return fail(HELM27_ENOMEM);
@@ -324,12 +344,12 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
     if (flags & HELM27_STORE_C64) {
         if (hipMalloc(&op->d_coef_f, 27 * N * sizeof(float2)) != hipSuccess) return fail(HELM27_ENOMEM);
         g.bytes += 27 * N * sizeof(float2);
-        if ((st = launch_fill_stored<float>(g, op->d_coef_f, 0.0, nullptr))) return fail(st);
+        if ((st = launch_fill_stored<float>(g, op->d_coef_f, 1.0, 0.0, nullptr))) return fail(st);
     }
     if (flags & HELM27_STORE_C128) {
         if (hipMalloc(&op->d_coef_d, 27 * N * sizeof(double2)) != hipSuccess) return fail(HELM27_ENOMEM);
         g.bytes += 27 * N * sizeof(double2);
-        if ((st = launch_fill_stored<double>(g, op->d_coef_d, 0.0, nullptr))) return fail(st);
+        if ((st = launch_fill_stored<double>(g, op->d_coef_d, 1.0, 0.0, nullptr))) return fail(st);
     }
     if (hipDeviceSynchronize() != hipSuccess) return fail(HELM27_EDEVICE);
     *out = op;
@@ -379,7 +399,7 @@ extern "C" int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t*
     if (!indices || !vals) return HELM27_EINVAL;
     void* d_coef = nullptr;
     if (hipMalloc(&d_coef, 27 * g.N * sizeof(double2)) != hipSuccess) return HELM27_ENOMEM;
-    int st = launch_fill_stored<double>(g, d_coef, 0.0, nullptr);
+    int st = launch_fill_stored<double>(g, d_coef, 1.0, 0.0, nullptr);
     std::vector<double> hco;
     if (st == HELM27_OK) {
         hco.resize(static_cast<size_t>(27) * g.N * 2);
@@ -413,8 +433,8 @@ extern "C" int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int
     if (u == y) return HELM27_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (variant == HELM27_RECOMPUTE) {
-        if (dtype == HELM27_C64) return launch_stencil<float>(op->g, 0, 0.0, u, y, nullptr, 0.0, nrhs, s);
-        if (dtype == HELM27_C128) return launch_stencil<double>(op->g, 0, 0.0, u, y, nullptr, 0.0, nrhs, s);
+        if (dtype == HELM27_C64) return launch_stencil<float>(op->g, 0, 1.0, 0.0, u, y, nullptr, 0.0, nrhs, s);
+        if (dtype == HELM27_C128) return launch_stencil<double>(op->g, 0, 1.0, 0.0, u, y, nullptr, 0.0, nrhs, s);
         return HELM27_EINVAL;
     }
     if (variant == HELM27_STORED) {
@@ -428,4 +448,55 @@ extern "C" int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int
         }
     }
     return HELM27_EINVAL;
+}
+
+extern "C" int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave) {
+    if (!op || rows_per_wave < 1 || rows_per_wave > 4) return HELM27_EINVAL;
+    if (dtype == HELM27_C64) op->g.plain_ry[0] = rows_per_wave;
+    else if (dtype == HELM27_C128) op->g.plain_ry[1] = rows_per_wave;
+    else return HELM27_EINVAL;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows) {
+    if (!op || nrhs <= 0 || (dtype != HELM27_C64 && dtype != HELM27_C128)) return HELM27_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t vb = dtype == HELM27_C64 ? 8 : 16;
+    const size_t bytes = static_cast<size_t>(op->g.N) * nrhs * vb;
+    void *u = nullptr, *y = nullptr;
+    if (hipMalloc(&u, bytes) != hipSuccess) return HELM27_ENOMEM;
+    if (hipMalloc(&y, bytes) != hipSuccess) {
+        hipFree(u);
+        return HELM27_ENOMEM;
+    }
+    int st = HELM27_OK;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    if (hipMemsetAsync(u, 0, bytes, s) != hipSuccess) st = HELM27_EDEVICE;
+    const int slot = dtype == HELM27_C64 ? 0 : 1;
+    float best = 1e30f;
+    int best_ry = op->g.plain_ry[slot];
+    for (int ry = 1; ry <= 4 && st == HELM27_OK; ++ry) {
+        op->g.plain_ry[slot] = ry;
+        for (int w = 0; w < 2 && st == HELM27_OK; ++w) st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
+        (void)hipEventRecord(e0, s);
+        const int reps = 10;
+        for (int r = 0; r < reps && st == HELM27_OK; ++r) st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) st = HELM27_EDEVICE;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (st == HELM27_OK && ms < best) {
+            best = ms;
+            best_ry = ry;
+        }
+    }
+    op->g.plain_ry[slot] = best_ry;
+    if (best_rows) *best_rows = best_ry;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hipFree(u);
+    hipFree(y);
+    return st;
 }

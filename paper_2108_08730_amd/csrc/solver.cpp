@@ -1,3 +1,559 @@
-// placeholder: filled in with the Krylov solver
-#include "internal.h"
-void solver_free(helm27_op* op) { (void)op; }
+// Krylov solve of [M + S] p = s (paper Sec. 2.1 / 3.1) on the GPU.
+//
+// The paper factorises the impedance matrix with a sparse direct solver; this
+// solver is matrix-free and iterative:
+//   * outer loop in FP64: r = b - A u with the FP64 stencil, stop when every
+//     right-hand side has ||r|| / ||b|| <= tol, else solve A e = r / ||r||
+//     approximately and update u += ||r|| e (iterative refinement);
+//   * inner solve: restarted GMRES(m) in the inner precision (complex FP32 by
+//     default), right-preconditioned, classical Gram-Schmidt with one
+//     reorthogonalisation (CGS2), Hessenberg / Givens / triangular solve in
+//     FP64 on the device, all right-hand sides advancing together;
+//   * preconditioner: one V-cycle of geometric multigrid on the complex-shifted
+//     operator S + (a + i b) k^2 M (a = 0.5, b = 1 by default), rediscretised on
+//     every level (velocity injected, h doubled, the same weight table and the
+//     same physical PML), damped-Jacobi smoothing with the same stencil kernel,
+//     full-weighting restriction and trilinear prolongation.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "krylov.h"
+
+namespace h27 {
+
+struct SolverState {
+    // hierarchy (levels 1..L-1 owned here; level 0 is the operator's grid)
+    int levels = 0;
+    int req_levels = -1;             // levels asked for when the hierarchy was built
+    std::vector<GridOp> coarse;
+    // workspace
+    int nrhs = 0, m = 0, prec = 0;   // prec = sizeof(real) of the inner precision
+    int64_t N = 0;
+    std::vector<void*> bufs;         // every allocation, freed together
+    void* V = nullptr;               // (m+1) x [nrhs][N]
+    void* w = nullptr;
+    void* e = nullptr;
+    void* rin = nullptr;
+    void* tmp = nullptr;
+    std::vector<void*> X, T, B, Rr;  // per level
+    double2* r64 = nullptr;
+    double* d_partial = nullptr;
+    int max_blocks = 1024;
+    double2* d_hcol = nullptr;
+    double2* d_htmp = nullptr;
+    double* d_nrm = nullptr;
+    double* d_beta = nullptr;
+    double* d_est = nullptr;
+    double* d_rn = nullptr;
+    double* d_bn = nullptr;
+    double2* d_H = nullptr;
+    double* d_cs = nullptr;
+    double2* d_sn = nullptr;
+    double2* d_g = nullptr;
+    double2* d_y = nullptr;
+    int64_t* d_lin = nullptr;
+    double2* d_amp = nullptr;
+    int src_cap = 0;
+};
+
+static void free_workspace(SolverState* S) {
+    for (void* p : S->bufs) hipFree(p);
+    S->bufs.clear();
+    S->X.clear();
+    S->T.clear();
+    S->B.clear();
+    S->Rr.clear();
+    S->nrhs = S->m = S->prec = 0;
+}
+
+static void free_hierarchy(SolverState* S) {
+    for (GridOp& g : S->coarse) grid_free(&g);
+    S->coarse.clear();
+    S->levels = 0;
+}
+
+static int alloc(SolverState* S, void** p, size_t bytes) {
+    if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+        *p = nullptr;
+        return HELM27_ENOMEM;
+    }
+    S->bufs.push_back(*p);
+    return HELM27_OK;
+}
+
+// Coarse grids: node i of level l+1 sits on node 2i of level l.
+static int build_hierarchy(helm27_op* op, SolverState* S, int levels) {
+    free_hierarchy(S);
+    const GridOp* prev = &op->g;
+    unsigned long long* d_cnt = nullptr;
+    if (hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)) != hipSuccess) return HELM27_ENOMEM;
+    int st = HELM27_OK;
+    S->coarse.reserve(levels > 1 ? levels - 1 : 0);
+    for (int l = 1; l < levels; ++l) {
+        const int cx = (prev->nx + 1) / 2, cy = (prev->ny + 1) / 2, cz = (prev->nz + 1) / 2;
+        if (cx < 3 || cy < 3 || cz < 3) break;
+        S->coarse.emplace_back();
+        GridOp& c = S->coarse.back();
+        c.nx = cx;
+        c.ny = cy;
+        c.nz = cz;
+        c.N = static_cast<int64_t>(cx) * cy * cz;
+        c.h = prev->h * 2.0;
+        c.omega = prev->omega;
+        c.R = prev->R;
+        c.c_ref = prev->c_ref;
+        for (int a = 0; a < 3; ++a) {
+            c.npml[a] = 0;
+            c.pml_lo[a] = prev->pml_lo[a];
+            c.pml_hi[a] = prev->pml_hi[a];
+            c.pml_L[a] = prev->pml_L[a];
+        }
+        if (hipMalloc(&c.d_c, c.N * sizeof(float)) != hipSuccess ||
+            hipMalloc(&c.d_idx, c.N * sizeof(uint16_t)) != hipSuccess) {
+            st = HELM27_ENOMEM;
+            break;
+        }
+        c.bytes += c.N * (sizeof(float) + sizeof(uint16_t));
+        if ((st = inject_velocity(prev->d_c, prev->nx, prev->ny, c.d_c, cx, cy, cz, nullptr))) break;
+        const double fh = op->freq * c.h;
+        if (hipMemset(d_cnt, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+            st = HELM27_EDEVICE;
+            break;
+        }
+        const int n_g = op->g.n_g;
+        if ((st = launch_select_index(c.d_c, c.d_idx, c.N, fh, op->table_gmin, op->table_dg, n_g, d_cnt, nullptr))) break;
+        if ((st = grid_setup(&c, op->w7.data(), n_g, op->g.fixed))) break;
+        c.idx_lo = host_index(op->cmin, fh, op->table_gmin, op->table_dg, n_g);
+        c.idx_hi = host_index(op->cmax, fh, op->table_gmin, op->table_dg, n_g);
+        prev = &c;
+    }
+    hipFree(d_cnt);
+    if (hipDeviceSynchronize() != hipSuccess && st == HELM27_OK) st = HELM27_EDEVICE;
+    S->levels = 1 + static_cast<int>(S->coarse.size());
+    return st;
+}
+
+static const GridOp& level_grid(const helm27_op* op, const SolverState* S, int l) {
+    return l == 0 ? op->g : S->coarse[l - 1];
+}
+
+static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int prec) {
+    if (S->nrhs == nrhs && S->m == m && S->prec == prec && S->N == op->g.N &&
+        static_cast<int>(S->X.size()) == S->levels)
+        return HELM27_OK;
+    free_workspace(S);
+    const int64_t N = op->g.N;
+    const size_t vb = static_cast<size_t>(2 * prec);   // complex element bytes
+    const size_t vec = static_cast<size_t>(N) * nrhs * vb;
+    int st;
+    if ((st = alloc(S, &S->V, vec * (m + 1)))) return st;
+    if ((st = alloc(S, &S->w, vec))) return st;
+    if ((st = alloc(S, &S->e, vec))) return st;
+    if ((st = alloc(S, &S->rin, vec))) return st;
+    if ((st = alloc(S, &S->tmp, vec))) return st;
+    S->X.resize(S->levels);
+    S->T.resize(S->levels);
+    S->B.resize(S->levels);
+    S->Rr.resize(S->levels);
+    for (int l = 0; l < S->levels; ++l) {
+        const size_t lv = static_cast<size_t>(level_grid(op, S, l).N) * nrhs * vb;
+        if ((st = alloc(S, &S->X[l], lv))) return st;
+        if ((st = alloc(S, &S->T[l], lv))) return st;
+        if ((st = alloc(S, &S->Rr[l], lv))) return st;
+        if (l > 0) {
+            if ((st = alloc(S, &S->B[l], lv))) return st;
+        } else {
+            S->B[l] = nullptr;
+        }
+    }
+    void* p;
+    if ((st = alloc(S, &p, static_cast<size_t>(N) * nrhs * sizeof(double2)))) return st;
+    S->r64 = static_cast<double2*>(p);
+    S->max_blocks = 1024;
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * 8 * S->max_blocks * 2 * sizeof(double)))) return st;
+    S->d_partial = static_cast<double*>(p);
+    const int ldh = m + 1;
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * ldh * sizeof(double2)))) return st;
+    S->d_hcol = static_cast<double2*>(p);
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * ldh * sizeof(double2)))) return st;
+    S->d_htmp = static_cast<double2*>(p);
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * ldh * sizeof(double2)))) return st;
+    S->d_y = static_cast<double2*>(p);
+    double* dd[5];
+    for (int k = 0; k < 5; ++k) {
+        if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * sizeof(double)))) return st;
+        dd[k] = static_cast<double*>(p);
+    }
+    S->d_nrm = dd[0];
+    S->d_beta = dd[1];
+    S->d_est = dd[2];
+    S->d_rn = dd[3];
+    S->d_bn = dd[4];
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1) * m * sizeof(double2)))) return st;
+    S->d_H = static_cast<double2*>(p);
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * m * sizeof(double)))) return st;
+    S->d_cs = static_cast<double*>(p);
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * m * sizeof(double2)))) return st;
+    S->d_sn = static_cast<double2*>(p);
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1) * sizeof(double2)))) return st;
+    S->d_g = static_cast<double2*>(p);
+    S->nrhs = nrhs;
+    S->m = m;
+    S->prec = prec;
+    S->N = N;
+    return HELM27_OK;
+}
+
+// Givens bookkeeping adds the two CGS passes' coefficients: hcol += htmp.
+__global__ void hadd_kernel(double2* __restrict__ a, const double2* __restrict__ b, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        a[i].x += b[i].x;
+        a[i].y += b[i].y;
+    }
+}
+
+struct Ctx {
+    helm27_op* op;
+    SolverState* S;
+    const helm27_solve_opts* o;
+    hipStream_t s;
+    int nrhs;
+};
+
+// One V-cycle on level l for right-hand side b (inner precision R); returns
+// the buffer that holds the result.
+template <typename R>
+static int vcycle(const Ctx& c, int l, const void* b, void** out) {
+    SolverState* S = c.S;
+    const GridOp& G = level_grid(c.op, S, l);
+    const int64_t bytes = G.N * c.nrhs * static_cast<int64_t>(2 * sizeof(R));
+    void* x = S->X[l];
+    void* t = S->T[l];
+    int st;
+    if ((st = fill_zero(x, bytes, c.s))) return st;
+    const bool coarsest = l == S->levels - 1;
+    const double a = c.o->mg_shift_re, bshift = c.o->mg_shift;
+    const int pre = coarsest ? c.o->mg_coarse_sweeps : c.o->mg_pre;
+    for (int k = 0; k < pre; ++k) {
+        if ((st = launch_stencil<R>(G, MODE_JACOBI, a, bshift, x, t, b, c.o->mg_omega, c.nrhs, c.s))) return st;
+        std::swap(x, t);
+    }
+    if (!coarsest) {
+        const GridOp& Gc = level_grid(c.op, S, l + 1);
+        if ((st = launch_stencil<R>(G, MODE_RESID, a, bshift, x, S->Rr[l], b, 0.0, c.nrhs, c.s))) return st;
+        if ((st = mg_restrict<R>(S->Rr[l], G.nx, G.ny, G.nz, S->B[l + 1], Gc.nx, Gc.ny, Gc.nz, c.nrhs, c.s))) return st;
+        void* xc = nullptr;
+        if ((st = vcycle<R>(c, l + 1, S->B[l + 1], &xc))) return st;
+        if ((st = mg_prolong_add<R>(xc, Gc.nx, Gc.ny, Gc.nz, x, G.nx, G.ny, G.nz, c.nrhs, c.s))) return st;
+        for (int k = 0; k < c.o->mg_post; ++k) {
+            if ((st = launch_stencil<R>(G, MODE_JACOBI, a, bshift, x, t, b, c.o->mg_omega, c.nrhs, c.s))) return st;
+            std::swap(x, t);
+        }
+    }
+    *out = x;
+    return HELM27_OK;
+}
+
+// z = M^-1 v (or z = v without preconditioner); returns the result buffer.
+template <typename R>
+static int precond(const Ctx& c, const void* v, void** z) {
+    if (c.S->levels <= 0 || c.o->mg_levels <= 0) {
+        *z = const_cast<void*>(v);
+        return HELM27_OK;
+    }
+    return vcycle<R>(c, 0, v, z);
+}
+
+static int read_host(std::vector<double>* h, const double* d, int n, hipStream_t s) {
+    h->resize(n);
+    H27_CHECK_HIP(hipMemcpyAsync(h->data(), d, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    H27_CHECK_HIP(hipStreamSynchronize(s));
+    return HELM27_OK;
+}
+
+// GMRES(m) on A x = rhs (inner precision R), x starting at zero.  Stops when
+// every right-hand side's residual estimate is <= thr[rhs] * ||rhs||.
+template <typename R>
+static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector<double>& thr, int max_it,
+                       int* iters, bool* conv) {
+    SolverState* S = c.S;
+    const GridOp& G = c.op->g;
+    const int nrhs = c.nrhs, m = S->m, ldh = m + 1;
+    const int64_t N = G.N;
+    const int64_t vstride = N * nrhs;
+    const int64_t vbytes = vstride * static_cast<int64_t>(2 * sizeof(R));
+    const size_t eb = 2 * sizeof(R);
+    int st;
+    if ((st = fill_zero(x, vbytes, c.s))) return st;
+    std::vector<double> bn, est;
+    if ((st = norms<R>(rhs, N, nrhs, S->d_partial, S->max_blocks, S->d_nrm, c.s))) return st;
+    if ((st = read_host(&bn, S->d_nrm, nrhs, c.s))) return st;
+    for (double v : bn)
+        if (!std::isfinite(v)) return HELM27_ENUMERIC;
+    int it = 0;
+    *conv = false;
+    bool first = true;
+    while (it < max_it) {
+        const void* r;
+        if (first) {
+            r = rhs;
+        } else {
+            if ((st = launch_stencil<R>(G, MODE_RESID, 1.0, 0.0, x, S->w, rhs, 0.0, nrhs, c.s))) return st;
+            r = S->w;
+        }
+        if ((st = norms<R>(r, N, nrhs, S->d_partial, S->max_blocks, S->d_beta, c.s))) return st;
+        std::vector<double> beta;
+        if ((st = read_host(&beta, S->d_beta, nrhs, c.s))) return st;
+        bool all = true;
+        for (int k = 0; k < nrhs; ++k) {
+            if (!std::isfinite(beta[k])) return HELM27_ENUMERIC;
+            if (beta[k] > thr[k] * bn[k]) all = false;
+        }
+        if (all) {
+            *conv = true;
+            break;
+        }
+        first = false;
+        if ((st = scale_by_norm<R, R>(r, S->V, N, nrhs, S->d_beta, 0, c.s))) return st;
+        if ((st = givens_init(S->d_g, m, nrhs, S->d_beta, c.s))) return st;
+        int k = 0;
+        bool cyc_conv = false;
+        for (int j = 0; j < m && it < max_it; ++j) {
+            void* vj = static_cast<char*>(S->V) + static_cast<size_t>(j) * vstride * eb;
+            void* z = nullptr;
+            if ((st = precond<R>(c, vj, &z))) return st;
+            if ((st = launch_stencil<R>(G, MODE_APPLY, 1.0, 0.0, z, S->w, nullptr, 0.0, nrhs, c.s))) return st;
+            if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_hcol, ldh, 0, c.s)))
+                return st;
+            if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_hcol, ldh, S->w, N, nrhs, c.s))) return st;
+            if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_htmp, ldh, 0, c.s)))
+                return st;
+            if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_htmp, ldh, S->w, N, nrhs, c.s))) return st;
+            hipLaunchKernelGGL(hadd_kernel, dim3((nrhs * ldh + 255) / 256), dim3(256), 0, c.s, S->d_hcol, S->d_htmp,
+                               nrhs * ldh);
+            if ((st = norms<R>(S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_nrm, c.s))) return st;
+            void* vj1 = static_cast<char*>(S->V) + static_cast<size_t>(j + 1) * vstride * eb;
+            if ((st = scale_by_norm<R, R>(S->w, vj1, N, nrhs, S->d_nrm, 0, c.s))) return st;
+            if ((st = givens_step(j, m, nrhs, S->d_hcol, ldh, S->d_nrm, S->d_H, S->d_cs, S->d_sn, S->d_g, S->d_est, c.s)))
+                return st;
+            ++it;
+            k = j + 1;
+            if ((st = read_host(&est, S->d_est, nrhs, c.s))) return st;
+            bool done = true;
+            for (int q = 0; q < nrhs; ++q) {
+                if (!std::isfinite(est[q])) return HELM27_ENUMERIC;
+                if (est[q] > thr[q] * bn[q]) done = false;
+            }
+            if (c.o->verbose)
+                std::fprintf(stderr, "helm27: gmres it %d est[0] %.3e (target %.3e)\n", it, est[0], thr[0] * bn[0]);
+            if (done) {
+                cyc_conv = true;
+                break;
+            }
+        }
+        if ((st = upper_solve(k, m, nrhs, S->d_H, S->d_g, S->d_y, ldh, c.s))) return st;
+        if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->tmp, N, nrhs, 0, c.s))) return st;
+        void* z = nullptr;
+        if ((st = precond<R>(c, S->tmp, &z))) return st;
+        if ((st = add_inplace<R>(x, z, vstride, c.s))) return st;
+        if (cyc_conv) {
+            *conv = true;
+            break;
+        }
+    }
+    *iters = it;
+    return HELM27_OK;
+}
+
+static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, const helm27_solve_opts* o,
+                      helm27_solve_stats* stats, hipStream_t s) {
+    SolverState* S = static_cast<SolverState*>(op->solver);
+    const int want_levels = o->mg_levels > 0 ? o->mg_levels : 0;
+    if (want_levels != S->req_levels) {
+        free_workspace(S);
+        free_hierarchy(S);
+        if (want_levels > 0) {
+            const int st = build_hierarchy(op, S, want_levels);
+            if (st) return st;
+        }
+        S->req_levels = want_levels;
+    }
+    const int prec = o->precision == HELM27_C128 ? 8 : 4;
+    int st = ensure_workspace(op, S, nrhs, o->restart, prec);
+    if (st) return st;
+    Ctx c{op, S, o, s, nrhs};
+    const GridOp& G = op->g;
+    const int64_t N = G.N;
+    if ((st = fill_zero(u, N * nrhs * static_cast<int64_t>(sizeof(double2)), s))) return st;
+    std::vector<double> bn, rn;
+    if ((st = norms<double>(b, N, nrhs, S->d_partial, S->max_blocks, S->d_bn, s))) return st;
+    if ((st = read_host(&bn, S->d_bn, nrhs, s))) return st;
+    for (double v : bn)
+        if (!std::isfinite(v)) return HELM27_ENUMERIC;
+    int outer = 0, inner_total = 0;
+    bool converged = false;
+    double maxrel = 0;
+    for (;;) {
+        if ((st = launch_stencil<double>(G, MODE_RESID, 1.0, 0.0, u, S->r64, b, 0.0, nrhs, s))) return st;
+        if ((st = norms<double>(S->r64, N, nrhs, S->d_partial, S->max_blocks, S->d_rn, s))) return st;
+        if ((st = read_host(&rn, S->d_rn, nrhs, s))) return st;
+        maxrel = 0;
+        for (int k = 0; k < nrhs; ++k) {
+            if (!std::isfinite(rn[k])) return HELM27_ENUMERIC;
+            const double rel = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+            maxrel = std::max(maxrel, rel);
+        }
+        if (o->verbose) std::fprintf(stderr, "helm27: outer %d max relres %.3e\n", outer, maxrel);
+        if (maxrel <= o->tol) {
+            converged = true;
+            break;
+        }
+        if (outer >= o->max_outer) break;
+        // inner thresholds relative to the normalised residual
+        std::vector<double> thr(nrhs);
+        for (int k = 0; k < nrhs; ++k) {
+            const double need = (bn[k] > 0 && rn[k] > 0) ? 0.5 * o->tol * bn[k] / rn[k] : 1.0;
+            thr[k] = std::min(1.0, std::max(need, o->inner_tol));
+            if (prec == 8) thr[k] = std::min(1.0, need);
+        }
+        int its = 0;
+        bool ic = false;
+        if (prec == 4) {
+            if ((st = scale_by_norm<double, float>(S->r64, S->rin, N, nrhs, S->d_rn, 0, s))) return st;
+            if ((st = gmres_inner<float>(c, S->rin, S->e, thr, o->max_inner, &its, &ic))) return st;
+            if ((st = refine_update<float>(u, S->e, N, nrhs, S->d_rn, s))) return st;
+        } else {
+            if ((st = scale_by_norm<double, double>(S->r64, S->rin, N, nrhs, S->d_rn, 0, s))) return st;
+            if ((st = gmres_inner<double>(c, S->rin, S->e, thr, o->max_inner, &its, &ic))) return st;
+            if ((st = refine_update<double>(u, S->e, N, nrhs, S->d_rn, s))) return st;
+        }
+        inner_total += its;
+        ++outer;
+        if (its == 0) break;   // no progress possible
+    }
+    if (stats) {
+        stats->outer_iters = outer;
+        stats->inner_iters = inner_total;
+        stats->converged = converged ? 1 : 0;
+        stats->max_relres = maxrel;
+    }
+    return converged ? HELM27_OK : HELM27_ENOCONV;
+}
+
+}  // namespace h27
+
+using namespace h27;
+
+void solver_free(helm27_op* op) {
+    if (!op || !op->solver) return;
+    SolverState* S = static_cast<SolverState*>(op->solver);
+    free_workspace(S);
+    free_hierarchy(S);
+    hipFree(S->d_lin);
+    hipFree(S->d_amp);
+    delete S;
+    op->solver = nullptr;
+}
+
+extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
+    if (!o) return;
+    o->tol = 1e-6;
+    o->restart = 30;
+    o->max_inner = 600;
+    o->max_outer = 10;
+    o->inner_tol = 1e-4;
+    o->precision = HELM27_C64;
+    o->mg_levels = 4;
+    o->mg_shift = 1.0;
+    o->mg_shift_re = 0.5;
+    o->mg_pre = 2;
+    o->mg_post = 2;
+    o->mg_omega = 0.6;
+    o->mg_coarse_sweeps = 20;
+    o->use_graph = 0;
+    o->verbose = 0;
+}
+
+static int check_opts(const helm27_solve_opts* o) {
+    if (!(o->tol > 0) || o->restart < 1 || o->restart > 63 || o->max_inner < 1 || o->max_outer < 0 ||
+        !(o->inner_tol > 0) || o->inner_tol >= 1 || (o->precision != HELM27_C64 && o->precision != HELM27_C128) ||
+        o->mg_levels < 0 || o->mg_levels > 8 || o->mg_pre < 0 || o->mg_post < 0 || o->mg_coarse_sweeps < 0 ||
+        !(o->mg_omega > 0) || !std::isfinite(o->mg_shift) || !std::isfinite(o->mg_shift_re))
+        return HELM27_EINVAL;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_solve_rhs(helm27_op* op, const void* b, void* u, int nrhs, const helm27_solve_opts* opts,
+                                helm27_solve_stats* stats, void* stream) {
+    if (!op || !b || !u || nrhs <= 0) return HELM27_EINVAL;
+    helm27_solve_opts o;
+    if (opts) o = *opts;
+    else helm27_solve_opts_default(&o);
+    int st = check_opts(&o);
+    if (st) return st;
+    if (!op->solver) {
+        op->solver = new (std::nothrow) SolverState;
+        if (!op->solver) return HELM27_ENOMEM;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = solve_core(op, static_cast<const double2*>(b), static_cast<double2*>(u), nrhs, &o, stats, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == HELM27_OK) st = HELM27_EDEVICE;
+    if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+extern "C" int helm27_solve(helm27_op* op, const double* src, void* u, int nrhs, const helm27_solve_opts* opts,
+                            helm27_solve_stats* stats, void* stream) {
+    if (!op || !src || !u || nrhs <= 0) return HELM27_EINVAL;
+    const GridOp& G = op->g;
+    std::vector<int64_t> lin(nrhs);
+    std::vector<double2> amp(nrhs);
+    const int dims[3] = {G.nx, G.ny, G.nz};
+    for (int k = 0; k < nrhs; ++k) {
+        int p[3];
+        for (int a = 0; a < 3; ++a) {
+            const double v = src[5 * k + a];
+            if (!(v == std::floor(v))) return HELM27_EINVAL;
+            p[a] = static_cast<int>(v);
+            if (p[a] < G.npml[a] || p[a] > dims[a] - 1 - G.npml[a]) return HELM27_ERANGE;
+        }
+        if (!std::isfinite(src[5 * k + 3]) || !std::isfinite(src[5 * k + 4])) return HELM27_ENUMERIC;
+        lin[k] = p[0] + static_cast<int64_t>(G.nx) * (p[1] + static_cast<int64_t>(G.ny) * p[2]);
+        amp[k].x = src[5 * k + 3];
+        amp[k].y = src[5 * k + 4];
+    }
+    if (!op->solver) {
+        op->solver = new (std::nothrow) SolverState;
+        if (!op->solver) return HELM27_ENOMEM;
+    }
+    SolverState* S = static_cast<SolverState*>(op->solver);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (S->src_cap < nrhs) {
+        hipFree(S->d_lin);
+        hipFree(S->d_amp);
+        S->d_lin = nullptr;
+        S->d_amp = nullptr;
+        if (hipMalloc(&S->d_lin, nrhs * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc(&S->d_amp, nrhs * sizeof(double2)) != hipSuccess)
+            return HELM27_ENOMEM;
+        S->src_cap = nrhs;
+    }
+    double2* b = nullptr;
+    if (hipMalloc(&b, static_cast<size_t>(G.N) * nrhs * sizeof(double2)) != hipSuccess) return HELM27_ENOMEM;
+    int st = HELM27_OK;
+    if (hipMemcpyAsync(S->d_lin, lin.data(), nrhs * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(S->d_amp, amp.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, s) != hipSuccess)
+        st = HELM27_EDEVICE;
+    if (!st) st = fill_zero(b, G.N * nrhs * static_cast<int64_t>(sizeof(double2)), s);
+    if (!st) st = inject_sources(b, G.N, S->d_lin, S->d_amp, nrhs, G.h, s);
+    if (!st) st = helm27_solve_rhs(op, b, u, nrhs, opts, stats, stream);
+    hipStreamSynchronize(s);
+    hipFree(b);
+    return st;
+}

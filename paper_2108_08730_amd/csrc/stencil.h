@@ -27,7 +27,7 @@ struct GridData {
     const AxisNode<R>* az;
     R omega2;                      // omega^2 (k^2 = omega^2 / c^2)
     R inv_h2;                      // 1 / h^2
-    R shift;                       // beta: mass scaled by (1 + i beta)
+    R shift_re, shift_im;          // mass scaled by (shift_re + i shift_im); (1, 0) = physical
 };
 
 template <typename R>
@@ -46,5 +46,26 @@ struct StencilArgs {
     const typename V2<R>::T* b;    // [nrhs][N] (RESID / JACOBI)
     R omega_j;                     // Jacobi damping
 };
+
+
+// Arguments of the plain-box kernel (one wavefront per tile of 62 output
+// columns x RY rows x zchunk planes; table slice staged in LDS).
+template <typename R>
+struct PlainArgs {
+    GridData<R> g;
+    int px0, py0, pw, ph;          // plain box
+    int ntx, nty, nzc, zchunk;     // tiles along x, y, z chunks
+    int nrhs, n_items;             // work items = ntx * nty * nzc * nrhs
+    int tab_lo, n_tab;             // table slice [tab_lo, tab_lo + n_tab)
+    const typename V2<R>::T* u;
+    typename V2<R>::T* y;
+    const typename V2<R>::T* b;
+    typename V2<R>::T* sink;       // [64] store target of lanes without an output
+    R omega_j;
+};
+
+constexpr int kWaveCols = 62;      // output columns per wavefront (lanes 1..62)
+
+template <typename R> int launch_plain(const PlainArgs<R>& a, int mode, bool shifted, int ry, hipStream_t s);
 
 }  // namespace h27

@@ -1,0 +1,159 @@
+"""GPU solves against the oracle.
+
+Every solve is certified by the oracle: the relative residual
+||b - A_oracle u|| / ||b|| is evaluated with the oracle's own FP64 CSR and
+must be <= the requested tolerance (1e-8 for the 41^3 homogeneous case,
+1e-6 otherwise); where the oracle can solve directly, the error against its
+solution is bounded too.  Both sides assemble with the oracle's table.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import analytic as An
+from oracle import operator as O
+from oracle import solve as S
+from oracle import table as T
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2108_08730_amd import api
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    return api.Context(0)
+
+
+@pytest.fixture(scope="module")
+def oracle_table():
+    Gs, W = T.build_table(3.0, 20.0, 0.05, 1e-3)
+    return Gs, W, T.complete_weights(W)
+
+
+@pytest.fixture(scope="module")
+def table(ctx, oracle_table):
+    return ctx.table_from_weights(3.0, 0.05, oracle_table[1])
+
+
+def _oracle_A(c, f, h, npml, W7):
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, len(W7))
+    return O.assemble(c, f, h, npml, O.row_weights("GA", idx, W7))
+
+
+def _certify(A, u, b):
+    return S.relative_residual(A, u.T, b)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_small_solve_matches_direct_solve(ctx, table, oracle_table, precision):
+    dims, npml, f, h = (16, 14, 12), 3, 6.0, 25.0
+    c = synth.random_field_model(dims, h, seed=4)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    src = [(7, 6, 5), (8, 7, 4)]
+    u, st = op.solve(src, tol=1e-10, precision=precision)
+    assert st["status"] == 0 and st["converged"] == 1
+    A = _oracle_A(c, f, h, npml, oracle_table[2])
+    b = S.point_source_rhs(dims, h, src)
+    ud = u.cpu().numpy()
+    assert np.all(_certify(A, ud, b) <= 1e-10 * 1.01)
+    ref = S.solve(A, b).T
+    for k in range(2):
+        assert np.linalg.norm(ud[k] - ref[k]) / np.linalg.norm(ref[k]) < 1e-8
+
+
+def test_homogeneous_41_greens_function(ctx, table, oracle_table):
+    """41^3 homogeneous, c = 2000 m/s, h = 20 m, f = 10 Hz (G = 10), 8-node
+    PML, centre source, GMRES(30) to 1e-8: oracle-certified residual and the
+    analytic Green's function after the discrete amplitude factor."""
+    n, npml, h, cv, f = 41, 8, 20.0, 2000.0, 10.0
+    c = synth.homogeneous((n, n, n), cv)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    s = (20, 20, 20)
+    u, st = op.solve([s], tol=1e-8, restart=30)
+    assert st["converged"] == 1
+    A = _oracle_A(c, f, h, npml, oracle_table[2])
+    b = S.point_source_rhs((n, n, n), h, [s])
+    ud = u.cpu().numpy()[0]
+    assert _certify(A, ud[None], b)[0] <= 1e-8 * 1.01
+    k = 2 * math.pi * f / cv
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X = np.stack([(ii - s[0]) * h, (jj - s[1]) * h, (kk - s[2]) * h], -1).reshape(-1, 3)
+    r = np.linalg.norm(X, axis=1)
+    inner = ((ii >= npml) & (ii < n - npml) & (jj >= npml) & (jj < n - npml)
+             & (kk >= npml) & (kk < n - npml)).ravel() & (r >= 2 * h)
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, 341)
+    alpha, _ = An.amplitude_factor([1, 0, 0], h, k, oracle_table[2][idx.ravel()[0]])
+    g = An.greens(r[inner], k)
+    err = np.linalg.norm(ud[inner] - alpha * g) / np.linalg.norm(alpha * g)
+    assert err < 2e-3
+
+
+def test_gradient_101_mixed_and_fp64(ctx, table, oracle_table):
+    """101^3 vertical gradient c = 1500 + 0.7 z, h = 25 m, f = 5 Hz, 10-node PML,
+    one source near the top: complex-FP32 GMRES with FP64 refinement and the
+    all-FP64 solve both reach 1e-6 certified by the oracle; their difference
+    is bounded by the conditioning of the tolerance."""
+    dims, npml, f, h = (101, 101, 101), 10, 5.0, 25.0
+    c = synth.gradient_z(dims, h, 1500.0, 0.7)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    src = [(50, 50, 11)]
+    um, stm = op.solve(src, tol=1e-6)
+    u6, st6 = op.solve(src, tol=1e-6, precision="fp64")
+    assert stm["converged"] == 1 and st6["converged"] == 1
+    A = _oracle_A(c, f, h, npml, oracle_table[2])
+    b = S.point_source_rhs(dims, h, src)
+    a = um.cpu().numpy()
+    d = u6.cpu().numpy()
+    assert _certify(A, a, b)[0] <= 1e-6 * 1.01
+    assert _certify(A, d, b)[0] <= 1e-6 * 1.01
+    assert np.linalg.norm(a - d) / np.linalg.norm(d) < 1e-3
+
+
+def test_batch_equals_single(ctx, table):
+    """Each right-hand side of a batched solve equals its single-RHS solve to
+    the solve tolerance."""
+    dims, npml, f, h = (48, 40, 36), 6, 6.0, 25.0
+    c = synth.random_field_model(dims, h, seed=9)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    src = [(12, 20, 8), (24, 20, 8), (36, 20, 8)]
+    ub, stb = op.solve(src, tol=1e-8)
+    assert stb["converged"] == 1
+    for k, s in enumerate(src):
+        us, sts = op.solve([s], tol=1e-8)
+        assert sts["converged"] == 1
+        a, b = ub[k].cpu().numpy(), us[0].cpu().numpy()
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5
+
+
+def test_solve_is_deterministic(ctx, table):
+    dims, npml, f, h = (30, 28, 26), 5, 6.0, 25.0
+    c = synth.random_field_model(dims, h, seed=2)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    u1, _ = op.solve([(15, 14, 8)], tol=1e-7)
+    u2, _ = op.solve([(15, 14, 8)], tol=1e-7)
+    assert torch.equal(u1, u2)
+
+
+def test_solve_error_paths(ctx, table):
+    from paper_2108_08730_amd import _lib as L
+    dims, npml, f, h = (20, 20, 20), 4, 6.0, 25.0
+    c = synth.homogeneous(dims, 2000.0)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    with pytest.raises(L.Helm27Error) as e:
+        op.solve([(2, 10, 10)])          # inside the PML
+    assert e.value.status == L.ERANGE
+    with pytest.raises(L.Helm27Error) as e:
+        op.solve([(10, 10, 25)])         # outside the grid
+    assert e.value.status == L.ERANGE
+    with pytest.raises(L.Helm27Error) as e:
+        op.solve([(10, 10, 10)], amps=[complex(float("nan"), 0)])
+    assert e.value.status == L.ENUMERIC
+    with pytest.raises(L.Helm27Error) as e:
+        op.solve([(10, 10, 10)], restart=0)
+    assert e.value.status == L.EINVAL
+    u, st = op.solve([(10, 10, 10)], tol=1e-10, max_inner=1, max_outer=1)
+    assert st["status"] == L.ENOCONV and st["converged"] == 0
