@@ -207,7 +207,7 @@ typedef struct {
     double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 1) */
     int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
     double mg_omega;     /* Jacobi damping (default 0.6) */
-    int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 20) */
+    int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 5) */
     int    use_graph;    /* capture the Arnoldi steps in hipGraphs (default 0) */
     int    verbose;
     double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0.5) */

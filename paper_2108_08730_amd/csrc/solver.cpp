@@ -474,7 +474,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->mg_pre = 2;
     o->mg_post = 2;
     o->mg_omega = 0.6;
-    o->mg_coarse_sweeps = 20;
+    o->mg_coarse_sweeps = 5;
     o->use_graph = 0;
     o->verbose = 0;
 }
