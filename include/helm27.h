@@ -239,6 +239,57 @@ int helm27_solve(helm27_op* op, const double* src, void* u, int nrhs,
 int helm27_solve_rhs(helm27_op* op, const void* b, void* u, int nrhs,
                      const helm27_solve_opts* opts, helm27_solve_stats* stats, void* stream);
 
+/* ---- serving ----------------------------------------------------------------
+ * A request loop on the context: requests (a velocity model, a frequency, point
+ * sources) arrive at any time; each is admitted when a slot is free and its
+ * estimated device footprint (operator + multigrid hierarchy + Krylov
+ * workspace) fits in the context's HBM budget next to the requests already
+ * running.  Admitted requests run concurrently, each on its own HIP stream, so
+ * their kernels overlap on the device; all right-hand sides of a request are
+ * solved together by the multi-RHS kernels.  Operators and their multigrid
+ * hierarchies stay resident in a cache keyed by (model_key, grid, h, f, PML)
+ * for later requests on the same model.  Timestamps are seconds on the host's
+ * steady clock. */
+typedef struct {
+    int    max_slots;            /* requests running at once (default 4) */
+    helm27_solve_opts solve;     /* solver options of every request */
+    double table_gmin, table_gmax, table_dg, table_lambda;   /* table built at start (2.5, 60, 0.05, 1e-3) */
+    int    max_cached_ops;       /* resident operators kept for reuse (default 8) */
+} helm27_serve_opts;
+
+typedef struct {
+    const float*  vel;           /* [nz][ny][nx] float32, host or device; copied at submit */
+    int           nx, ny, nz;
+    double        h, freq;
+    helm27_pml    pml;
+    const double* src;           /* host [nrhs][5] (i, j, k, amp_re, amp_im); copied at submit */
+    int           nrhs;
+    uint64_t      model_key;     /* same key = same velocity model (0: never reuse) */
+    void*         out;           /* device [nrhs][N] complex128, caller-owned, written at completion */
+} helm27_request;
+
+typedef struct {
+    int    status;               /* HELM27_OK / ENOCONV / ... of the solve */
+    helm27_solve_stats stats;
+    double t_submit, t_start, t_done;
+} helm27_result;
+
+void helm27_serve_opts_default(helm27_serve_opts* opts);
+/* Start the loop (builds the weight table once).  Errors: EINVAL (already
+ * started, bad options), ENOMEM. */
+int helm27_serve_start(helm27_ctx* ctx, const helm27_serve_opts* opts);
+/* Queue a request; returns a ticket.  Errors: EINVAL (bad request or not
+ * started), EADMIT (the request alone exceeds the HBM budget), ERANGE (a
+ * source outside the grid or in the PML). */
+int helm27_serve_submit(helm27_ctx* ctx, const helm27_request* req, uint64_t* ticket);
+/* Result of a ticket: HELM27_OK with *res filled when done, HELM27_EAGAIN while
+ * queued or running, HELM27_ENOTFOUND for an unknown ticket. */
+int helm27_serve_poll(helm27_ctx* ctx, uint64_t ticket, helm27_result* res);
+/* Block until the ticket is done or timeout_s elapses (EAGAIN). */
+int helm27_serve_wait(helm27_ctx* ctx, uint64_t ticket, helm27_result* res, double timeout_s);
+/* Finish every submitted request, then stop the workers and free the cache. */
+int helm27_serve_stop(helm27_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

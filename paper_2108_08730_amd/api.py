@@ -244,3 +244,87 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Request loop over a context (helm27_serve_*): submit solves at any time,
+    poll or wait for their results."""
+
+    def __init__(self, ctx: Context, max_slots=4, table=(2.5, 60.0, 0.05, 1e-3), max_cached_ops=8, **solve):
+        o = L.ServeOpts()
+        L.lib.helm27_serve_opts_default(C.byref(o))
+        o.max_slots = max_slots
+        o.table_gmin, o.table_gmax, o.table_dg, o.table_lambda = table
+        o.max_cached_ops = max_cached_ops
+        so = solve_opts(**solve)
+        o.solve = so
+        self._ctx = ctx
+        self._keep = {}
+        L.check(L.lib.helm27_serve_start(ctx.handle, C.byref(o)), "serve_start")
+        self._running = True
+
+    def submit(self, vel, h, freq, sources, amps=None, npml=8, R=1e-3, c_ref=0.0, model_key=0, out=None):
+        """vel: numpy float32 [nz, ny, nx] or device tensor; returns (ticket,
+        out tensor [nrhs, N] complex128 that receives the solution)."""
+        torch = _torch()
+        if hasattr(vel, "data_ptr"):
+            nz, ny, nx = vel.shape
+            vptr = C.cast(C.c_void_p(vel.data_ptr()), C.POINTER(C.c_float))
+        else:
+            vel = np.ascontiguousarray(vel, dtype=np.float32)
+            nz, ny, nx = vel.shape
+            vptr = vel.ctypes.data_as(C.POINTER(C.c_float))
+        n = len(sources)
+        src = np.zeros((n, 5), np.float64)
+        for s, p in enumerate(sources):
+            src[s, :3] = p
+            a = 1.0 if amps is None else amps[s]
+            src[s, 3], src[s, 4] = np.real(a), np.imag(a)
+        if out is None:
+            out = torch.empty((n, nx * ny * nz), dtype=torch.complex128, device="cuda")
+        if np.isscalar(npml):
+            npml = (int(npml),) * 3
+        req = L.Request()
+        req.vel = vptr
+        req.nx, req.ny, req.nz = nx, ny, nz
+        req.h, req.freq = h, freq
+        req.pml = L.Pml((C.c_int * 3)(*npml), R, c_ref)
+        req.src = src.ctypes.data_as(C.POINTER(C.c_double))
+        req.nrhs = n
+        req.model_key = model_key
+        req.out = C.c_void_p(out.data_ptr())
+        t = C.c_uint64()
+        L.check(L.lib.helm27_serve_submit(self._ctx.handle, C.byref(req), C.byref(t)), "serve_submit")
+        self._keep[t.value] = out
+        return t.value, out
+
+    @staticmethod
+    def _res(r):
+        d = {f: getattr(r, f) for f, _ in L.Result._fields_ if f != "stats"}
+        d.update({f: getattr(r.stats, f) for f, _ in L.SolveStats._fields_})
+        return d
+
+    def poll(self, ticket):
+        r = L.Result()
+        st = L.lib.helm27_serve_poll(self._ctx.handle, ticket, C.byref(r))
+        if st == L.EAGAIN:
+            return None
+        L.check(st, "serve_poll")
+        return self._res(r)
+
+    def wait(self, ticket, timeout=600.0):
+        r = L.Result()
+        L.check(L.lib.helm27_serve_wait(self._ctx.handle, ticket, C.byref(r), timeout), "serve_wait")
+        return self._res(r)
+
+    def stop(self):
+        if self._running:
+            L.check(L.lib.helm27_serve_stop(self._ctx.handle), "serve_stop")
+            self._running = False
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

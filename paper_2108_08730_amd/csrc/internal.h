@@ -140,6 +140,12 @@ void complete_weights(const double w5[5], double w7[7]);
 int op_build(helm27_ctx* ctx, const double* w7, int n_g, double g_min, double dg,
              const float* vel, int nx, int ny, int nz, double h, double freq, double omega_shift,
              const helm27_pml* pml, int flags, helm27_op** out);
+int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, int ny, int nz, double h,
+              double freq, const helm27_pml* pml, int flags, hipStream_t stream, helm27_op** out);
+// solver.cpp: drop the solver's Krylov workspace (keeps the multigrid hierarchy)
+void solver_trim(helm27_op* op);
+// device bytes a solve of nrhs right-hand sides would allocate (estimate)
+size_t solve_footprint(int64_t N, int nrhs, int restart, int precision, int levels);
 void make_tiling(int nx, int ny, const int plain_lo[2], const int plain_hi[2], Tiling* t, int zchunk, int nz);
 void axis_nodes(int n, double h, double x_lo, double x_hi, double L, double omega, double c_ref, double R,
                 std::vector<AxisNode<double>>* out);

@@ -255,8 +255,10 @@ static bool is_device_ptr(const void* p) {
     return attr.type == hipMemoryTypeDevice;
 }
 
-extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, int ny, int nz,
-                               double h, double freq, const helm27_pml* pml, int flags, helm27_op** out) {
+namespace h27 {
+// Assembly on a given stream (the serving workers use their own streams).
+int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, int ny, int nz, double h,
+              double freq, const helm27_pml* pml, int flags, hipStream_t stream, helm27_op** out) {
     if (!ctx || !t || !vel || !out) return HELM27_EINVAL;
     if (nx < 3 || ny < 3 || nz < 3 || !(h > 0) || !(freq > 0)) return HELM27_EINVAL;
     const int wmode = flags & 0x3;
@@ -273,7 +275,12 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
     const int64_t N = static_cast<int64_t>(nx) * ny * nz;
     std::vector<float> hc(N);
     const bool dev = is_device_ptr(vel);
-    H27_CHECK_HIP(hipMemcpy(hc.data(), vel, N * sizeof(float), dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    if (dev) {
+        H27_CHECK_HIP(hipMemcpyAsync(hc.data(), vel, N * sizeof(float), hipMemcpyDeviceToHost, stream));
+        H27_CHECK_HIP(hipStreamSynchronize(stream));
+    } else {
+        std::memcpy(hc.data(), vel, N * sizeof(float));
+    }
     float cmin = std::numeric_limits<float>::infinity(), cmax = 0.0f;
     for (int64_t i = 0; i < N; ++i) {
         const float v = hc[i];
@@ -317,14 +324,16 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
     if (hipMalloc(&g.d_c, N * sizeof(float)) != hipSuccess) return fail(HELM27_ENOMEM);
     if (hipMalloc(&g.d_idx, N * sizeof(uint16_t)) != hipSuccess) return fail(HELM27_ENOMEM);
     g.bytes += N * (sizeof(float) + sizeof(uint16_t));
-    if (hipMemcpy(g.d_c, hc.data(), N * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpyAsync(g.d_c, hc.data(), N * sizeof(float), hipMemcpyHostToDevice, stream) != hipSuccess)
         return fail(HELM27_EDEVICE);
     if (hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)) != hipSuccess) return fail(HELM27_ENOMEM);
-    if (hipMemset(d_cnt, 0, 2 * sizeof(unsigned long long)) != hipSuccess) return fail(HELM27_EDEVICE);
-    if ((st = launch_select_index(g.d_c, g.d_idx, N, fh, t->g_min, t->dg, t->n_g, d_cnt, nullptr)))
+    if (hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess) return fail(HELM27_EDEVICE);
+    if ((st = launch_select_index(g.d_c, g.d_idx, N, fh, t->g_min, t->dg, t->n_g, d_cnt, stream)))
         return fail(st);
     unsigned long long cnt[2] = {0, 0};
-    if (hipMemcpy(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess) return fail(HELM27_EDEVICE);
+    if (hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return fail(HELM27_EDEVICE);
     hipFree(d_cnt);
     d_cnt = nullptr;
     if (cnt[1] != 0) return fail(HELM27_EINVAL);
@@ -338,22 +347,28 @@ extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const flo
         if (hipMalloc(&g.d_row_f, N * sizeof(EntryCoef<float>)) != hipSuccess) return fail(HELM27_ENOMEM);
         if (hipMalloc(&g.d_row_d, N * sizeof(EntryCoef<double>)) != hipSuccess) return fail(HELM27_ENOMEM);
         g.bytes += N * (sizeof(EntryCoef<float>) + sizeof(EntryCoef<double>));
-        if ((st = launch_gam_average<float>(g, g.d_row_f, nullptr))) return fail(st);
-        if ((st = launch_gam_average<double>(g, g.d_row_d, nullptr))) return fail(st);
+        if ((st = launch_gam_average<float>(g, g.d_row_f, stream))) return fail(st);
+        if ((st = launch_gam_average<double>(g, g.d_row_d, stream))) return fail(st);
     }
     if (flags & HELM27_STORE_C64) {
         if (hipMalloc(&op->d_coef_f, 27 * N * sizeof(float2)) != hipSuccess) return fail(HELM27_ENOMEM);
         g.bytes += 27 * N * sizeof(float2);
-        if ((st = launch_fill_stored<float>(g, op->d_coef_f, 1.0, 0.0, nullptr))) return fail(st);
+        if ((st = launch_fill_stored<float>(g, op->d_coef_f, 1.0, 0.0, stream))) return fail(st);
     }
     if (flags & HELM27_STORE_C128) {
         if (hipMalloc(&op->d_coef_d, 27 * N * sizeof(double2)) != hipSuccess) return fail(HELM27_ENOMEM);
         g.bytes += 27 * N * sizeof(double2);
-        if ((st = launch_fill_stored<double>(g, op->d_coef_d, 1.0, 0.0, nullptr))) return fail(st);
+        if ((st = launch_fill_stored<double>(g, op->d_coef_d, 1.0, 0.0, stream))) return fail(st);
     }
-    if (hipDeviceSynchronize() != hipSuccess) return fail(HELM27_EDEVICE);
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(HELM27_EDEVICE);
     *out = op;
     return HELM27_OK;
+}
+}  // namespace h27
+
+extern "C" int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, int ny, int nz,
+                               double h, double freq, const helm27_pml* pml, int flags, helm27_op** out) {
+    return h27::op_create(ctx, t, vel, nx, ny, nz, h, freq, pml, flags, nullptr, out);
 }
 
 void solver_free(helm27_op* op);  // solver.cpp

@@ -58,6 +58,7 @@ struct SolverState {
     int64_t* d_lin = nullptr;
     double2* d_amp = nullptr;
     int src_cap = 0;
+    double2* d_b = nullptr;          // point-source right-hand sides [src_cap][N]
 };
 
 static void free_workspace(SolverState* S) {
@@ -86,7 +87,7 @@ static int alloc(SolverState* S, void** p, size_t bytes) {
 }
 
 // Coarse grids: node i of level l+1 sits on node 2i of level l.
-static int build_hierarchy(helm27_op* op, SolverState* S, int levels) {
+static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_t s) {
     free_hierarchy(S);
     const GridOp* prev = &op->g;
     unsigned long long* d_cnt = nullptr;
@@ -118,21 +119,21 @@ static int build_hierarchy(helm27_op* op, SolverState* S, int levels) {
             break;
         }
         c.bytes += c.N * (sizeof(float) + sizeof(uint16_t));
-        if ((st = inject_velocity(prev->d_c, prev->nx, prev->ny, c.d_c, cx, cy, cz, nullptr))) break;
+        if ((st = inject_velocity(prev->d_c, prev->nx, prev->ny, c.d_c, cx, cy, cz, s))) break;
         const double fh = op->freq * c.h;
-        if (hipMemset(d_cnt, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), s) != hipSuccess) {
             st = HELM27_EDEVICE;
             break;
         }
         const int n_g = op->g.n_g;
-        if ((st = launch_select_index(c.d_c, c.d_idx, c.N, fh, op->table_gmin, op->table_dg, n_g, d_cnt, nullptr))) break;
+        if ((st = launch_select_index(c.d_c, c.d_idx, c.N, fh, op->table_gmin, op->table_dg, n_g, d_cnt, s))) break;
         if ((st = grid_setup(&c, op->w7.data(), n_g, op->g.fixed))) break;
         c.idx_lo = host_index(op->cmin, fh, op->table_gmin, op->table_dg, n_g);
         c.idx_hi = host_index(op->cmax, fh, op->table_gmin, op->table_dg, n_g);
         prev = &c;
     }
+    if (hipStreamSynchronize(s) != hipSuccess && st == HELM27_OK) st = HELM27_EDEVICE;
     hipFree(d_cnt);
-    if (hipDeviceSynchronize() != hipSuccess && st == HELM27_OK) st = HELM27_EDEVICE;
     S->levels = 1 + static_cast<int>(S->coarse.size());
     return st;
 }
@@ -378,7 +379,7 @@ static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, con
         free_workspace(S);
         free_hierarchy(S);
         if (want_levels > 0) {
-            const int st = build_hierarchy(op, S, want_levels);
+            const int st = build_hierarchy(op, S, want_levels, s);
             if (st) return st;
         }
         S->req_levels = want_levels;
@@ -456,6 +457,7 @@ void solver_free(helm27_op* op) {
     free_hierarchy(S);
     hipFree(S->d_lin);
     hipFree(S->d_amp);
+    hipFree(S->d_b);
     delete S;
     op->solver = nullptr;
 }
@@ -537,15 +539,18 @@ extern "C" int helm27_solve(helm27_op* op, const double* src, void* u, int nrhs,
     if (S->src_cap < nrhs) {
         hipFree(S->d_lin);
         hipFree(S->d_amp);
+        hipFree(S->d_b);
         S->d_lin = nullptr;
         S->d_amp = nullptr;
+        S->d_b = nullptr;
+        S->src_cap = 0;
         if (hipMalloc(&S->d_lin, nrhs * sizeof(int64_t)) != hipSuccess ||
-            hipMalloc(&S->d_amp, nrhs * sizeof(double2)) != hipSuccess)
+            hipMalloc(&S->d_amp, nrhs * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&S->d_b, static_cast<size_t>(G.N) * nrhs * sizeof(double2)) != hipSuccess)
             return HELM27_ENOMEM;
         S->src_cap = nrhs;
     }
-    double2* b = nullptr;
-    if (hipMalloc(&b, static_cast<size_t>(G.N) * nrhs * sizeof(double2)) != hipSuccess) return HELM27_ENOMEM;
+    double2* b = S->d_b;
     int st = HELM27_OK;
     if (hipMemcpyAsync(S->d_lin, lin.data(), nrhs * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(S->d_amp, amp.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, s) != hipSuccess)
@@ -553,7 +558,31 @@ extern "C" int helm27_solve(helm27_op* op, const double* src, void* u, int nrhs,
     if (!st) st = fill_zero(b, G.N * nrhs * static_cast<int64_t>(sizeof(double2)), s);
     if (!st) st = inject_sources(b, G.N, S->d_lin, S->d_amp, nrhs, G.h, s);
     if (!st) st = helm27_solve_rhs(op, b, u, nrhs, opts, stats, stream);
-    hipStreamSynchronize(s);
-    hipFree(b);
+    else hipStreamSynchronize(s);
     return st;
+}
+
+void h27::solver_trim(helm27_op* op) {
+    if (!op || !op->solver) return;
+    SolverState* S = static_cast<SolverState*>(op->solver);
+    free_workspace(S);
+    hipFree(S->d_lin);
+    hipFree(S->d_amp);
+    hipFree(S->d_b);
+    S->d_lin = nullptr;
+    S->d_amp = nullptr;
+    S->d_b = nullptr;
+    S->src_cap = 0;
+}
+
+size_t h27::solve_footprint(int64_t N, int nrhs, int restart, int precision, int levels) {
+    const double e = precision == HELM27_C128 ? 16.0 : 8.0;   // complex element bytes, inner precision
+    const double n = static_cast<double>(N) * nrhs;
+    double bytes = n * e * (restart + 1 + 4);                   // Krylov basis, w, e, rin, tmp
+    double lv = 0, f = 1;
+    for (int l = 0; l < levels; ++l, f /= 8) lv += f * (l == 0 ? 3 : 4);
+    bytes += n * e * lv;                                        // multigrid vectors
+    bytes += n * 16.0 * 2;                                      // FP64 residual and right-hand side
+    bytes += static_cast<double>(N) * 7.0;                      // coarse grids (velocity + index + ...)
+    return static_cast<size_t>(bytes * 1.05) + (16u << 20);
 }
