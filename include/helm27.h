@@ -193,6 +193,11 @@ int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave);
 int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows);
+/* Kernel family of the recompute stencil: 0 = one wavefront per tile, box and
+ * PML frame in one launch (default); 1 = LDS-tiled blocks (one block per
+ * 64 x 8 or 16 x 16 column tile).  Both compute the same operator.
+ * Errors: EINVAL. */
+int helm27_set_kernel_variant(helm27_op* op, int variant);
 
 /* ---- (c) solve ------------------------------------------------------------ */
 typedef struct {

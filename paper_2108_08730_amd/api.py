@@ -118,6 +118,9 @@ class Operator:
         dt = L.C64 if dtype in ("c64", L.C64) else L.C128
         L.check(L.lib.helm27_set_tuning(self._h, dt, rows_per_wave), "set_tuning")
 
+    def set_kernel_variant(self, variant):
+        L.check(L.lib.helm27_set_kernel_variant(self._h, variant), "set_kernel_variant")
+
     def tune(self, nrhs=1, dtype="c64", stream=None):
         dt = L.C64 if dtype in ("c64", L.C64) else L.C128
         best = C.c_int()

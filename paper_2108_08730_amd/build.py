@@ -35,7 +35,7 @@ EXTRA = {
 }
 SOURCES = [
     "table.cpp", "op.cpp", "solver.cpp", "serve.cpp",
-    "kernels_assemble.hip", "kernels_stencil.hip", "kernels_plain.hip", "kernels_krylov.hip",
+    "kernels_assemble.hip", "kernels_stencil.hip", "kernels_wave.hip", "kernels_krylov.hip",
 ]
 
 

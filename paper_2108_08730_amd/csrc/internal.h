@@ -105,7 +105,8 @@ struct GridOp {
     AxisNode<float>* d_ax_f[3] = {nullptr, nullptr, nullptr};
     AxisNode<double>* d_ax_d[3] = {nullptr, nullptr, nullptr};
     Tiling tiling;
-    int plain_ry[2] = {2, 1};                  // plain-kernel rows per wave: [fp32, fp64] (1..4)
+    int plain_ry[2] = {2, 1};                  // box rows per wavefront: [fp32, fp64] (1..4)
+    int kernel_variant = 0;                    // 0: wavefront-per-tile kernel, 1: LDS-tiled kernel
     void* d_sink = nullptr;                    // 64 x 16 B target of masked-off lanes' stores
     size_t bytes = 0;
 };

@@ -423,47 +423,63 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     a.fstart[4] = acc;
     a.n_plain_blocks = t.n_plain_blocks;
     a.zchunk = t.zchunk;
-    // The plain box goes to the wavefront-per-tile kernel when it can: table
-    // rows (not per-row averaged entries), a table slice that fits in LDS and
-    // 32-bit byte offsets for the buffer stores.
-    const int64_t vbytes = g.N * static_cast<int64_t>(sizeof(typename V2<R>::T));
-    const int n_tab = g.fixed ? 1 : g.idx_hi - g.idx_lo + 1;
-    (void)vbytes;
-    const bool use_plain = t.n_plain_blocks > 0 && !a.g.rowcoef && g.d_sink &&
-                           n_tab > 0 && static_cast<size_t>(n_tab) * 8 * sizeof(R) <= 64 * 1024;
-    if (use_plain) {
-        PlainArgs<R> p{};
-        p.g = a.g;
-        p.px0 = t.plain_x0; p.py0 = t.plain_y0; p.pw = t.plain_w; p.ph = t.plain_h;
-        const int RY = g.plain_ry[sizeof(R) == 8 ? 1 : 0];
-        p.ntx = (p.pw + kWaveCols - 1) / kWaveCols;
-        p.nty = (p.ph + RY - 1) / RY;
-        const int64_t tiles = static_cast<int64_t>(p.ntx) * p.nty * nrhs;
-        int64_t nzc = (4096 + tiles - 1) / tiles;
-        int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
-        zc = std::max(2, std::min(32, zc));
-        p.zchunk = std::min(zc, g.nz);
-        p.nzc = (g.nz + p.zchunk - 1) / p.zchunk;
-        p.nrhs = nrhs;
-        const int64_t items = tiles * p.nzc;
-        if (items > (int64_t(1) << 30)) return HELM27_EINVAL;
-        p.n_items = static_cast<int>(items);
-        p.tab_lo = g.fixed ? 0 : g.idx_lo;
-        p.n_tab = n_tab;
-        p.u = static_cast<const typename V2<R>::T*>(u);
-        p.y = static_cast<typename V2<R>::T*>(y);
-        p.b = static_cast<const typename V2<R>::T*>(b);
-        p.sink = static_cast<typename V2<R>::T*>(g.d_sink);
-        p.omega_j = static_cast<R>(omega_j);
-        const int st = launch_plain<R>(p, mode, shifted, RY, s);
-        if (st) return st;
-        a.n_plain_blocks = 0;
-    }
     a.nrhs = nrhs;
     a.u = static_cast<const typename V2<R>::T*>(u);
     a.y = static_cast<typename V2<R>::T*>(y);
     a.b = static_cast<const typename V2<R>::T*>(b);
     a.omega_j = static_cast<R>(omega_j);
+    // Default: the wavefront-per-tile kernel for the whole grid (box + frame
+    // work items in one launch).  Variant 1 keeps the LDS-tiled kernel below.
+    const int n_tab = g.fixed ? 1 : g.idx_hi - g.idx_lo + 1;
+    const bool use_wave = g.kernel_variant == 0 && g.d_sink && n_tab > 0 &&
+                          (a.g.rowcoef || static_cast<size_t>(n_tab) * 8 * sizeof(R) <= 64 * 1024);
+    if (use_wave) {
+        WaveArgs<R> w{};
+        w.g = a.g;
+        const int RY = g.plain_ry[sizeof(R) == 8 ? 1 : 0];
+        const int RQ = frame_rows<R>();
+        w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
+        w.ntx = w.pw > 0 ? (w.pw + kWaveCols - 1) / kWaveCols : 0;
+        w.nty = w.ph > 0 ? (w.ph + RY - 1) / RY : 0;
+        w.n_plain = w.ntx * w.nty;
+        int accf = 0;
+        for (int k = 0; k < 4; ++k) {
+            const Rect& r = t.frame[k];
+            w.fx0[k] = r.x0; w.fy0[k] = r.y0; w.fw[k] = r.w; w.fh[k] = r.h;
+            // lanes always run along x: whole-wave groups (62 columns) for strips
+            // spanning x (bottom / top, or the whole grid), 16-lane groups (14
+            // columns, 4 groups stacked along y) for the narrow left / right strips
+            const bool wide = !(k >= 2 && t.plain_w > 0);
+            w.flx[k] = wide ? 1 : 0;
+            const int cols = wide ? kWaveCols : 14, rows = wide ? RQ : 4 * RQ;
+            const bool empty = r.w <= 0 || r.h <= 0;
+            w.fnl[k] = empty ? 1 : (r.w + cols - 1) / cols;
+            w.fnq[k] = empty ? 0 : (r.h + rows - 1) / rows;
+            w.fstart[k] = accf;
+            accf += empty ? 0 : w.fnl[k] * w.fnq[k];
+        }
+        w.fstart[4] = accf;
+        w.n_frame = accf;
+        const int64_t tiles = static_cast<int64_t>(w.n_plain + w.n_frame) * nrhs;
+        if (tiles <= 0) return HELM27_OK;
+        int64_t nzc = (4096 + tiles - 1) / tiles;
+        int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
+        zc = std::max(2, std::min(32, zc));
+        w.zchunk = std::min(zc, g.nz);
+        w.nzc = (g.nz + w.zchunk - 1) / w.zchunk;
+        w.nrhs = nrhs;
+        const int64_t items = tiles * w.nzc;
+        if (items > (int64_t(1) << 30)) return HELM27_EINVAL;
+        w.n_items = static_cast<int>(items);
+        w.tab_lo = g.fixed ? 0 : g.idx_lo;
+        w.n_tab = n_tab;
+        w.u = a.u;
+        w.y = a.y;
+        w.b = a.b;
+        w.sink = static_cast<typename V2<R>::T*>(g.d_sink);
+        w.omega_j = a.omega_j;
+        return launch_wave<R>(w, mode, shifted, RY, RQ, s);
+    }
     const int nblk = a.n_plain_blocks + t.n_frame_blocks;
     if (nblk == 0) return HELM27_OK;
     const int per_rhs = nblk * t.n_zchunks;

@@ -515,3 +515,9 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
     hipFree(y);
     return st;
 }
+
+extern "C" int helm27_set_kernel_variant(helm27_op* op, int variant) {
+    if (!op || variant < 0 || variant > 1) return HELM27_EINVAL;
+    op->g.kernel_variant = variant;
+    return HELM27_OK;
+}

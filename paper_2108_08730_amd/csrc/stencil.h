@@ -48,14 +48,21 @@ struct StencilArgs {
 };
 
 
-// Arguments of the plain-box kernel (one wavefront per tile of 62 output
-// columns x RY rows x zchunk planes; table slice staged in LDS).
+// Arguments of the wavefront-per-tile kernel: one wavefront per work item
+// (a tile of 62 output columns along its lane axis x RY or RQ rows along the
+// other in-plane axis x a z chunk x one right-hand side).  Work items are the
+// PML-frame tiles (general complex formula) followed by the unstretched-box
+// tiles (lanes along x); the weight-table slice is staged in LDS per block.
 template <typename R>
-struct PlainArgs {
+struct WaveArgs {
     GridData<R> g;
-    int px0, py0, pw, ph;          // plain box
-    int ntx, nty, nzc, zchunk;     // tiles along x, y, z chunks
-    int nrhs, n_items;             // work items = ntx * nty * nzc * nrhs
+    int px0, py0, pw, ph;          // unstretched box
+    int ntx, nty, n_plain;         // box tiles along x (62 columns) and y (RY rows)
+    int fx0[4], fy0[4], fw[4], fh[4];   // frame rectangles
+    int flx[4];                    // 1: lane groups of 64 (62 columns), 0: groups of 16 (14 columns)
+    int fnl[4], fnq[4];            // tiles along x and along y
+    int fstart[5], n_frame;        // prefix sums of frame tiles
+    int nzc, zchunk, nrhs, n_items;
     int tab_lo, n_tab;             // table slice [tab_lo, tab_lo + n_tab)
     const typename V2<R>::T* u;
     typename V2<R>::T* y;
@@ -66,6 +73,12 @@ struct PlainArgs {
 
 constexpr int kWaveCols = 62;      // output columns per wavefront (lanes 1..62)
 
-template <typename R> int launch_plain(const PlainArgs<R>& a, int mode, bool shifted, int ry, hipStream_t s);
+// which work items a launch covers
+enum WaveWhich { WAVE_BOTH = 0, WAVE_PLAIN = 1, WAVE_FRAME = 2 };
+
+template <typename R>
+int launch_wave(const WaveArgs<R>& a, int mode, bool shifted, int ry, int rq, hipStream_t s);
+template <typename R>
+int frame_rows();
 
 }  // namespace h27
