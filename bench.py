@@ -131,6 +131,13 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 
+    # calibration for hardware byte counters: a plain device copy of known size
+    calib = torch.empty(16 << 20, dtype=torch.float32, device="cuda")
+    calib_dst = torch.empty_like(calib)
+    for _ in range(3):
+        calib_dst.copy_(calib)
+    torch.cuda.synchronize()
+
     # apply roofline on the workload's operator (launch shape of the solve's matvec)
     tab = ctx.build_table(gmin, gmax, dg, lam)
     op = ctx.assemble(tab, c_dev, h, f, npml=npml)
