@@ -63,6 +63,28 @@ def apply_timing(op, torch, nrhs=1, reps=200, dtype=None):
     return sec, alg_bytes
 
 
+def apply_only(args, torch, api, synth):
+    """FP32 recompute apply on a large grid (working set well beyond the 256 MB
+    MALL): seeded random-field model, h = 25 m, f = 10 Hz, 8-node PML."""
+    dims = tuple(int(v) for v in args.grid.split(","))
+    h, f, npml = 25.0, 10.0, 8
+    c = synth.random_field_model(dims, h, seed=3)
+    ctx = api.Context(0)
+    tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
+    op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, f, npml=npml)
+    calib = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    calib_dst = torch.empty_like(calib)
+    for _ in range(3):
+        calib_dst.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib_dst
+    sec, alg = apply_timing(op, torch, nrhs=args.nrhs, reps=args.apply_reps)
+    achieved = alg / sec / 1e9
+    print(json.dumps({"grid": dims, "nrhs": args.nrhs, "apply_us": sec * 1e6,
+                      "gpts": op.N * args.nrhs / sec / 1e9, "alg_bytes": alg,
+                      "GBs": achieved, "frac": achieved / HBM_PEAK_GBS}), flush=True)
+
+
 def cpu_baseline(c, W7, seconds=10.0):
     """The oracle (scipy CSR, FP64) on the host: assemble the same operator
     once, then repeat the SpMV y = A u for about `seconds`."""
@@ -93,6 +115,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--apply-reps", type=int, default=200)
+    ap.add_argument("--apply-only", action="store_true",
+                    help="time only the FP32 apply on --grid (seeded random-field model, h=25 m, f=10 Hz, 8-node PML)")
+    ap.add_argument("--grid", type=str, default="400,400,200")
+    ap.add_argument("--nrhs", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded path is a design "
@@ -103,6 +129,10 @@ def main():
     import torch
     from paper_2108_08730_amd import api
     import synth
+
+    if args.apply_only:
+        apply_only(args, torch, api, synth)
+        return
 
     wl = WORKLOAD
     dims, h, f, npml = wl["dims"], wl["h"], wl["freq"], wl["npml"]

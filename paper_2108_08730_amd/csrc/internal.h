@@ -107,7 +107,6 @@ struct GridOp {
     Tiling tiling;
     int plain_ry[2] = {2, 1};                  // box rows per wavefront: [fp32, fp64] (1..4)
     int kernel_variant = 0;                    // 0: wavefront-per-tile kernel, 1: LDS-tiled kernel
-    void* d_sink = nullptr;                    // 64 x 16 B target of masked-off lanes' stores
     size_t bytes = 0;
 };
 

@@ -430,9 +430,9 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     a.omega_j = static_cast<R>(omega_j);
     // Default: the wavefront-per-tile kernel for the whole grid (box + frame
     // work items in one launch).  Variant 1 keeps the LDS-tiled kernel below.
-    const int n_tab = g.fixed ? 1 : g.idx_hi - g.idx_lo + 1;
-    const bool use_wave = g.kernel_variant == 0 && g.d_sink && n_tab > 0 &&
-                          (a.g.rowcoef || static_cast<size_t>(n_tab) * 8 * sizeof(R) <= 64 * 1024);
+    const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
+    const bool use_wave = g.kernel_variant == 0 && n_tab > 0 &&
+                          wave_lds_bytes(a.g.rowcoef ? 0 : n_tab, g.nz, sizeof(R) == 8) <= 64 * 1024;
     if (use_wave) {
         WaveArgs<R> w{};
         w.g = a.g;
@@ -471,12 +471,11 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         const int64_t items = tiles * w.nzc;
         if (items > (int64_t(1) << 30)) return HELM27_EINVAL;
         w.n_items = static_cast<int>(items);
-        w.tab_lo = g.fixed ? 0 : g.idx_lo;
+        w.tab_lo = g.idx_lo;
         w.n_tab = n_tab;
         w.u = a.u;
         w.y = a.y;
         w.b = a.b;
-        w.sink = static_cast<typename V2<R>::T*>(g.d_sink);
         w.omega_j = a.omega_j;
         return launch_wave<R>(w, mode, shifted, RY, RQ, s);
     }

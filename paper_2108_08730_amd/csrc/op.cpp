@@ -115,7 +115,6 @@ void grid_free(GridOp* g) {
     hipFree(g->d_entry_d);
     hipFree(g->d_row_f);
     hipFree(g->d_row_d);
-    hipFree(g->d_sink);
     for (int a = 0; a < 3; ++a) {
         hipFree(g->d_ax_f[a]);
         hipFree(g->d_ax_d[a]);
@@ -196,8 +195,6 @@ int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
         plain_range(nd, &lo[a], &hi[a]);
     }
     make_tiling(g->nx, g->ny, lo, hi, &g->tiling, 0, g->nz);
-    if (hipMalloc(&g->d_sink, 64 * 16) != hipSuccess) return HELM27_ENOMEM;
-    g->bytes += 64 * 16;
     return HELM27_OK;
 }
 

@@ -67,7 +67,6 @@ struct WaveArgs {
     const typename V2<R>::T* u;
     typename V2<R>::T* y;
     const typename V2<R>::T* b;
-    typename V2<R>::T* sink;       // [64] store target of lanes without an output
     R omega_j;
 };
 
@@ -80,5 +79,8 @@ template <typename R>
 int launch_wave(const WaveArgs<R>& a, int mode, bool shifted, int ry, int rq, hipStream_t s);
 template <typename R>
 int frame_rows();
+// LDS bytes of the wavefront kernel: the staged weight-table slice (n_tab
+// entries; 0 with per-row coefficients) and the z-axis PML nodes
+size_t wave_lds_bytes(int n_tab, int nz, bool fp64);
 
 }  // namespace h27
