@@ -41,7 +41,7 @@ def _ensure_lib():
 
 
 def apply_timing(op, torch, nrhs=1, reps=200, dtype=None):
-    """Average duration of helm27_apply (FP32 recompute) over `reps` launches
+    """Average duration of helm27_apply (recompute) over `reps` launches
     bracketed by HIP events on the stream the kernels run on."""
     dtype = dtype or torch.complex64
     stream = torch.cuda.current_stream()
@@ -78,9 +78,10 @@ def apply_only(args, torch, api, synth):
         calib_dst.copy_(calib)
     torch.cuda.synchronize()
     del calib, calib_dst
-    sec, alg = apply_timing(op, torch, nrhs=args.nrhs, reps=args.apply_reps)
+    dt = torch.complex64 if args.apply_dtype == "c64" else torch.complex128
+    sec, alg = apply_timing(op, torch, nrhs=args.nrhs, reps=args.apply_reps, dtype=dt)
     achieved = alg / sec / 1e9
-    print(json.dumps({"grid": dims, "nrhs": args.nrhs, "apply_us": sec * 1e6,
+    print(json.dumps({"grid": dims, "nrhs": args.nrhs, "dtype": args.apply_dtype, "apply_us": sec * 1e6,
                       "gpts": op.N * args.nrhs / sec / 1e9, "alg_bytes": alg,
                       "GBs": achieved, "frac": achieved / HBM_PEAK_GBS}), flush=True)
 
@@ -119,6 +120,7 @@ def main():
                     help="time only the FP32 apply on --grid (seeded random-field model, h=25 m, f=10 Hz, 8-node PML)")
     ap.add_argument("--grid", type=str, default="400,400,200")
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--apply-dtype", choices=("c64", "c128"), default="c64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded path is a design "

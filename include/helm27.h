@@ -198,6 +198,11 @@ int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows
  * 64 x 8 or 16 x 16 column tile).  Both compute the same operator.
  * Errors: EINVAL. */
 int helm27_set_kernel_variant(helm27_op* op, int variant);
+/* z planes per work item of the wavefront kernel (each item marches its
+ * chunk of planes; two extra planes are read per chunk): 0 = automatic
+ * (about 4096 work items, 2..32 planes each), else 2..4096.  Results do not
+ * depend on it.  Errors: EINVAL. */
+int helm27_set_zchunk(helm27_op* op, int zchunk);
 
 /* ---- (c) solve ------------------------------------------------------------ */
 typedef struct {

@@ -121,6 +121,10 @@ class Operator:
     def set_kernel_variant(self, variant):
         L.check(L.lib.helm27_set_kernel_variant(self._h, variant), "set_kernel_variant")
 
+    def set_zchunk(self, zchunk):
+        """z planes per work item of the wavefront kernel (0 = automatic)."""
+        L.check(L.lib.helm27_set_zchunk(self._h, zchunk), "set_zchunk")
+
     def tune(self, nrhs=1, dtype="c64", stream=None):
         dt = L.C64 if dtype in ("c64", L.C64) else L.C128
         best = C.c_int()

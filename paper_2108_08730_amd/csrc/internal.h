@@ -107,6 +107,7 @@ struct GridOp {
     Tiling tiling;
     int plain_ry[2] = {2, 1};                  // box rows per wavefront: [fp32, fp64] (1..4)
     int kernel_variant = 0;                    // 0: wavefront-per-tile kernel, 1: LDS-tiled kernel
+    int wave_zchunk = 0;                       // z planes per wavefront work item (0: automatic)
     size_t bytes = 0;
 };
 

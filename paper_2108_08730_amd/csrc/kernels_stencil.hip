@@ -431,7 +431,10 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     // Default: the wavefront-per-tile kernel for the whole grid (box + frame
     // work items in one launch).  Variant 1 keeps the LDS-tiled kernel below.
     const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
+    // the wavefront kernel addresses one right-hand side with 32-bit buffer
+    // offsets: its byte size must stay below 2^31
     const bool use_wave = g.kernel_variant == 0 && n_tab > 0 &&
+                          static_cast<int64_t>(g.N) * static_cast<int64_t>(2 * sizeof(R)) < (int64_t(1) << 31) &&
                           wave_lds_bytes(a.g.rowcoef ? 0 : n_tab, g.nz, sizeof(R) == 8) <= 64 * 1024;
     if (use_wave) {
         WaveArgs<R> w{};
@@ -465,6 +468,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         int64_t nzc = (4096 + tiles - 1) / tiles;
         int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
         zc = std::max(2, std::min(32, zc));
+        if (g.wave_zchunk > 0) zc = g.wave_zchunk;
         w.zchunk = std::min(zc, g.nz);
         w.nzc = (g.nz + w.zchunk - 1) / w.zchunk;
         w.nrhs = nrhs;

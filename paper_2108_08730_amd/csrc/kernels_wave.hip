@@ -42,7 +42,7 @@ namespace h27 {
 // LDS copy of one table entry: s = stiffness class weights times 1/h^2,
 // m = mass class weights, b2 / b3 = unscaled beta2 / beta3 (frame formula).
 template <typename R>
-struct TabEntry {
+struct alignas(16) TabEntry {
     R s[4];
     R m[4];
     R b2, b3, pad0, pad1;
@@ -121,6 +121,78 @@ __device__ __forceinline__ Cx<R> finish(R omega_j, Cx<R> acc, Cx<R> diag, Cx<R> 
     return xcen + omega_j * (rr * inv_of(diag));
 }
 
+// ---------------------------------------------------------------------------
+// Buffer loads and stores.  Every vector access goes through a buffer resource
+// with the byte size of its array, so the hardware range check does the grid
+// boundary: a lane offset of kOff (or a plane outside the grid, whose
+// resource has size 0) reads 0 and drops the store; no lane masks, no
+// address arithmetic in the vector unit.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;          // untyped 32-bit data, range checked
+constexpr unsigned kOff = 0x80000000u;          // beyond every buffer (sizes < 2^31 bytes)
+
+__device__ __forceinline__ Rsrc rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRsrcWord3);
+}
+__device__ __forceinline__ void bld(float2& v, Rsrc r, unsigned vo, unsigned so) {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(vo), static_cast<int>(so), 0);
+    v.x = __uint_as_float(w.x);
+    v.y = __uint_as_float(w.y);
+}
+__device__ __forceinline__ void bld(double2& v, Rsrc r, unsigned vo, unsigned so) {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(vo), static_cast<int>(so), 0);
+    v.x = __hiloint2double(static_cast<int>(w.y), static_cast<int>(w.x));
+    v.y = __hiloint2double(static_cast<int>(w.w), static_cast<int>(w.z));
+}
+__device__ __forceinline__ void bst(Cx<float> v, Rsrc r, unsigned vo, unsigned so) {
+    u32x2 w;
+    w.x = __float_as_uint(v.re);
+    w.y = __float_as_uint(v.im);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(vo), static_cast<int>(so), 0);
+}
+__device__ __forceinline__ void bst(Cx<double> v, Rsrc r, unsigned vo, unsigned so) {
+    u32x4 w;
+    w.x = static_cast<unsigned>(__double2loint(v.re));
+    w.y = static_cast<unsigned>(__double2hiint(v.re));
+    w.z = static_cast<unsigned>(__double2loint(v.im));
+    w.w = static_cast<unsigned>(__double2hiint(v.im));
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, static_cast<int>(vo), static_cast<int>(so), 0);
+}
+__device__ __forceinline__ int bld_u16(Rsrc r, unsigned vo, unsigned so) {
+    return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), 0));
+}
+__device__ __forceinline__ float bld_f32(Rsrc r, unsigned vo, unsigned so) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo), static_cast<int>(so), 0));
+}
+
+// table entry reads from LDS as 16-byte loads
+__device__ __forceinline__ void tab_sm(const TabEntry<float>* t, int e, float (&s)[4], float (&m)[4]) {
+    const float4* p = reinterpret_cast<const float4*>(t + e);
+    const float4 a = p[0], b = p[1];
+    s[0] = a.x; s[1] = a.y; s[2] = a.z; s[3] = a.w;
+    m[0] = b.x; m[1] = b.y; m[2] = b.z; m[3] = b.w;
+}
+__device__ __forceinline__ void tab_sm(const TabEntry<double>* t, int e, double (&s)[4], double (&m)[4]) {
+    const double2* p = reinterpret_cast<const double2*>(t + e);
+    const double2 a = p[0], b = p[1], c = p[2], d = p[3];
+    s[0] = a.x; s[1] = a.y; s[2] = b.x; s[3] = b.y;
+    m[0] = c.x; m[1] = c.y; m[2] = d.x; m[3] = d.y;
+}
+__device__ __forceinline__ void tab_bm(const TabEntry<float>* t, int e, float& b2, float& b3, float (&m)[4]) {
+    const float4* p = reinterpret_cast<const float4*>(t + e);
+    const float4 b = p[1], c = p[2];
+    m[0] = b.x; m[1] = b.y; m[2] = b.z; m[3] = b.w;
+    b2 = c.x; b3 = c.y;
+}
+__device__ __forceinline__ void tab_bm(const TabEntry<double>* t, int e, double& b2, double& b3, double (&m)[4]) {
+    const double2* p = reinterpret_cast<const double2*>(t + e);
+    const double2 c = p[2], d = p[3], x = p[4];
+    m[0] = c.x; m[1] = c.y; m[2] = d.x; m[3] = d.y;
+    b2 = x.x; b3 = x.y;
+}
+
 // per-point data of one output plane: table index, velocity and (residual /
 // Jacobi modes) the right-hand side
 template <typename R, int NR>
@@ -135,83 +207,98 @@ struct BoxPlane {
     Cx<R> c[NR], f[NR], e[NR];
 };
 
+// the arrays of one work item (one right-hand side) as buffer resources
+template <typename R, int MODE>
+struct ItemBuf {
+    const typename V2<R>::T* u;
+    unsigned vbytes;          // N * sizeof(complex)
+    unsigned plane_b;         // plane * sizeof(complex)
+    unsigned plane;
+    Rsrc ry, rb, ri, rc;
+    __device__ __forceinline__ ItemBuf(const WaveArgs<R>& a, int rhs) {
+        const GridData<R>& g = a.g;
+        using V = typename V2<R>::T;
+        const int64_t ro = static_cast<int64_t>(rhs) * g.N;
+        vbytes = static_cast<unsigned>(g.N) * static_cast<unsigned>(sizeof(V));
+        plane = static_cast<unsigned>(g.plane);
+        plane_b = plane * static_cast<unsigned>(sizeof(V));
+        u = a.u + ro;
+        ry = rsrc(a.y + ro, vbytes);
+        rb = rsrc(MODE == MODE_APPLY ? a.y + ro : a.b + ro, vbytes);
+        ri = rsrc(g.idx, static_cast<unsigned>(g.N) * 2u);
+        rc = rsrc(g.c, static_cast<unsigned>(g.N) * 4u);
+    }
+    // plane q of u: offsets of the lanes' rows in ofs; zero outside the grid
+    template <int NK>
+    __device__ __forceinline__ void load_plane(int q, int nz, const unsigned (&ofs)[NK],
+                                               typename V2<R>::T (&L)[NK]) const {
+        const bool in = q >= 0 && q < nz;
+        const Rsrc r = rsrc(u, in ? vbytes : 0u);
+        const unsigned so = in ? static_cast<unsigned>(q) * plane_b : 0u;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) bld(L[k], r, ofs[k], so);
+    }
+    // per-point data of plane q (0 <= q < nz); mo = element offsets of the rows
+    template <int NR, bool ROWC>
+    __device__ __forceinline__ void load_meta(int q, const unsigned (&mo)[NR], Meta<R, NR>& M) const {
+        const unsigned pe = static_cast<unsigned>(q) * plane;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!ROWC) M.idx[r] = bld_u16(ri, mo[r] * 2u, pe * 2u);
+            M.c[r] = bld_f32(rc, mo[r] * 4u, pe * 4u);
+            if (MODE != MODE_APPLY)
+                bld(M.b[r], rb, mo[r] * static_cast<unsigned>(sizeof(typename V2<R>::T)), q * plane_b);
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // unstretched-box tile
 template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC>
 __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                          int tile, int zc, int rhs, int lane) {
     using V = typename V2<R>::T;
+    constexpr unsigned SV = sizeof(V);
     const GridData<R>& g = a.g;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
-    const int xb = a.px0 + tx * kWaveCols - 1;              // x of lane 0
-    const int gx = xb + lane;
-    const bool outx = lane >= 1 && lane <= kWaveCols && gx < a.px0 + a.pw;
+    const int gx = a.px0 + tx * kWaveCols - 1 + lane;
     const bool inx = gx >= 0 && gx < g.nx;
+    const bool outx = lane >= 1 && lane <= kWaveCols && gx < a.px0 + a.pw;
     const int gxc = min(max(gx, 0), g.nx - 1);
     const int y0 = a.py0 + ty * RY;
     const int z0 = zc * a.zchunk;
     const int z1 = min(z0 + a.zchunk, g.nz);
-    const int nrow = min(RY, a.py0 + a.ph - y0);            // output rows of this tile
-    const bool edge = xb < 0 || xb + 63 >= g.nx || y0 - 1 < 0 || y0 + RY >= g.ny;
-    unsigned off[RY + 2];
-    bool okk[RY + 2];
+    const int yend = a.py0 + a.ph;
+    unsigned lo[RY + 2];      // byte offsets of the loaded rows (kOff outside the grid)
+    unsigned so[RY];          // byte offsets of the stored rows (kOff: no output)
+    unsigned mo[RY];          // element offsets of the output rows (clamped, always valid)
 #pragma unroll
     for (int k = 0; k < RY + 2; ++k) {
         const int yy = y0 - 1 + k;
-        okk[k] = inx && yy >= 0 && yy < g.ny;
-        off[k] = static_cast<unsigned>(min(max(yy, 0), g.ny - 1) * g.nx + gxc);
+        lo[k] = (inx && yy >= 0 && yy < g.ny) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
     }
-    const V* u = a.u + static_cast<int64_t>(rhs) * g.N;
-    V* const yrhs = a.y + static_cast<int64_t>(rhs) * g.N;
-    const V* brhs = (MODE == MODE_APPLY) ? nullptr : a.b + static_cast<int64_t>(rhs) * g.N;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int yy = y0 + r;
+        so[r] = (outx && yy < yend) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
+        mo[r] = static_cast<unsigned>(min(yy, g.ny - 1) * g.nx + gxc);
+    }
+    const ItemBuf<R, MODE> B_(a, rhs);
     const R sig = g.inv_h2;
 
-    auto load = [&](int q, V (&L)[RY + 2]) __attribute__((always_inline)) {
-        const int qc = min(max(q, 0), g.nz - 1);
-        const V* p = u + static_cast<int64_t>(qc) * g.plane;
-#pragma unroll
-        for (int k = 0; k < RY + 2; ++k) L[k] = p[off[k]];
-    };
-    auto load_meta = [&](int q, Meta<R, RY>& M) __attribute__((always_inline)) {
-        const int64_t pb = static_cast<int64_t>(q) * g.plane;
-        const uint16_t* ip = g.idx + pb;
-        const float* cp = g.c + pb;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            if (!ROWC) M.idx[r] = static_cast<int>(ip[off[r + 1]]);
-            M.c[r] = cp[off[r + 1]];
-            if (MODE != MODE_APPLY) M.b[r] = brhs[pb + off[r + 1]];
-        }
-    };
-    // plane q from its raw loads: zero outside the grid
-    auto unpack = [&](int q, const V (&L)[RY + 2], Cx<R> (&U)[RY + 2]) __attribute__((always_inline)) {
-        if (q < 0 || q >= g.nz) {
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) U[k] = zero<R>();
-        } else if (edge) {
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{okk[k] ? L[k].x : R(0), okk[k] ? L[k].y : R(0)};
-        } else {
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{L[k].x, L[k].y};
-        }
-    };
     auto output = [&](int zo, const Meta<R, RY>& M, const BoxPlane<R, RY>& A, const BoxPlane<R, RY>& B,
                       const BoxPlane<R, RY>& C) __attribute__((always_inline)) {
         const AxisNode<R> Z = zn[zo];
-        const int64_t pb = static_cast<int64_t>(zo) * g.plane;
-        V* yp = yrhs + pb;
+        const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            R s0, s1, s2, s3, m0, m1, m2, m3;
+            R s[4], m[4];
             if (ROWC) {
-                const EntryCoef<R> F = g.rowcoef[pb + off[r + 1]];
-                s0 = sig * F.s0; s1 = sig * F.s1; s2 = sig * F.s2; s3 = sig * F.s3;
-                m0 = F.m0; m1 = F.m1; m2 = F.m2; m3 = F.m3;
+                const EntryCoef<R> F = g.rowcoef[static_cast<int64_t>(zo) * g.plane + mo[r]];
+                s[0] = sig * F.s0; s[1] = sig * F.s1; s[2] = sig * F.s2; s[3] = sig * F.s3;
+                m[0] = F.m0; m[1] = F.m1; m[2] = F.m2; m[3] = F.m3;
             } else {
-                const TabEntry<R>& E = tab[M.idx[r] - a.tab_lo];
-                s0 = E.s[0]; s1 = E.s[1]; s2 = E.s[2]; s3 = E.s[3];
-                m0 = E.m[0]; m1 = E.m[1]; m2 = E.m[2]; m3 = E.m[3];
+                tab_sm(tab, M.idx[r] - a.tab_lo, s, m);
             }
             const R cvr = static_cast<R>(M.c[r]);
             const R kap = g.omega2 * rcp_of(cvr * cvr);
@@ -222,15 +309,16 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
                 const Cx<R> Co = A.e[r] + C.e[r];
                 if (SHIFTED) {
                     const R kr = kap * g.shift_re, ks = kap * g.shift_im;
-                    const Cx<R> K0{s0 + kr * m0, ks * m0}, K1{s1 + kr * m1, ks * m1};
-                    const Cx<R> K2{s2 + kr * m2, ks * m2}, K3{s3 + kr * m3, ks * m3};
+                    const Cx<R> K0{s[0] + kr * m[0], ks * m[0]}, K1{s[1] + kr * m[1], ks * m[1]};
+                    const Cx<R> K2{s[2] + kr * m[2], ks * m[2]}, K3{s[3] + kr * m[3], ks * m[3]};
                     acc = K0 * B.c[r];
                     cmac(acc, K1, Fc);
                     cmac(acc, K2, Ec);
                     cmac(acc, K3, Co);
                     diag = K0;
                 } else {
-                    const R A0 = s0 + kap * m0, A1 = s1 + kap * m1, A2 = s2 + kap * m2, A3 = s3 + kap * m3;
+                    const R A0 = s[0] + kap * m[0], A1 = s[1] + kap * m[1];
+                    const R A2 = s[2] + kap * m[2], A3 = s[3] + kap * m[3];
                     acc = A0 * B.c[r];
                     rmac(acc, A1, Fc);
                     rmac(acc, A2, Ec);
@@ -238,56 +326,62 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
                     diag = Cx<R>{A0, R(0)};
                 }
             } else {
-                // z-stretched plane: stiffness sig (s1 T_z + ...), mass kappa (2 m1 U_z + ...)
-                const R b2 = s2 + R(2) * s3;   // sig * beta2
+                // z-stretched plane: the in-plane class sums of planes zo - 1,
+                // zo, zo + 1 with real weights, then the complex z factors
+                const R b2 = s[2] + R(2) * s[3];   // beta2 / h^2
+                const R x0 = R(4) * b2 - R(4) * sig, x1 = sig - R(2) * b2;
+                Cx<R> Sm = s[1] * A.c[r], Sp = s[1] * C.c[r], S0 = s[1] * B.c[r], SX = x0 * B.c[r];
+                rmac(Sm, s[2], A.f[r]); rmac(Sm, s[3], A.e[r]);
+                rmac(Sp, s[2], C.f[r]); rmac(Sp, s[3], C.e[r]);
+                rmac(S0, s[2], B.f[r]); rmac(S0, s[3], B.e[r]);
+                rmac(SX, x1, B.f[r]); rmac(SX, b2, B.e[r]);
+                Cx<R> Mm = m[1] * A.c[r], Mp = m[1] * C.c[r], MX = m[0] * B.c[r];
+                rmac(Mm, m[2], A.f[r]); rmac(Mm, m[3], A.e[r]);
+                rmac(Mp, m[2], C.f[r]); rmac(Mp, m[3], C.e[r]);
+                rmac(MX, m[1], B.f[r]); rmac(MX, m[2], B.e[r]);
                 const Cx<R> tm{Z.tm_re, Z.tm_im}, tp{Z.tp_re, Z.tp_im};
                 const Cx<R> t0 = -(tm + tp);
                 const Cx<R> xz{Z.xi_re, Z.xi_im};
-                const Cx<R> um{Z.um_re, Z.um_im}, up{Z.up_re, Z.up_im};
-                const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
-                const Cx<R> kum = kc * um, kup = kc * up, kxz = kc * xz;
-                const Cx<R> Kcm = s1 * tm + (R(2) * m1) * kum;
-                const Cx<R> Kfm = s2 * tm + (R(2) * m2) * kum;
-                const Cx<R> Kem = s3 * tm + (R(2) * m3) * kum;
-                const Cx<R> Kcp = s1 * tp + (R(2) * m1) * kup;
-                const Cx<R> Kfp = s2 * tp + (R(2) * m2) * kup;
-                const Cx<R> Kep = s3 * tp + (R(2) * m3) * kup;
-                const Cx<R> Kc0 = s1 * t0 + (R(4) * b2 - R(4) * sig) * xz + m0 * kxz;
-                const Cx<R> Kf0 = s2 * t0 + (sig - R(2) * b2) * xz + m1 * kxz;
-                const Cx<R> Ke0 = s3 * t0 + b2 * xz + m2 * kxz;
-                acc = Kcm * A.c[r];
-                cmac(acc, Kfm, A.f[r]);
-                cmac(acc, Kem, A.e[r]);
-                cmac(acc, Kc0, B.c[r]);
-                cmac(acc, Kf0, B.f[r]);
-                cmac(acc, Ke0, B.e[r]);
-                cmac(acc, Kcp, C.c[r]);
-                cmac(acc, Kfp, C.f[r]);
-                cmac(acc, Kep, C.e[r]);
-                diag = Kc0;
+                const Cx<R> um2{R(2) * Z.um_re, R(2) * Z.um_im}, up2{R(2) * Z.up_re, R(2) * Z.up_im};
+                Cx<R> st = tm * Sm;
+                cmac(st, tp, Sp);
+                cmac(st, t0, S0);
+                cmac(st, xz, SX);
+                Cx<R> ms = um2 * Mm;
+                cmac(ms, up2, Mp);
+                cmac(ms, xz, MX);
+                if (SHIFTED) {
+                    const Cx<R> kc{kap * g.shift_re, kap * g.shift_im};
+                    acc = st;
+                    cmac(acc, kc, ms);
+                } else {
+                    acc = st;
+                    rmac(acc, kap, ms);
+                }
+                if (MODE == MODE_JACOBI) {
+                    const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
+                    diag = s[1] * t0 + x0 * xz + m[0] * (kc * xz);
+                } else {
+                    diag = zero<R>();
+                }
             }
             V bb{};
             if (MODE != MODE_APPLY) bb = M.b[r];
-            const Cx<R> o = finish<R, MODE>(a.omega_j, acc, diag, B.c[r], bb);
-            if (outx && r < nrow) {
-                V ov;
-                ov.x = o.re;
-                ov.y = o.im;
-                yp[off[r + 1]] = ov;
-            }
+            bst(finish<R, MODE>(a.omega_j, acc, diag, B.c[r], bb), B_.ry, so[r], pso);
         }
     };
-    // one z step: plane q enters, output plane q - 1 leaves
-    // plane q + 2 and the per-point data of plane q + 1 are loaded two steps
-    // ahead of their use; past the chunk the last plane is loaded again, so
-    // every step issues the same loads and the waits stay exact
+    // one z step: plane q enters, output plane q - 1 leaves.  Plane q + 2 and
+    // the per-point data of plane q + 1 are loaded two steps ahead of their
+    // use; past the chunk the last plane is loaded again, so every step issues
+    // the same loads and the waits stay exact.
     auto step = [&](int q, bool out, const V (&Lc)[RY + 2], V (&Ln)[RY + 2], const BoxPlane<R, RY>& A,
                     const BoxPlane<R, RY>& B, BoxPlane<R, RY>& C, const Meta<R, RY>& Mc, Meta<R, RY>& Mn)
                     __attribute__((always_inline)) {
-        load(min(q + 2, z1), Ln);
-        load_meta(min(q + 1, z1 - 1), Mn);
+        B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
+        B_.template load_meta<RY, ROWC>(min(q + 1, z1 - 1), mo, Mn);
         Cx<R> U[RY + 2];
-        unpack(q, Lc, U);
+#pragma unroll
+        for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
         Cx<R> sx[RY + 2];
 #pragma unroll
         for (int k = 0; k < RY + 2; ++k) sx[k] = nxt_g<64>(U[k]) + prv_g<64>(U[k]);
@@ -305,8 +399,8 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     V L0[RY + 2], L1[RY + 2], L2[RY + 2];
     BoxPlane<R, RY> P0, P1, P2;
     Meta<R, RY> M0, M1, M2;
-    load(z0 - 1, L0);
-    load(z0, L1);
+    B_.load_plane(z0 - 1, g.nz, lo, L0);
+    B_.load_plane(z0, g.nz, lo, L1);
     // planes z0 - 1 and z0 enter without an output; then one output per step
     step(z0 - 1, false, L0, L2, P1, P2, P0, M2, M1);
     step(z0, false, L1, L0, P2, P0, P1, M0, M2);
@@ -323,7 +417,8 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
 
 // ---------------------------------------------------------------------------
 // PML-frame tile: lanes along x in groups of LW (LW - 2 output columns each,
-// halo at both ends), 64 / LW groups stacked along y, RQ rows per lane
+// halo at both ends), 64 / LW groups stacked along y, RQ rows per lane.  The
+// 16-lane groups serve the left / right strips, whose rows are unstretched.
 template <typename R>
 struct Factors {
     Cx<R> tm, tp, t0, xi, um, up;
@@ -349,6 +444,8 @@ template <typename R, int MODE, bool SHIFTED, int RQ, int LW, bool ROWC>
 __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                            int fr, int ft, int zc, int rhs, int lane) {
     using V = typename V2<R>::T;
+    constexpr unsigned SV = sizeof(V);
+    constexpr bool QPLAIN = LW == 16;   // left / right strips: rows unstretched
     const GridData<R>& g = a.g;
     constexpr int NG = 64 / LW;
     const int lx = lane % LW, ly = lane / LW;
@@ -365,84 +462,51 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
     const Factors<R> FL = factors<R>(g.ax[lcc]);
     Factors<R> FQ[RQ];
     Cx<R> xLQ[RQ];
-    unsigned off[RQ + 2];
-    bool okk[RQ + 2];
+    unsigned lo[RQ + 2], so[RQ], mo[RQ];
 #pragma unroll
     for (int k = 0; k < RQ + 2; ++k) {
         const int qq = q0 - 1 + k;
-        okk[k] = inl && qq >= 0 && qq < g.ny;
-        off[k] = static_cast<unsigned>(min(max(qq, 0), g.ny - 1) * g.nx + lcc);
+        lo[k] = (inl && qq >= 0 && qq < g.ny) ? static_cast<unsigned>(qq * g.nx + lc) * SV : kOff;
     }
-    bool outr[RQ];
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
-        FQ[r] = factors<R>(g.ay[min(q0 + r, g.ny - 1)]);
-        xLQ[r] = FL.xi * FQ[r].xi;
-        outr[r] = outl && (q0 + r < y_org + y_ext);
+        const int qq = q0 + r;
+        FQ[r] = factors<R>(g.ay[min(qq, g.ny - 1)]);
+        xLQ[r] = QPLAIN ? FL.xi : FL.xi * FQ[r].xi;
+        so[r] = (outl && qq < y_org + y_ext) ? static_cast<unsigned>(qq * g.nx + lc) * SV : kOff;
+        mo[r] = static_cast<unsigned>(min(qq, g.ny - 1) * g.nx + lcc);
     }
-    const V* u = a.u + static_cast<int64_t>(rhs) * g.N;
-    V* const yrhs = a.y + static_cast<int64_t>(rhs) * g.N;
-    const V* brhs = (MODE == MODE_APPLY) ? nullptr : a.b + static_cast<int64_t>(rhs) * g.N;
+    const ItemBuf<R, MODE> B_(a, rhs);
     const R sig = g.inv_h2;
 
-    auto load = [&](int q, V (&L)[RQ + 2]) __attribute__((always_inline)) {
-        const int qc = min(max(q, 0), g.nz - 1);
-        const V* p = u + static_cast<int64_t>(qc) * g.plane;
-#pragma unroll
-        for (int k = 0; k < RQ + 2; ++k) L[k] = p[off[k]];
-    };
-    auto load_meta = [&](int q, Meta<R, RQ>& M) __attribute__((always_inline)) {
-        const int64_t pb = static_cast<int64_t>(q) * g.plane;
-        const uint16_t* ip = g.idx + pb;
-        const float* cp = g.c + pb;
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) {
-            if (!ROWC) M.idx[r] = static_cast<int>(ip[off[r + 1]]);
-            M.c[r] = cp[off[r + 1]];
-            if (MODE != MODE_APPLY) M.b[r] = brhs[pb + off[r + 1]];
-        }
-    };
-    auto unpack = [&](int q, const V (&L)[RQ + 2], Cx<R> (&U)[RQ + 2]) __attribute__((always_inline)) {
-        if (q < 0 || q >= g.nz) {
-#pragma unroll
-            for (int k = 0; k < RQ + 2; ++k) U[k] = zero<R>();
-        } else {
-#pragma unroll
-            for (int k = 0; k < RQ + 2; ++k) U[k] = Cx<R>{okk[k] ? L[k].x : R(0), okk[k] ? L[k].y : R(0)};
-        }
-    };
     auto output = [&](int zo, const Meta<R, RQ>& M, const FramePlane<R, RQ>& A, const FramePlane<R, RQ>& B,
                       const FramePlane<R, RQ>& C) __attribute__((always_inline)) {
         const AxisNode<R> Z = zn[zo];
         const bool plainz = Z.plain != 0;
         const Factors<R> FZ = factors<R>(Z);
-        const int64_t pb = static_cast<int64_t>(zo) * g.plane;
-        V* yp = yrhs + pb;
+        const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
 #pragma unroll
         for (int r = 0; r < RQ; ++r) {
-            R b2, b3, m0, m1, m2, m3;
+            R b2, b3, m[4];
             if (ROWC) {
-                const EntryCoef<R> E = g.rowcoef[pb + off[r + 1]];
-                b2 = E.beta2; b3 = E.beta3; m0 = E.m0; m1 = E.m1; m2 = E.m2; m3 = E.m3;
+                const EntryCoef<R> E = g.rowcoef[static_cast<int64_t>(zo) * g.plane + mo[r]];
+                b2 = E.beta2; b3 = E.beta3; m[0] = E.m0; m[1] = E.m1; m[2] = E.m2; m[3] = E.m3;
             } else {
-                const TabEntry<R>& E = tab[M.idx[r] - a.tab_lo];
-                b2 = E.b2; b3 = E.b3;
-                m0 = E.m[0]; m1 = E.m[1]; m2 = E.m[2]; m3 = E.m[3];
+                tab_bm(tab, M.idx[r] - a.tab_lo, b2, b3, m);
             }
             const R cvr = static_cast<R>(M.c[r]);
             const R kap = g.omega2 * rcp_of(cvr * cvr);
-            const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
             Cx<R> PTA = A.a[r], PTB = B.a[r], PTC = C.a[r];
             rmac(PTA, b2, A.b[r]); rmac(PTA, b3, A.c[r]);
             rmac(PTB, b2, B.b[r]); rmac(PTB, b3, B.c[r]);
             rmac(PTC, b2, C.b[r]); rmac(PTC, b3, C.c[r]);
-            const R w1 = R(2) * m1, w2 = R(4) * m2, w3 = R(8) * m3;
+            const R w1 = R(2) * m[1], w2 = R(4) * m[2], w3 = R(8) * m[3];
             Cx<R> PUA = w1 * A.a[r], PUC = w1 * C.a[r];
             rmac(PUA, w2, A.d[r]); rmac(PUA, w3, A.e[r]);
             rmac(PUC, w2, C.d[r]); rmac(PUC, w3, C.e[r]);
             Cx<R> PXs = B.b[r];
             rmac(PXs, b2, B.c[r]);
-            Cx<R> PXm = m0 * B.a[r];
+            Cx<R> PXm = m[0] * B.a[r];
             rmac(PXm, w1, B.d[r]); rmac(PXm, w2, B.e[r]);
             Cx<R> stiff, mass;
             if (plainz) {   // T_z = (1, -2, 1), X_z = 1, U_z = (1/2, 0, 1/2)
@@ -458,41 +522,38 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
                 cmac(mass, FZ.xi, PXm);
             }
             Cx<R> acc = sig * stiff;
-            cmac(acc, kc, mass);
+            if (SHIFTED) {
+                cmac(acc, Cx<R>{kap * g.shift_re, kap * g.shift_im}, mass);
+            } else {
+                rmac(acc, kap, mass);
+            }
             Cx<R> diag = zero<R>();
             if (MODE == MODE_JACOBI) {
+                const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
                 const Factors<R>& Q = FQ[r];
                 const Cx<R> ac = xLQ[r];
-                const Cx<R> bc = FL.t0 * Q.xi + FL.xi * Q.t0;
-                const Cx<R> cc = FL.t0 * Q.t0;
+                const Cx<R> bc = QPLAIN ? FL.t0 + R(-2) * FL.xi : FL.t0 * Q.xi + FL.xi * Q.t0;
+                const Cx<R> cc = QPLAIN ? R(-2) * FL.t0 : FL.t0 * Q.t0;
                 Cx<R> pc = ac;
                 rmac(pc, b2, bc);
                 rmac(pc, b3, cc);
                 Cx<R> pxs = bc;
                 rmac(pxs, b2, cc);
-                diag = sig * (FZ.t0 * pc + FZ.xi * pxs) + (m0 * kc) * (FZ.xi * ac);
+                diag = sig * (FZ.t0 * pc + FZ.xi * pxs) + (m[0] * kc) * (FZ.xi * ac);
             }
             V bb{};
             if (MODE != MODE_APPLY) bb = M.b[r];
-            const Cx<R> o = finish<R, MODE>(a.omega_j, acc, diag, B.u[r], bb);
-            if (outr[r]) {
-                V ov;
-                ov.x = o.re;
-                ov.y = o.im;
-                yp[off[r + 1]] = ov;
-            }
+            bst(finish<R, MODE>(a.omega_j, acc, diag, B.u[r], bb), B_.ry, so[r], pso);
         }
     };
-    // plane q + 2 and the per-point data of plane q + 1 are loaded two steps
-    // ahead of their use; past the chunk the last plane is loaded again, so
-    // every step issues the same loads and the waits stay exact
     auto step = [&](int q, bool out, const V (&Lc)[RQ + 2], V (&Ln)[RQ + 2], const FramePlane<R, RQ>& A,
                     const FramePlane<R, RQ>& B, FramePlane<R, RQ>& C, const Meta<R, RQ>& Mc, Meta<R, RQ>& Mn)
                     __attribute__((always_inline)) {
-        load(min(q + 2, z1), Ln);
-        load_meta(min(q + 1, z1 - 1), Mn);
+        B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
+        B_.template load_meta<RQ, ROWC>(min(q + 1, z1 - 1), mo, Mn);
         Cx<R> U[RQ + 2];
-        unpack(q, Lc, U);
+#pragma unroll
+        for (int k = 0; k < RQ + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
         Cx<R> RT[RQ + 2], RU[RQ + 2];
 #pragma unroll
         for (int k = 0; k < RQ + 2; ++k) {
@@ -502,13 +563,21 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
         }
 #pragma unroll
         for (int r = 0; r < RQ; ++r) {
-            const Factors<R>& Q = FQ[r];
             C.u[r] = U[r + 1];
             C.a[r] = xLQ[r] * U[r + 1];
-            C.b[r] = Q.xi * RT[r + 1] + FL.xi * (Q.tm * U[r] + Q.t0 * U[r + 1] + Q.tp * U[r + 2]);
-            C.c[r] = Q.tm * RT[r] + Q.t0 * RT[r + 1] + Q.tp * RT[r + 2];
-            C.d[r] = Q.xi * RU[r + 1] + FL.xi * (Q.um * U[r] + Q.up * U[r + 2]);
-            C.e[r] = Q.um * RU[r] + Q.up * RU[r + 2];
+            if (QPLAIN) {   // row factors T = (1, -2, 1), X = 1, U = (1/2, 0, 1/2)
+                const Cx<R> ys = U[r] + U[r + 2];
+                C.b[r] = RT[r + 1] + FL.xi * (ys - R(2) * U[r + 1]);
+                C.c[r] = RT[r] + RT[r + 2] - R(2) * RT[r + 1];
+                C.d[r] = RU[r + 1] + R(0.5) * (FL.xi * ys);
+                C.e[r] = R(0.5) * (RU[r] + RU[r + 2]);
+            } else {
+                const Factors<R>& Q = FQ[r];
+                C.b[r] = Q.xi * RT[r + 1] + FL.xi * (Q.tm * U[r] + Q.t0 * U[r + 1] + Q.tp * U[r + 2]);
+                C.c[r] = Q.tm * RT[r] + Q.t0 * RT[r + 1] + Q.tp * RT[r + 2];
+                C.d[r] = Q.xi * RU[r + 1] + FL.xi * (Q.um * U[r] + Q.up * U[r + 2]);
+                C.e[r] = Q.um * RU[r] + Q.up * RU[r + 2];
+            }
         }
         if (out) output(q - 1, Mc, A, B, C);
     };
@@ -518,9 +587,8 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
     V L0[RQ + 2], L1[RQ + 2], L2[RQ + 2];
     FramePlane<R, RQ> P0, P1, P2;
     Meta<R, RQ> M0, M1, M2;
-    load(z0 - 1, L0);
-    load(z0, L1);
-    // planes z0 - 1 and z0 enter without an output; then one output per step
+    B_.load_plane(z0 - 1, g.nz, lo, L0);
+    B_.load_plane(z0, g.nz, lo, L1);
     step(z0 - 1, false, L0, L2, P1, P2, P0, M2, M1);
     step(z0, false, L1, L0, P2, P0, P1, M0, M2);
     int q = z0 + 1;

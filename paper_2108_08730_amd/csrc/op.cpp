@@ -518,3 +518,9 @@ extern "C" int helm27_set_kernel_variant(helm27_op* op, int variant) {
     op->g.kernel_variant = variant;
     return HELM27_OK;
 }
+
+extern "C" int helm27_set_zchunk(helm27_op* op, int zchunk) {
+    if (!op || zchunk < 0 || zchunk == 1 || zchunk > 4096) return HELM27_EINVAL;
+    op->g.wave_zchunk = zchunk;
+    return HELM27_OK;
+}
