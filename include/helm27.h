@@ -218,7 +218,10 @@ typedef struct {
     int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
     double mg_omega;     /* Jacobi damping (default 0.6) */
     int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 5) */
-    int    use_graph;    /* capture the Arnoldi steps in hipGraphs (default 0) */
+    int    use_graph;    /* replay each multigrid V-cycle from one captured hipGraph
+                            (captured on first use, kept with the workspace; the
+                            same kernels as the eager launches, so the same
+                            results); 0 = eager launches (default 1) */
     int    verbose;
     double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0.5) */
 } helm27_solve_opts;

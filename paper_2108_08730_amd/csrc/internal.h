@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <mutex>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "helm27.h"
@@ -22,6 +24,45 @@
     } while (0)
 
 namespace h27 {
+
+// Launch recorder: while a GraphRec is installed on the calling thread,
+// launch() appends a kernel node (depending on the previous one) to its graph
+// instead of launching; otherwise it launches on the stream.  Building the
+// graph node by node needs no stream capture, so it is unaffected by what
+// other threads do on their streams meanwhile.
+struct GraphRec {
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+};
+GraphRec*& graph_rec();   // the calling thread's recorder (null: launch eagerly)
+
+template <typename... P, typename... A>
+inline hipError_t launch(void (*fn)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s, A&&... a) {
+    GraphRec* rec = graph_rec();
+    if (!rec) {
+        hipLaunchKernelGGL(fn, grid, block, lds, s, std::forward<A>(a)...);
+        return hipGetLastError();
+    }
+    if (rec->err != hipSuccess) return rec->err;
+    std::tuple<P...> vals(static_cast<P>(a)...);
+    void* ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    std::apply([&](auto&... v) {
+        int k = 0;
+        ((ptrs[k++] = static_cast<void*>(&v)), ...);
+    }, vals);
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = static_cast<unsigned int>(lds);
+    kp.kernelParams = ptrs;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    rec->err = hipGraphAddKernelNode(&node, rec->graph, rec->last ? &rec->last : nullptr, rec->last ? 1 : 0, &kp);
+    if (rec->err == hipSuccess) rec->last = node;
+    return rec->err;
+}
 
 // Per-table-entry coefficients used by the kernels (all dimensionless).
 // s0..s3: interior stiffness class values (centre, face, edge, corner) times h^2;

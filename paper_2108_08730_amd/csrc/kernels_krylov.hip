@@ -10,6 +10,11 @@
 
 namespace h27 {
 
+GraphRec*& graph_rec() {
+    static thread_local GraphRec* rec = nullptr;
+    return rec;
+}
+
 constexpr int kRedBlock = 256;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -53,14 +58,13 @@ int fill_zero(void* p, int64_t bytes, hipStream_t s) {
     if (bytes <= 0) return HELM27_OK;
     if (bytes % 16 == 0) {
         const int64_t n = bytes / 16;
-        hipLaunchKernelGGL(fill_zero_kernel<double2>, dim3(grid_for(n)), dim3(kRedBlock), 0, s,
-                           static_cast<double2*>(p), n);
+        H27_CHECK_HIP(launch(fill_zero_kernel<double2>, dim3(grid_for(n)), dim3(kRedBlock), 0, s,
+                             static_cast<double2*>(p), n));
     } else {
         const int64_t n = bytes / 4;
-        hipLaunchKernelGGL(fill_zero_kernel<float>, dim3(grid_for(n)), dim3(kRedBlock), 0, s, static_cast<float*>(p),
-                           n);
+        H27_CHECK_HIP(launch(fill_zero_kernel<float>, dim3(grid_for(n)), dim3(kRedBlock), 0, s,
+                             static_cast<float*>(p), n));
     }
-    H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
 
@@ -128,94 +132,101 @@ template int norms<double>(const void*, int64_t, int, double*, int, double*, hip
 
 // ---------------------------------------------------------------------------
 // Multi-vector dot products h[rhs][j] = sum_i conj(V_j[rhs][i]) w[rhs][i] for
-// j in [j0, j0 + jn), jn <= 8.  V is [m+1][nrhs][N]; partial is
-// [nrhs][8][nb] (complex as 2 doubles).
+// all j < J in one launch (8 basis vectors per pass over the block's
+// elements).  V is [m+1][nrhs][N]; partial is [nrhs][J][nb] (complex as 2
+// doubles).
 template <typename R>
 __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
-                                                                 int j0, int jn, const typename V2<R>::T* __restrict__ w,
+                                                                 int J, const typename V2<R>::T* __restrict__ w,
                                                                  int64_t N, double* __restrict__ partial) {
     __shared__ double sh[16 * 4];
     const int rhs = blockIdx.y;
     const typename V2<R>::T* wr = w + static_cast<int64_t>(rhs) * N;
-    double acc[16];
+    for (int j0 = 0; j0 < J; j0 += 8) {
+        const int jn = J - j0 < 8 ? J - j0 : 8;
+        double acc[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
-        const typename V2<R>::T wv = wr[i];
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+        for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+             i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
+            const typename V2<R>::T wv = wr[i];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < jn) {
-                const typename V2<R>::T v = V[static_cast<int64_t>(j0 + k) * vstride + static_cast<int64_t>(rhs) * N + i];
-                // conj(v) * w
-                acc[2 * k] += static_cast<double>(v.x) * wv.x + static_cast<double>(v.y) * wv.y;
-                acc[2 * k + 1] += static_cast<double>(v.x) * wv.y - static_cast<double>(v.y) * wv.x;
+            for (int k = 0; k < 8; ++k) {
+                if (k < jn) {
+                    const typename V2<R>::T v =
+                        V[static_cast<int64_t>(j0 + k) * vstride + static_cast<int64_t>(rhs) * N + i];
+                    // conj(v) * w
+                    acc[2 * k] += static_cast<double>(v.x) * wv.x + static_cast<double>(v.y) * wv.y;
+                    acc[2 * k + 1] += static_cast<double>(v.x) * wv.y - static_cast<double>(v.y) * wv.x;
+                }
             }
         }
-    }
-    block_sum<16>(acc, sh);
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < jn; ++k) {
-            double* p = partial + ((static_cast<int64_t>(rhs) * 8 + k) * gridDim.x + blockIdx.x) * 2;
-            p[0] = acc[2 * k];
-            p[1] = acc[2 * k + 1];
+        block_sum<16>(acc, sh);
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < jn; ++k) {
+                double* p = partial + ((static_cast<int64_t>(rhs) * J + j0 + k) * gridDim.x + blockIdx.x) * 2;
+                p[0] = acc[2 * k];
+                p[1] = acc[2 * k + 1];
+            }
         }
     }
 }
 
-// h[rhs * ldh + j0 + k] (+)= sum_b partial[rhs][k][b]; one block per (rhs, k)
-__global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, int j0, int jn, double2* __restrict__ h,
-                                   int ldh, int accumulate) {
+// h[rhs * ldh + j] = sum_b partial[rhs][j][b] (and hsum[rhs * ldh + j] += the
+// same when hsum is given); one block per (rhs, j), summed in a fixed order
+__global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, int J, double2* __restrict__ h,
+                                   double2* __restrict__ hsum, int ldh) {
     __shared__ double sh[8];
-    const int rhs = blockIdx.x / 8, k = blockIdx.x % 8;
-    if (k >= jn) return;
+    const int rhs = blockIdx.x / J, j = blockIdx.x % J;
     double acc[2] = {0.0, 0.0};
-    const double* p = partial + (static_cast<int64_t>(rhs) * 8 + k) * nb * 2;
+    const double* p = partial + (static_cast<int64_t>(rhs) * J + j) * nb * 2;
     for (int b = threadIdx.x; b < nb; b += kRedBlock) {
         acc[0] += p[2 * b];
         acc[1] += p[2 * b + 1];
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
-        double2* o = h + static_cast<int64_t>(rhs) * ldh + j0 + k;
-        if (accumulate) {
-            o->x += acc[0];
-            o->y += acc[1];
-        } else {
-            o->x = acc[0];
-            o->y = acc[1];
+        double2* o = h + static_cast<int64_t>(rhs) * ldh + j;
+        o->x = acc[0];
+        o->y = acc[1];
+        if (hsum) {
+            double2* t = hsum + static_cast<int64_t>(rhs) * ldh + j;
+            t->x += acc[0];
+            t->y += acc[1];
         }
     }
 }
 
 template <typename R>
 int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nrhs, double* d_partial, int max_blocks,
-         double2* d_h, int ldh, int accumulate, hipStream_t s) {
+         double2* d_h, double2* d_hsum, int ldh, hipStream_t s) {
+    if (J <= 0 || J > ldh) return HELM27_EINVAL;
     unsigned nb = grid_for(N);
     if (nb > static_cast<unsigned>(max_blocks)) nb = max_blocks;
-    for (int j0 = 0; j0 < J; j0 += 8) {
-        const int jn = J - j0 < 8 ? J - j0 : 8;
-        hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
-                           static_cast<const typename V2<R>::T*>(V), vstride, j0, jn,
-                           static_cast<const typename V2<R>::T*>(w), N, d_partial);
-        hipLaunchKernelGGL(mdot_reduce_kernel, dim3(nrhs * 8), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb),
-                           j0, jn, d_h, ldh, accumulate);
-    }
+    hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
+                       static_cast<const typename V2<R>::T*>(V), vstride, J,
+                       static_cast<const typename V2<R>::T*>(w), N, d_partial);
+    hipLaunchKernelGGL(mdot_reduce_kernel, dim3(nrhs * J), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb), J,
+                       d_h, d_hsum, ldh);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
-template int mdot<float>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, int, int,
+template int mdot<float>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, double2*, int,
                          hipStream_t);
-template int mdot<double>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, int, int,
+template int mdot<double>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, double2*, int,
                           hipStream_t);
 
 // w[rhs] -= sum_{j < J} V_j[rhs] * hc[rhs][j] where hc are the coefficients of
-// the current pass (FP64 on the device, applied in the vector precision).
+// the current pass (FP64 on the device, applied in the vector precision);
+// with partial != null also partial[rhs][blk] = sum of |w_new|^2 over the
+// block's elements (FP64)
 template <typename R>
 __global__ __launch_bounds__(kRedBlock) void cgs_update_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
                                                                int J, const double2* __restrict__ hc, int ldh,
-                                                               typename V2<R>::T* __restrict__ w, int64_t N) {
+                                                               typename V2<R>::T* __restrict__ w, int64_t N,
+                                                               double* __restrict__ partial) {
     __shared__ R hs[2 * 64];
+    __shared__ double sh[4];
     const int rhs = blockIdx.y;
     for (int j = threadIdx.x; j < J; j += kRedBlock) {
         const double2 c = hc[static_cast<int64_t>(rhs) * ldh + j];
@@ -224,6 +235,7 @@ __global__ __launch_bounds__(kRedBlock) void cgs_update_kernel(const typename V2
     }
     __syncthreads();
     typename V2<R>::T* wr = w + static_cast<int64_t>(rhs) * N;
+    double nrm[1] = {0.0};
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
          i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
         typename V2<R>::T acc = wr[i];
@@ -234,31 +246,45 @@ __global__ __launch_bounds__(kRedBlock) void cgs_update_kernel(const typename V2
             acc.y -= v.x * hi + v.y * hr;
         }
         wr[i] = acc;
+        nrm[0] += static_cast<double>(acc.x) * acc.x + static_cast<double>(acc.y) * acc.y;
+    }
+    if (partial) {
+        block_sum<1>(nrm, sh);
+        if (threadIdx.x == 0) partial[static_cast<int64_t>(rhs) * gridDim.x + blockIdx.x] = nrm[0];
     }
 }
 
 template <typename R>
 int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int ldh, void* w, int64_t N, int nrhs,
-               hipStream_t s) {
+               double* d_partial, int max_blocks, double* d_nrm, hipStream_t s) {
     if (J > 64) return HELM27_EINVAL;
-    hipLaunchKernelGGL(cgs_update_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
+    unsigned nb = grid_for(N);
+    if (d_nrm && nb > static_cast<unsigned>(max_blocks)) nb = max_blocks;
+    hipLaunchKernelGGL(cgs_update_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
                        static_cast<const typename V2<R>::T*>(V), vstride, J, d_hc, ldh,
-                       static_cast<typename V2<R>::T*>(w), N);
+                       static_cast<typename V2<R>::T*>(w), N, d_nrm ? d_partial : nullptr);
+    if (d_nrm)
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3(nrhs), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb),
+                           d_nrm, 1);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
-template int cgs_update<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, hipStream_t);
-template int cgs_update<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, hipStream_t);
+template int cgs_update<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, double*, int,
+                               double*, hipStream_t);
+template int cgs_update<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, double*, int,
+                                double*, hipStream_t);
 
 // out[rhs] = x[rhs] * f(nrm[rhs]): mode 0 -> 1/nrm (0 if nrm == 0), mode 1 -> nrm
 template <typename Ri, typename Ro>
-__global__ void scale_kernel(const typename V2<Ri>::T* __restrict__ x, typename V2<Ro>::T* __restrict__ out, int64_t N,
-                             const double* __restrict__ nrm, int mode) {
+__global__ void scale_kernel(const typename V2<Ri>::T* __restrict__ x, typename V2<Ro>::T* __restrict__ out,
+                             typename V2<Ro>::T* __restrict__ out2, int64_t N, const double* __restrict__ nrm,
+                             int mode) {
     const int rhs = blockIdx.y;
     const double n = nrm[rhs];
     const double f = mode == 0 ? (n > 0 ? 1.0 / n : 0.0) : n;
     const typename V2<Ri>::T* xr = x + static_cast<int64_t>(rhs) * N;
     typename V2<Ro>::T* orr = out + static_cast<int64_t>(rhs) * N;
+    typename V2<Ro>::T* orr2 = out2 ? out2 + static_cast<int64_t>(rhs) * N : nullptr;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
          i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
         const typename V2<Ri>::T v = xr[i];
@@ -266,20 +292,22 @@ __global__ void scale_kernel(const typename V2<Ri>::T* __restrict__ x, typename 
         o.x = static_cast<Ro>(static_cast<double>(v.x) * f);
         o.y = static_cast<Ro>(static_cast<double>(v.y) * f);
         orr[i] = o;
+        if (orr2) orr2[i] = o;
     }
 }
 
 template <typename Ri, typename Ro>
-int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s) {
+int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s,
+                  void* out2) {
     hipLaunchKernelGGL((scale_kernel<Ri, Ro>), dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
-                       static_cast<const typename V2<Ri>::T*>(x), static_cast<typename V2<Ro>::T*>(out), N, d_nrm,
-                       mode);
+                       static_cast<const typename V2<Ri>::T*>(x), static_cast<typename V2<Ro>::T*>(out),
+                       static_cast<typename V2<Ro>::T*>(out2), N, d_nrm, mode);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
-template int scale_by_norm<float, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t);
-template int scale_by_norm<double, double>(const void*, void*, int64_t, int, const double*, int, hipStream_t);
-template int scale_by_norm<double, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t);
+template int scale_by_norm<float, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*);
+template int scale_by_norm<double, double>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*);
+template int scale_by_norm<double, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*);
 
 // u64[rhs] += nrm[rhs] * e[rhs]  (refinement update, e in the inner precision)
 template <typename R>
@@ -590,19 +618,17 @@ __global__ void prolong_add_kernel(const typename V2<R>::T* __restrict__ c, int 
 template <typename R>
 int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s) {
     const int64_t total = static_cast<int64_t>(cx) * cy * cz * nrhs;
-    hipLaunchKernelGGL(restrict_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
-                       static_cast<const typename V2<R>::T*>(f), nx, ny, nz, static_cast<typename V2<R>::T*>(c), cx, cy,
-                       cz, nrhs);
-    H27_CHECK_HIP(hipGetLastError());
+    H27_CHECK_HIP(launch(restrict_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
+                         static_cast<const typename V2<R>::T*>(f), nx, ny, nz, static_cast<typename V2<R>::T*>(c), cx,
+                         cy, cz, nrhs));
     return HELM27_OK;
 }
 template <typename R>
 int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int ny, int nz, int nrhs, hipStream_t s) {
     const int64_t total = static_cast<int64_t>(nx) * ny * nz * nrhs;
-    hipLaunchKernelGGL(prolong_add_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
-                       static_cast<const typename V2<R>::T*>(c), cx, cy, cz, static_cast<typename V2<R>::T*>(f), nx, ny,
-                       nz, nrhs);
-    H27_CHECK_HIP(hipGetLastError());
+    H27_CHECK_HIP(launch(prolong_add_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
+                         static_cast<const typename V2<R>::T*>(c), cx, cy, cz, static_cast<typename V2<R>::T*>(f), nx,
+                         ny, nz, nrhs));
     return HELM27_OK;
 }
 template int mg_restrict<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);

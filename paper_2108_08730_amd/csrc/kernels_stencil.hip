@@ -396,8 +396,7 @@ GridData<double> grid_data<double>(const GridOp& g, double shift_re, double shif
 
 template <typename R, int MODE, bool SHIFTED>
 static int launch_mode(const StencilArgs<R>& args, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((stencil27_kernel<R, MODE, SHIFTED, kRows>), grid, dim3(kBlock), 0, s, args);
-    H27_CHECK_HIP(hipGetLastError());
+    H27_CHECK_HIP(launch(stencil27_kernel<R, MODE, SHIFTED, kRows>, grid, dim3(kBlock), 0, s, args));
     return HELM27_OK;
 }
 

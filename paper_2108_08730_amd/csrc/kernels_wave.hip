@@ -685,8 +685,7 @@ static int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
     const int cap = resident_blocks(fn, lds);
     if (cap <= 0) return HELM27_EDEVICE;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC>), dim3(blocks), dim3(kBlock), lds, s, a);
-    H27_CHECK_HIP(hipGetLastError());
+    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC>, dim3(blocks), dim3(kBlock), lds, s, a));
     return HELM27_OK;
 }
 

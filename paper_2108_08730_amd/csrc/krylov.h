@@ -10,16 +10,22 @@ int inject_sources(double2* b, int64_t N, const int64_t* d_lin, const double2* d
 // d_out[rhs] = ||x[rhs]||_2 (FP64); d_partial holds nrhs * max_blocks doubles
 template <typename R>
 int norms(const void* x, int64_t N, int nrhs, double* d_partial, int max_blocks, double* d_out, hipStream_t s);
-// d_h[rhs * ldh + j] (+)= <V_j[rhs], w[rhs]> for j < J; d_partial holds nrhs * 8 * max_blocks * 2 doubles
+// d_h[rhs * ldh + j] = <V_j[rhs], w[rhs]> for j < J (J <= ldh), and
+// d_hsum[...] += the same when d_hsum is not null; d_partial holds
+// nrhs * ldh * max_blocks * 2 doubles
 template <typename R>
 int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nrhs, double* d_partial, int max_blocks,
-         double2* d_h, int ldh, int accumulate, hipStream_t s);
+         double2* d_h, double2* d_hsum, int ldh, hipStream_t s);
+// w[rhs] -= sum_{j<J} V_j[rhs] d_hc[rhs * ldh + j]; with d_nrm not null also
+// d_nrm[rhs] = ||w_new[rhs]|| (FP64, deterministic two-stage sum)
 template <typename R>
 int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int ldh, void* w, int64_t N, int nrhs,
-               hipStream_t s);
-// out = x / nrm (mode 0) or x * nrm (mode 1), per right-hand side
+               double* d_partial, int max_blocks, double* d_nrm, hipStream_t s);
+// out = x / nrm (mode 0) or x * nrm (mode 1), per right-hand side; the same
+// values also to out2 when it is not null
 template <typename Ri, typename Ro>
-int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s);
+int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s,
+                  void* out2 = nullptr);
 template <typename R>
 int refine_update(double2* u, const void* e, int64_t N, int nrhs, const double* d_nrm, hipStream_t s);
 template <typename R>

@@ -59,9 +59,24 @@ struct SolverState {
     double2* d_amp = nullptr;
     int src_cap = 0;
     double2* d_b = nullptr;          // point-source right-hand sides [src_cap][N]
+    // captured V-cycle (hipGraph): reads vin, leaves its result in vgraph_out
+    void* vin = nullptr;
+    hipGraphExec_t vgraph = nullptr;
+    void* vgraph_out = nullptr;
+    double gkey_d[3] = {0, 0, 0};
+    int gkey_i[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    bool graph_failed = false;
 };
 
+static void drop_graph(SolverState* S) {
+    if (S->vgraph) hipGraphExecDestroy(S->vgraph);
+    S->vgraph = nullptr;
+    S->vgraph_out = nullptr;
+}
+
 static void free_workspace(SolverState* S) {
+    drop_graph(S);
+    S->vin = nullptr;
     for (void* p : S->bufs) hipFree(p);
     S->bufs.clear();
     S->X.clear();
@@ -72,6 +87,7 @@ static void free_workspace(SolverState* S) {
 }
 
 static void free_hierarchy(SolverState* S) {
+    drop_graph(S);
     for (GridOp& g : S->coarse) grid_free(&g);
     S->coarse.clear();
     S->levels = 0;
@@ -156,6 +172,7 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     if ((st = alloc(S, &S->e, vec))) return st;
     if ((st = alloc(S, &S->rin, vec))) return st;
     if ((st = alloc(S, &S->tmp, vec))) return st;
+    if ((st = alloc(S, &S->vin, vec))) return st;
     S->X.resize(S->levels);
     S->T.resize(S->levels);
     S->B.resize(S->levels);
@@ -175,7 +192,8 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     if ((st = alloc(S, &p, static_cast<size_t>(N) * nrhs * sizeof(double2)))) return st;
     S->r64 = static_cast<double2*>(p);
     S->max_blocks = 1024;
-    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * 8 * S->max_blocks * 2 * sizeof(double)))) return st;
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1 > 8 ? m + 1 : 8) * S->max_blocks * 2 * sizeof(double))))
+        return st;
     S->d_partial = static_cast<double*>(p);
     const int ldh = m + 1;
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * ldh * sizeof(double2)))) return st;
@@ -207,15 +225,6 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->prec = prec;
     S->N = N;
     return HELM27_OK;
-}
-
-// Givens bookkeeping adds the two CGS passes' coefficients: hcol += htmp.
-__global__ void hadd_kernel(double2* __restrict__ a, const double2* __restrict__ b, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        a[i].x += b[i].x;
-        a[i].y += b[i].y;
-    }
 }
 
 struct Ctx {
@@ -270,6 +279,56 @@ static int precond(const Ctx& c, const void* v, void** z) {
     return vcycle<R>(c, 0, v, z);
 }
 
+static bool use_vgraph(const Ctx& c) {
+    return c.o->use_graph && c.S->levels > 0 && c.o->mg_levels > 0 && !c.S->graph_failed;
+}
+
+// The V-cycle on S->vin replayed from one hipGraph: the launch sequence
+// depends only on the hierarchy, the right-hand-side count, the precision, the
+// smoother options and the tile tuning, which key the graph.  The graph is
+// built node by node from the same launchers (kernel nodes only: the zero
+// fills are kernels), so a replay runs exactly the eager kernels.  Falls back
+// to eager launches if building the graph fails.
+template <typename R>
+static int precond_vin(const Ctx& c, void** z) {
+    SolverState* S = c.S;
+    const GridOp& G = c.op->g;
+    const double kd[3] = {c.o->mg_shift_re, c.o->mg_shift, c.o->mg_omega};
+    const int ki[9] = {c.nrhs, static_cast<int>(sizeof(R)), c.o->mg_pre, c.o->mg_post, c.o->mg_coarse_sweeps,
+                       G.plain_ry[0], G.plain_ry[1], G.kernel_variant, G.wave_zchunk};
+    bool same = S->vgraph != nullptr;
+    for (int k = 0; k < 3 && same; ++k) same = S->gkey_d[k] == kd[k];
+    for (int k = 0; k < 9 && same; ++k) same = S->gkey_i[k] == ki[k];
+    if (!same) {
+        drop_graph(S);
+        GraphRec rec;
+        if (hipGraphCreate(&rec.graph, 0) != hipSuccess) {
+            S->graph_failed = true;
+            return precond<R>(c, S->vin, z);
+        }
+        void* out = nullptr;
+        graph_rec() = &rec;
+        const int st = vcycle<R>(c, 0, S->vin, &out);
+        graph_rec() = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (st || rec.err != hipSuccess || hipGraphInstantiate(&ex, rec.graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(rec.graph);
+            (void)hipGetLastError();
+            S->graph_failed = true;
+            if (st) return st;
+            return precond<R>(c, S->vin, z);
+        }
+        hipGraphDestroy(rec.graph);
+        S->vgraph = ex;
+        S->vgraph_out = out;
+        for (int k = 0; k < 3; ++k) S->gkey_d[k] = kd[k];
+        for (int k = 0; k < 9; ++k) S->gkey_i[k] = ki[k];
+    }
+    H27_CHECK_HIP(hipGraphLaunch(S->vgraph, c.s));
+    *z = S->vgraph_out;
+    return HELM27_OK;
+}
+
 static int read_host(std::vector<double>* h, const double* d, int n, hipStream_t s) {
     h->resize(n);
     H27_CHECK_HIP(hipMemcpyAsync(h->data(), d, n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -320,26 +379,33 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             break;
         }
         first = false;
-        if ((st = scale_by_norm<R, R>(r, S->V, N, nrhs, S->d_beta, 0, c.s))) return st;
+        const bool g = use_vgraph(c);
+        if ((st = scale_by_norm<R, R>(r, S->V, N, nrhs, S->d_beta, 0, c.s, g ? S->vin : nullptr))) return st;
         if ((st = givens_init(S->d_g, m, nrhs, S->d_beta, c.s))) return st;
         int k = 0;
         bool cyc_conv = false;
         for (int j = 0; j < m && it < max_it; ++j) {
             void* vj = static_cast<char*>(S->V) + static_cast<size_t>(j) * vstride * eb;
             void* z = nullptr;
-            if ((st = precond<R>(c, vj, &z))) return st;
+            if ((st = g ? precond_vin<R>(c, &z) : precond<R>(c, vj, &z))) return st;
             if ((st = launch_stencil<R>(G, MODE_APPLY, 1.0, 0.0, z, S->w, nullptr, 0.0, nrhs, c.s))) return st;
-            if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_hcol, ldh, 0, c.s)))
+            // classical Gram-Schmidt, two passes: h = V^H w; w -= V h; h2 = V^H w
+            // (h += h2 in the same reduction); w -= V h2 with ||w|| in the same pass
+            if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_hcol, nullptr, ldh,
+                              c.s)))
                 return st;
-            if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_hcol, ldh, S->w, N, nrhs, c.s))) return st;
-            if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_htmp, ldh, 0, c.s)))
+            if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_hcol, ldh, S->w, N, nrhs, S->d_partial, S->max_blocks,
+                                    nullptr, c.s)))
                 return st;
-            if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_htmp, ldh, S->w, N, nrhs, c.s))) return st;
-            hipLaunchKernelGGL(hadd_kernel, dim3((nrhs * ldh + 255) / 256), dim3(256), 0, c.s, S->d_hcol, S->d_htmp,
-                               nrhs * ldh);
-            if ((st = norms<R>(S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_nrm, c.s))) return st;
+            if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_htmp, S->d_hcol,
+                              ldh, c.s)))
+                return st;
+            if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_htmp, ldh, S->w, N, nrhs, S->d_partial, S->max_blocks,
+                                    S->d_nrm, c.s)))
+                return st;
             void* vj1 = static_cast<char*>(S->V) + static_cast<size_t>(j + 1) * vstride * eb;
-            if ((st = scale_by_norm<R, R>(S->w, vj1, N, nrhs, S->d_nrm, 0, c.s))) return st;
+            if ((st = scale_by_norm<R, R>(S->w, vj1, N, nrhs, S->d_nrm, 0, c.s, g && j + 1 < m ? S->vin : nullptr)))
+                return st;
             if ((st = givens_step(j, m, nrhs, S->d_hcol, ldh, S->d_nrm, S->d_H, S->d_cs, S->d_sn, S->d_g, S->d_est, c.s)))
                 return st;
             ++it;
@@ -358,9 +424,14 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             }
         }
         if ((st = upper_solve(k, m, nrhs, S->d_H, S->d_g, S->d_y, ldh, c.s))) return st;
-        if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->tmp, N, nrhs, 0, c.s))) return st;
         void* z = nullptr;
-        if ((st = precond<R>(c, S->tmp, &z))) return st;
+        if (g) {
+            if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->vin, N, nrhs, 0, c.s))) return st;
+            if ((st = precond_vin<R>(c, &z))) return st;
+        } else {
+            if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->tmp, N, nrhs, 0, c.s))) return st;
+            if ((st = precond<R>(c, S->tmp, &z))) return st;
+        }
         if ((st = add_inplace<R>(x, z, vstride, c.s))) return st;
         if (cyc_conv) {
             *conv = true;
@@ -477,7 +548,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->mg_post = 2;
     o->mg_omega = 0.6;
     o->mg_coarse_sweeps = 5;
-    o->use_graph = 0;
+    o->use_graph = 1;
     o->verbose = 0;
 }
 
@@ -578,11 +649,12 @@ void h27::solver_trim(helm27_op* op) {
 size_t h27::solve_footprint(int64_t N, int nrhs, int restart, int precision, int levels) {
     const double e = precision == HELM27_C128 ? 16.0 : 8.0;   // complex element bytes, inner precision
     const double n = static_cast<double>(N) * nrhs;
-    double bytes = n * e * (restart + 1 + 4);                   // Krylov basis, w, e, rin, tmp
+    double bytes = n * e * (restart + 1 + 5);                   // Krylov basis, w, e, rin, tmp, vin
     double lv = 0, f = 1;
     for (int l = 0; l < levels; ++l, f /= 8) lv += f * (l == 0 ? 3 : 4);
     bytes += n * e * lv;                                        // multigrid vectors
     bytes += n * 16.0 * 2;                                      // FP64 residual and right-hand side
     bytes += static_cast<double>(N) * 7.0;                      // coarse grids (velocity + index + ...)
+    bytes += static_cast<double>(nrhs) * (restart + 1) * 1024 * 16;   // reduction partials
     return static_cast<size_t>(bytes * 1.05) + (16u << 20);
 }
