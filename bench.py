@@ -63,27 +63,90 @@ def apply_timing(op, torch, nrhs=1, reps=200, dtype=None):
     return sec, alg_bytes
 
 
-def apply_only(args, torch, api, synth):
-    """FP32 recompute apply on a large grid (working set well beyond the 256 MB
+def large_apply(ctx, torch, synth, dims, nrhs=1, reps=50, dtype="c64"):
+    """Recompute apply on a large grid (working set well beyond the 256 MB
     MALL): seeded random-field model, h = 25 m, f = 10 Hz, 8-node PML."""
-    dims = tuple(int(v) for v in args.grid.split(","))
     h, f, npml = 25.0, 10.0, 8
     c = synth.random_field_model(dims, h, seed=3)
-    ctx = api.Context(0)
     tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
     op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, f, npml=npml)
-    calib = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    dt = torch.complex64 if dtype == "c64" else torch.complex128
+    sec, alg = apply_timing(op, torch, nrhs=nrhs, reps=reps, dtype=dt)
+    achieved = alg / sec / 1e9
+    return {"grid": list(dims), "nrhs": nrhs, "dtype": dtype, "apply_us": sec * 1e6,
+            "gpts": op.N * nrhs / sec / 1e9, "alg_bytes": alg, "GBs": achieved, "frac": achieved / HBM_PEAK_GBS}
+
+
+def calibration_copy(torch, mib=256):
+    """A plain device copy of known size, the reference for hardware byte counters."""
+    calib = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
     calib_dst = torch.empty_like(calib)
     for _ in range(3):
         calib_dst.copy_(calib)
     torch.cuda.synchronize()
-    del calib, calib_dst
-    dt = torch.complex64 if args.apply_dtype == "c64" else torch.complex128
-    sec, alg = apply_timing(op, torch, nrhs=args.nrhs, reps=args.apply_reps, dtype=dt)
-    achieved = alg / sec / 1e9
-    print(json.dumps({"grid": dims, "nrhs": args.nrhs, "dtype": args.apply_dtype, "apply_us": sec * 1e6,
-                      "gpts": op.N * args.nrhs / sec / 1e9, "alg_bytes": alg,
-                      "GBs": achieved, "frac": achieved / HBM_PEAK_GBS}), flush=True)
+
+
+def apply_only(args, torch, api, synth):
+    dims = tuple(int(v) for v in args.grid.split(","))
+    ctx = api.Context(0)
+    calibration_copy(torch)
+    print(json.dumps(large_apply(ctx, torch, synth, dims, args.nrhs, args.apply_reps, args.apply_dtype)), flush=True)
+
+
+def serving(args, torch, api, synth):
+    """Serving mix: Poisson arrivals of solve requests over seeded random-field
+    models (frequencies 2.5-10 Hz, h = 1500 / (4 f) so the smallest G is about
+    4, grids 64^3 / 96^3 / 128^2 x 64, 1-16 surface sources each), served by
+    the request loop (mixed precision, all of a request's sources as one
+    multi-RHS solve, up to 4 requests on the device at once, admission by
+    HBM footprint); then the same requests as plain FP64 single-RHS solves
+    one after another.  Both reach relative residual 1e-6."""
+    reqs = synth.serving_requests(args.serve_requests, seed=11, rate_hz=args.serve_rate,
+                                  dims_choices=((64, 64, 64), (96, 96, 96), (128, 128, 64)), nrhs_max=16)
+    models = [synth.random_field_model(r["dims"], r["h"], seed=r["model_seed"] % 1000003) for r in reqs]
+    srcs = [synth.surface_sources(r["dims"], r["nrhs"], 9, 10) for r in reqs]
+    table = (2.5, 60.0, 0.05, 1e-3)
+    ctx = api.Context(0)
+    srv = api.Server(ctx, max_slots=4, table=table, tol=1e-6)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, v, sr in zip(reqs, models, srcs):
+        wait = t0 + r["t_arrival"] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(v, r["h"], r["freq"], sr, npml=8, model_key=r["id"] + 1)[0])
+    res = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - t0
+    srv.stop()
+    lat = np.array([(x["t_done"] - x["t_submit"]) * 1e3 for x in res])
+    nrhs_tot = int(sum(r["nrhs"] for r in reqs))
+    ok = all(x["status"] == 0 and x["converged"] == 1 for x in res)
+    # the same requests as plain FP64 single-RHS solves, one after another
+    tab = ctx.build_table(*table)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    worst = 0.0
+    ok64 = True
+    for r, v, sr in zip(reqs, models, srcs):
+        op = ctx.assemble(tab, v, r["h"], r["freq"], npml=8)
+        for s1 in sr:
+            _, st = op.solve([s1], tol=1e-6, precision="fp64")
+            ok64 = ok64 and st["converged"] == 1
+            worst = max(worst, st["max_relres"])
+        del op
+    torch.cuda.synchronize()
+    wall64 = time.perf_counter() - t1
+    return {
+        "requests": len(reqs), "rhs": nrhs_tot, "arrival_rate_hz": args.serve_rate,
+        "mixed_multi_rhs_serving": {"rhs_per_s": nrhs_tot / wall, "requests_per_s": len(reqs) / wall,
+                                    "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+                                    "p99_ms": float(np.percentile(lat, 99)), "all_converged": ok,
+                                    "max_relres": max(x["max_relres"] for x in res)},
+        "fp64_single_rhs": {"rhs_per_s": nrhs_tot / wall64, "wall_s": wall64, "all_converged": ok64,
+                            "max_relres": worst},
+        "speedup_rhs_per_s": (nrhs_tot / wall) / (nrhs_tot / wall64),
+        "note": "serving wall time includes waiting for Poisson arrivals; FP64 baseline runs back to back",
+    }
 
 
 def cpu_baseline(c, W7, seconds=10.0):
@@ -121,6 +184,9 @@ def main():
     ap.add_argument("--grid", type=str, default="400,400,200")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--apply-dtype", choices=("c64", "c128"), default="c64")
+    ap.add_argument("--no-large", action="store_true", help="skip the 400x400x200 apply roofline")
+    ap.add_argument("--serve-requests", type=int, default=16, help="serving-mix requests (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="serving-mix Poisson arrival rate (1/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded path is a design "
@@ -143,15 +209,26 @@ def main():
     ctx = api.Context(0)
     gmin, gmax, dg, lam = wl["table"]
 
+    phases = {"table": [], "assemble": [], "solve": []}
+
     def step():
+        t0 = time.perf_counter()
         tab = ctx.build_table(gmin, gmax, dg, lam)
+        t1 = time.perf_counter()
         op = ctx.assemble(tab, c_dev, h, f, npml=npml)
+        t2 = time.perf_counter()
         u, st = op.solve([wl["src"]], tol=wl["tol"])
+        t3 = time.perf_counter()
+        phases["table"].append(t1 - t0)
+        phases["assemble"].append(t2 - t1)
+        phases["solve"].append(t3 - t2)
         return op, u, st
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    for v in phases.values():
+        v.clear()
     lat = []
     stats = None
     t_start = time.perf_counter()
@@ -163,12 +240,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 
-    # calibration for hardware byte counters: a plain device copy of known size
-    calib = torch.empty(16 << 20, dtype=torch.float32, device="cuda")
-    calib_dst = torch.empty_like(calib)
-    for _ in range(3):
-        calib_dst.copy_(calib)
-    torch.cuda.synchronize()
+    calibration_copy(torch, 64)
 
     # apply roofline on the workload's operator (launch shape of the solve's matvec)
     tab = ctx.build_table(gmin, gmax, dg, lam)
@@ -200,15 +272,22 @@ def main():
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "solve": {"inner_iters": stats["inner_iters"], "outer_iters": stats["outer_iters"],
                   "relres": stats["max_relres"], "converged": bool(stats["converged"])},
+        "phase_ms": {k: float(np.mean(v) * 1e3) for k, v in phases.items()},
         "apply_gpts": op.N / sec / 1e9,
         "apply_us": sec * 1e6,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "helm27_apply recompute FP32, 1 RHS (plain-box + PML-frame launches)",
+                     "kernel": "helm27_apply recompute FP32, 1 RHS (wave27 kernel, box and PML frame in one launch)",
                      "alg_bytes_per_launch": alg},
     }
+    del op, tab
+    if not args.no_large:
+        out["roofline_large"] = dict(large_apply(ctx, torch, synth, (400, 400, 200), reps=50), bound="hbm",
+                                     peak=HBM_PEAK_GBS, unit="GB/s")
+    if args.serve_requests > 0:
+        out["serving"] = serving(args, torch, api, synth)
     if not args.no_cpu_baseline:
-        W7 = tab.weights()[0]
+        W7 = ctx.build_table(gmin, gmax, dg, lam).weights()[0]
         out["cpu_baseline"] = cpu_baseline(c_host, W7, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
