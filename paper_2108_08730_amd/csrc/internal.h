@@ -197,12 +197,16 @@ int host_index(float c, double fh, double gmin, double dg, int n_g);
 // kernels (kernels_*.hip): host-side launchers
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
                         int n_g, unsigned long long* d_nclamp, hipStream_t s);
-// y = A u (MODE_APPLY), y = b - A u (MODE_RESID) or y = u + omega_j D^-1 (b - A u)
-// (MODE_JACOBI) with A's mass scaled by (shift_re + i shift_im); (1, 0) is the
+// y = A u (MODE_APPLY), y = b - A u (MODE_RESID), y = u + omega_j D^-1 (b - A u)
+// (MODE_JACOBI) or y = omega_j D^-1 b (MODE_JACOBI0, u not read; wavefront
+// kernel only) with A's mass scaled by (shift_re + i shift_im); (1, 0) is the
 // physical operator.  R = float | double.
 template <typename R>
 int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, const void* u, void* y,
                    const void* b, double omega_j, int nrhs, hipStream_t s);
+// whether launch_stencil runs the wavefront kernel on this grid (which also
+// provides the zero-iterate Jacobi mode)
+bool stencil_wave_path(const GridOp& g, bool fp64);
 template <typename R>
 int launch_fill_stored(const GridOp& g, void* coef, double shift_re, double shift_im, hipStream_t s);
 template <typename R>

@@ -400,6 +400,16 @@ static int launch_mode(const StencilArgs<R>& args, dim3 grid, hipStream_t s) {
     return HELM27_OK;
 }
 
+// whether the wavefront kernel serves this grid (else the LDS-tiled kernel)
+bool stencil_wave_path(const GridOp& g, bool fp64) {
+    const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
+    // the wavefront kernel addresses one right-hand side with 32-bit buffer
+    // offsets: its byte size must stay below 2^31
+    return g.kernel_variant == 0 && n_tab > 0 &&
+           static_cast<int64_t>(g.N) * (fp64 ? 16 : 8) < (int64_t(1) << 31) &&
+           wave_lds_bytes(g.d_row_f ? 0 : n_tab, g.nz, fp64) <= 64 * 1024;
+}
+
 template <typename R>
 int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, const void* u, void* y, const void* b,
                    double omega_j, int nrhs, hipStream_t s) {
@@ -429,12 +439,9 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     a.omega_j = static_cast<R>(omega_j);
     // Default: the wavefront-per-tile kernel for the whole grid (box + frame
     // work items in one launch).  Variant 1 keeps the LDS-tiled kernel below.
-    const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
-    // the wavefront kernel addresses one right-hand side with 32-bit buffer
-    // offsets: its byte size must stay below 2^31
-    const bool use_wave = g.kernel_variant == 0 && n_tab > 0 &&
-                          static_cast<int64_t>(g.N) * static_cast<int64_t>(2 * sizeof(R)) < (int64_t(1) << 31) &&
-                          wave_lds_bytes(a.g.rowcoef ? 0 : n_tab, g.nz, sizeof(R) == 8) <= 64 * 1024;
+    const int n_tab = g.idx_hi - g.idx_lo + 1;
+    const bool use_wave = stencil_wave_path(g, sizeof(R) == 8);
+    if (mode == MODE_JACOBI0 && !use_wave) return HELM27_EINVAL;   // wavefront kernel only
     if (use_wave) {
         WaveArgs<R> w{};
         w.g = a.g;

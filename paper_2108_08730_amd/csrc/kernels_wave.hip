@@ -116,6 +116,7 @@ template <typename R, int MODE>
 __device__ __forceinline__ Cx<R> finish(R omega_j, Cx<R> acc, Cx<R> diag, Cx<R> xcen,
                                         typename V2<R>::T bb) {
     if (MODE == MODE_APPLY) return acc;
+    if (MODE == MODE_JACOBI0) return omega_j * (Cx<R>{bb.x, bb.y} * inv_of(diag));
     const Cx<R> rr{bb.x - acc.re, bb.y - acc.im};
     if (MODE == MODE_RESID) return rr;
     return xcen + omega_j * (rr * inv_of(diag));
@@ -232,6 +233,11 @@ struct ItemBuf {
     template <int NK>
     __device__ __forceinline__ void load_plane(int q, int nz, const unsigned (&ofs)[NK],
                                                typename V2<R>::T (&L)[NK]) const {
+        if (MODE == MODE_JACOBI0) {   // the iterate is zero: nothing to read
+#pragma unroll
+            for (int k = 0; k < NK; ++k) L[k] = typename V2<R>::T{};
+            return;
+        }
         const bool in = q >= 0 && q < nz;
         const Rsrc r = rsrc(u, in ? vbytes : 0u);
         const unsigned so = in ? static_cast<unsigned>(q) * plane_b : 0u;
@@ -358,7 +364,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
                     acc = st;
                     rmac(acc, kap, ms);
                 }
-                if (MODE == MODE_JACOBI) {
+                if (MODE == MODE_JACOBI || MODE == MODE_JACOBI0) {
                     const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
                     diag = s[1] * t0 + x0 * xz + m[0] * (kc * xz);
                 } else {
@@ -528,7 +534,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
                 rmac(acc, kap, mass);
             }
             Cx<R> diag = zero<R>();
-            if (MODE == MODE_JACOBI) {
+            if (MODE == MODE_JACOBI || MODE == MODE_JACOBI0) {
                 const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
                 const Factors<R>& Q = FQ[r];
                 const Cx<R> ac = xLQ[r];
@@ -720,6 +726,9 @@ int launch_wave(const WaveArgs<R>& a, int mode, bool shifted, int ry, int rq, hi
         case MODE_JACOBI:
             return shifted ? launch_wave_mode<R, MODE_JACOBI, true>(a, ry, s)
                            : launch_wave_mode<R, MODE_JACOBI, false>(a, ry, s);
+        case MODE_JACOBI0:
+            return shifted ? launch_wave_mode<R, MODE_JACOBI0, true>(a, ry, s)
+                           : launch_wave_mode<R, MODE_JACOBI0, false>(a, ry, s);
         default:
             return HELM27_EINVAL;
     }

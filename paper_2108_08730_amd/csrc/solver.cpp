@@ -245,11 +245,19 @@ static int vcycle(const Ctx& c, int l, const void* b, void** out) {
     void* x = S->X[l];
     void* t = S->T[l];
     int st;
-    if ((st = fill_zero(x, bytes, c.s))) return st;
     const bool coarsest = l == S->levels - 1;
     const double a = c.o->mg_shift_re, bshift = c.o->mg_shift;
     const int pre = coarsest ? c.o->mg_coarse_sweeps : c.o->mg_pre;
-    for (int k = 0; k < pre; ++k) {
+    // the iterate starts at zero: the first sweep is omega D^-1 b
+    const bool zero_sweep = pre > 0 && stencil_wave_path(G, sizeof(R) == 8);
+    if (zero_sweep) {
+        if ((st = launch_stencil<R>(G, MODE_JACOBI0, a, bshift, nullptr, t, b, c.o->mg_omega, c.nrhs, c.s)))
+            return st;
+        std::swap(x, t);
+    } else if ((st = fill_zero(x, bytes, c.s))) {
+        return st;
+    }
+    for (int k = zero_sweep ? 1 : 0; k < pre; ++k) {
         if ((st = launch_stencil<R>(G, MODE_JACOBI, a, bshift, x, t, b, c.o->mg_omega, c.nrhs, c.s))) return st;
         std::swap(x, t);
     }

@@ -5,7 +5,9 @@
 
 namespace h27 {
 
-enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
+// MODE_JACOBI0: the first damped-Jacobi sweep from a zero iterate,
+// y = omega D^-1 b (the input vector is not read)
+enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2, MODE_JACOBI0 = 3 };
 
 constexpr int kPlainTX = 64;   // plain tile width (one wavefront row along x)
 constexpr int kPlainTY = 4;    // thread rows per block
