@@ -33,6 +33,24 @@ WORKLOAD = dict(name="gradz101", dims=(101, 101, 101), h=25.0, freq=5.0, npml=10
                 src=(50, 50, 11), tol=1e-6, table=(3.0, 30.0, 0.05, 1e-3))
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of the apply kernel from the committed hardware-counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wave27_apply_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        for src, digest in rec["sources_sha256"].items():
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != digest:
+                    return None
+        return float(rec[key]["traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _ensure_lib():
     lib = os.path.join(ROOT, "paper_2108_08730_amd", "libhelm27.so")
     if not os.path.exists(lib):
@@ -276,14 +294,15 @@ def main():
         "apply_gpts": op.N / sec / 1e9,
         "apply_us": sec * 1e6,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("gradz101"),
                      "kernel": "helm27_apply recompute FP32, 1 RHS (wave27 kernel, box and PML frame in one launch)",
                      "alg_bytes_per_launch": alg},
     }
     del op, tab
     if not args.no_large:
         out["roofline_large"] = dict(large_apply(ctx, torch, synth, (400, 400, 200), reps=50), bound="hbm",
-                                     peak=HBM_PEAK_GBS, unit="GB/s")
+                                     peak=HBM_PEAK_GBS, unit="GB/s",
+                                     traffic=measured_traffic("large_400x400x200"))
     if args.serve_requests > 0:
         out["serving"] = serving(args, torch, api, synth)
     if not args.no_cpu_baseline:
