@@ -213,8 +213,10 @@ typedef struct {
     double inner_tol;    /* relative reduction asked of each inner solve (default 1e-4) */
     int    precision;    /* HELM27_C64: FP32 inner + FP64 refinement (default);
                             HELM27_C128: everything in FP64 */
-    int    mg_levels;    /* multigrid levels (default 4; 0 = no preconditioner) */
-    double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 1) */
+    int    mg_levels;    /* multigrid levels, 1..8; -1 (default) = halve while the coarser
+                            grid keeps >= 8192 points (4 levels for 400x400x200, 3 for
+                            101^3, 2 for 41^3); 0 = no preconditioner */
+    double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 0.8) */
     int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
     double mg_omega;     /* Jacobi damping (default 0.6) */
     int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 5) */
@@ -223,7 +225,10 @@ typedef struct {
                             same kernels as the eager launches, so the same
                             results); 0 = eager launches (default 1) */
     int    verbose;
-    double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0.5) */
+    double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0.4) */
+    int    reorth_always;/* 1: second classical Gram-Schmidt pass at every Arnoldi step;
+                            0 (default): per right-hand side only when the first pass
+                            leaves less than 1/sqrt(2) of the vector's norm */
 } helm27_solve_opts;
 
 typedef struct {

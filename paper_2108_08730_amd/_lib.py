@@ -39,7 +39,8 @@ class SolveOpts(C.Structure):
                 ("max_outer", C.c_int), ("inner_tol", C.c_double), ("precision", C.c_int),
                 ("mg_levels", C.c_int), ("mg_shift", C.c_double), ("mg_pre", C.c_int),
                 ("mg_post", C.c_int), ("mg_omega", C.c_double), ("mg_coarse_sweeps", C.c_int),
-                ("use_graph", C.c_int), ("verbose", C.c_int), ("mg_shift_re", C.c_double)]
+                ("use_graph", C.c_int), ("verbose", C.c_int), ("mg_shift_re", C.c_double),
+                ("reorth_always", C.c_int)]
 
 
 class SolveStats(C.Structure):

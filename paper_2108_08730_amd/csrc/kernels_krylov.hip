@@ -131,19 +131,41 @@ template int norms<float>(const void*, int64_t, int, double*, int, double*, hipS
 template int norms<double>(const void*, int64_t, int, double*, int, double*, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Selective second Gram-Schmidt pass: a right-hand side is orthogonalised a
+// second time only if the first pass cancelled more than 1 - 1/sqrt(2) of its
+// norm, ||w'|| < ||w|| / sqrt(2) (the "twice is enough" test of Kahan and
+// Parlett, as used by Daniel, Gragg, Kaufman and Stewart, 1976).  The test
+// runs on the device per right-hand side; without the gate every pass runs.
+__device__ __forceinline__ bool second_pass(const double* nrm0, const double* nrm1, int rhs) {
+    if (!nrm0) return true;
+    return nrm1[rhs] * nrm1[rhs] * 2.0 < nrm0[rhs] * nrm0[rhs];
+}
+
 // Multi-vector dot products h[rhs][j] = sum_i conj(V_j[rhs][i]) w[rhs][i] for
 // all j < J in one launch (8 basis vectors per pass over the block's
-// elements).  V is [m+1][nrhs][N]; partial is [nrhs][J][nb] (complex as 2
-// doubles).
+// elements), plus |w|^2 in slot J when self_norm is set.  V is [m+1][nrhs][N];
+// partial is [nrhs][J + self_norm][nb] (complex as 2 doubles).  With the gate
+// (nrm0, nrm1) a right-hand side that needs no second pass writes zeros.
 template <typename R>
 __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
                                                                  int J, const typename V2<R>::T* __restrict__ w,
-                                                                 int64_t N, double* __restrict__ partial) {
+                                                                 int64_t N, double* __restrict__ partial, int self_norm,
+                                                                 const double* __restrict__ nrm0,
+                                                                 const double* __restrict__ nrm1) {
     __shared__ double sh[16 * 4];
     const int rhs = blockIdx.y;
+    const int JS = J + self_norm;
+    if (!second_pass(nrm0, nrm1, rhs)) {
+        if (threadIdx.x < JS) {
+            double* p = partial + ((static_cast<int64_t>(rhs) * JS + threadIdx.x) * gridDim.x + blockIdx.x) * 2;
+            p[0] = 0.0;
+            p[1] = 0.0;
+        }
+        return;
+    }
     const typename V2<R>::T* wr = w + static_cast<int64_t>(rhs) * N;
-    for (int j0 = 0; j0 < J; j0 += 8) {
-        const int jn = J - j0 < 8 ? J - j0 : 8;
+    for (int j0 = 0; j0 < JS; j0 += 8) {
+        const int jn = JS - j0 < 8 ? JS - j0 : 8;
         double acc[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) acc[k] = 0.0;
@@ -153,8 +175,9 @@ __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename 
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 if (k < jn) {
+                    const int j = j0 + k;
                     const typename V2<R>::T v =
-                        V[static_cast<int64_t>(j0 + k) * vstride + static_cast<int64_t>(rhs) * N + i];
+                        j < J ? V[static_cast<int64_t>(j) * vstride + static_cast<int64_t>(rhs) * N + i] : wv;
                     // conj(v) * w
                     acc[2 * k] += static_cast<double>(v.x) * wv.x + static_cast<double>(v.y) * wv.y;
                     acc[2 * k + 1] += static_cast<double>(v.x) * wv.y - static_cast<double>(v.y) * wv.x;
@@ -164,7 +187,7 @@ __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename 
         block_sum<16>(acc, sh);
         if (threadIdx.x == 0) {
             for (int k = 0; k < jn; ++k) {
-                double* p = partial + ((static_cast<int64_t>(rhs) * J + j0 + k) * gridDim.x + blockIdx.x) * 2;
+                double* p = partial + ((static_cast<int64_t>(rhs) * JS + j0 + k) * gridDim.x + blockIdx.x) * 2;
                 p[0] = acc[2 * k];
                 p[1] = acc[2 * k + 1];
             }
@@ -172,20 +195,27 @@ __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename 
     }
 }
 
-// h[rhs * ldh + j] = sum_b partial[rhs][j][b] (and hsum[rhs * ldh + j] += the
-// same when hsum is given); one block per (rhs, j), summed in a fixed order
-__global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, int J, double2* __restrict__ h,
-                                   double2* __restrict__ hsum, int ldh) {
+// h[rhs * ldh + j] = sum_b partial[rhs][j][b] for j < J (and hsum[...] += the
+// same when hsum is given); slot J (self_norm) gives selfn[rhs] = sqrt of the
+// real part.  One block per (rhs, slot), summed in a fixed order.
+__global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, int J, int self_norm,
+                                   double2* __restrict__ h, double2* __restrict__ hsum, int ldh,
+                                   double* __restrict__ selfn) {
     __shared__ double sh[8];
-    const int rhs = blockIdx.x / J, j = blockIdx.x % J;
+    const int JS = J + self_norm;
+    const int rhs = blockIdx.x / JS, j = blockIdx.x % JS;
     double acc[2] = {0.0, 0.0};
-    const double* p = partial + (static_cast<int64_t>(rhs) * J + j) * nb * 2;
+    const double* p = partial + (static_cast<int64_t>(rhs) * JS + j) * nb * 2;
     for (int b = threadIdx.x; b < nb; b += kRedBlock) {
         acc[0] += p[2 * b];
         acc[1] += p[2 * b + 1];
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
+        if (j == J) {
+            selfn[rhs] = sqrt(acc[0] > 0.0 ? acc[0] : 0.0);
+            return;
+        }
         double2* o = h + static_cast<int64_t>(rhs) * ldh + j;
         o->x = acc[0];
         o->y = acc[1];
@@ -199,35 +229,46 @@ __global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, i
 
 template <typename R>
 int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nrhs, double* d_partial, int max_blocks,
-         double2* d_h, double2* d_hsum, int ldh, hipStream_t s) {
+         double2* d_h, double2* d_hsum, int ldh, hipStream_t s, double* d_selfnrm, const double* d_gate0,
+         const double* d_gate1) {
     if (J <= 0 || J > ldh) return HELM27_EINVAL;
     unsigned nb = grid_for(N);
     if (nb > static_cast<unsigned>(max_blocks)) nb = max_blocks;
+    const int self_norm = d_selfnrm ? 1 : 0;
     hipLaunchKernelGGL(mdot_partial_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
                        static_cast<const typename V2<R>::T*>(V), vstride, J,
-                       static_cast<const typename V2<R>::T*>(w), N, d_partial);
-    hipLaunchKernelGGL(mdot_reduce_kernel, dim3(nrhs * J), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb), J,
-                       d_h, d_hsum, ldh);
+                       static_cast<const typename V2<R>::T*>(w), N, d_partial, self_norm, d_gate0, d_gate1);
+    hipLaunchKernelGGL(mdot_reduce_kernel, dim3(nrhs * (J + self_norm)), dim3(kRedBlock), 0, s, d_partial,
+                       static_cast<int>(nb), J, self_norm, d_h, d_hsum, ldh, d_selfnrm);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
 template int mdot<float>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, double2*, int,
-                         hipStream_t);
+                         hipStream_t, double*, const double*, const double*);
 template int mdot<double>(const void*, int64_t, int, const void*, int64_t, int, double*, int, double2*, double2*, int,
-                          hipStream_t);
+                          hipStream_t, double*, const double*, const double*);
 
 // w[rhs] -= sum_{j < J} V_j[rhs] * hc[rhs][j] where hc are the coefficients of
 // the current pass (FP64 on the device, applied in the vector precision);
 // with partial != null also partial[rhs][blk] = sum of |w_new|^2 over the
-// block's elements (FP64)
+// block's elements (FP64).  With the gate (nrm0, nrm1) a right-hand side that
+// needs no second pass keeps w and reports |w|^2 = nrm1^2 (block 0).
 template <typename R>
 __global__ __launch_bounds__(kRedBlock) void cgs_update_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
                                                                int J, const double2* __restrict__ hc, int ldh,
                                                                typename V2<R>::T* __restrict__ w, int64_t N,
-                                                               double* __restrict__ partial) {
+                                                               double* __restrict__ partial,
+                                                               const double* __restrict__ nrm0,
+                                                               const double* __restrict__ nrm1) {
     __shared__ R hs[2 * 64];
     __shared__ double sh[4];
     const int rhs = blockIdx.y;
+    if (!second_pass(nrm0, nrm1, rhs)) {
+        if (partial && threadIdx.x == 0)
+            partial[static_cast<int64_t>(rhs) * gridDim.x + blockIdx.x] =
+                blockIdx.x == 0 ? nrm1[rhs] * nrm1[rhs] : 0.0;
+        return;
+    }
     for (int j = threadIdx.x; j < J; j += kRedBlock) {
         const double2 c = hc[static_cast<int64_t>(rhs) * ldh + j];
         hs[2 * j] = static_cast<R>(c.x);
@@ -256,13 +297,14 @@ __global__ __launch_bounds__(kRedBlock) void cgs_update_kernel(const typename V2
 
 template <typename R>
 int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int ldh, void* w, int64_t N, int nrhs,
-               double* d_partial, int max_blocks, double* d_nrm, hipStream_t s) {
+               double* d_partial, int max_blocks, double* d_nrm, hipStream_t s, const double* d_gate0,
+               const double* d_gate1) {
     if (J > 64) return HELM27_EINVAL;
     unsigned nb = grid_for(N);
     if (d_nrm && nb > static_cast<unsigned>(max_blocks)) nb = max_blocks;
     hipLaunchKernelGGL(cgs_update_kernel<R>, dim3(nb, nrhs), dim3(kRedBlock), 0, s,
                        static_cast<const typename V2<R>::T*>(V), vstride, J, d_hc, ldh,
-                       static_cast<typename V2<R>::T*>(w), N, d_nrm ? d_partial : nullptr);
+                       static_cast<typename V2<R>::T*>(w), N, d_nrm ? d_partial : nullptr, d_gate0, d_gate1);
     if (d_nrm)
         hipLaunchKernelGGL(reduce_rows_kernel, dim3(nrhs), dim3(kRedBlock), 0, s, d_partial, static_cast<int>(nb),
                            d_nrm, 1);
@@ -270,9 +312,9 @@ int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int l
     return HELM27_OK;
 }
 template int cgs_update<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, double*, int,
-                               double*, hipStream_t);
+                               double*, hipStream_t, const double*, const double*);
 template int cgs_update<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, double*, int,
-                                double*, hipStream_t);
+                                double*, hipStream_t, const double*, const double*);
 
 // out[rhs] = x[rhs] * f(nrm[rhs]): mode 0 -> 1/nrm (0 if nrm == 0), mode 1 -> nrm
 template <typename Ri, typename Ro>

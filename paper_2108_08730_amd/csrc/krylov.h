@@ -13,14 +13,22 @@ int norms(const void* x, int64_t N, int nrhs, double* d_partial, int max_blocks,
 // d_h[rhs * ldh + j] = <V_j[rhs], w[rhs]> for j < J (J <= ldh), and
 // d_hsum[...] += the same when d_hsum is not null; d_partial holds
 // nrhs * ldh * max_blocks * 2 doubles
+// d_selfnrm (optional): also ||w[rhs]||.  d_gate0 / d_gate1 (optional): the
+// norms of w before / after a first Gram-Schmidt pass; a right-hand side with
+// ||after|| >= ||before|| / sqrt(2) gets h = 0 without reading V (no second
+// pass needed).  d_partial holds nrhs * (ldh + 1) * max_blocks * 2 doubles.
 template <typename R>
 int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nrhs, double* d_partial, int max_blocks,
-         double2* d_h, double2* d_hsum, int ldh, hipStream_t s);
+         double2* d_h, double2* d_hsum, int ldh, hipStream_t s, double* d_selfnrm = nullptr,
+         const double* d_gate0 = nullptr, const double* d_gate1 = nullptr);
 // w[rhs] -= sum_{j<J} V_j[rhs] d_hc[rhs * ldh + j]; with d_nrm not null also
-// d_nrm[rhs] = ||w_new[rhs]|| (FP64, deterministic two-stage sum)
+// d_nrm[rhs] = ||w_new[rhs]|| (FP64, deterministic two-stage sum).  With the
+// gate, a right-hand side that needs no second pass keeps w and gets
+// d_nrm = d_gate1.
 template <typename R>
 int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int ldh, void* w, int64_t N, int nrhs,
-               double* d_partial, int max_blocks, double* d_nrm, hipStream_t s);
+               double* d_partial, int max_blocks, double* d_nrm, hipStream_t s, const double* d_gate0 = nullptr,
+               const double* d_gate1 = nullptr);
 // out = x / nrm (mode 0) or x * nrm (mode 1), per right-hand side; the same
 // values also to out2 when it is not null
 template <typename Ri, typename Ro>

@@ -46,6 +46,8 @@ struct SolverState {
     double2* d_hcol = nullptr;
     double2* d_htmp = nullptr;
     double* d_nrm = nullptr;
+    double* d_n0 = nullptr;          // ||w|| before / after the first Gram-Schmidt pass
+    double* d_n1 = nullptr;
     double* d_beta = nullptr;
     double* d_est = nullptr;
     double* d_rn = nullptr;
@@ -100,6 +102,24 @@ static int alloc(SolverState* S, void** p, size_t bytes) {
     }
     S->bufs.push_back(*p);
     return HELM27_OK;
+}
+
+// Automatic depth: halve the grid while the coarser grid keeps at least
+// 8192 points and 3 nodes per axis (at least two levels when possible, at
+// most eight).  Coarse grids below that size cost a launch per sweep while
+// doing almost no work.
+static int auto_levels(const GridOp& g) {
+    int nx = g.nx, ny = g.ny, nz = g.nz, levels = 1;
+    while (levels < 8) {
+        const int cx = (nx + 1) / 2, cy = (ny + 1) / 2, cz = (nz + 1) / 2;
+        if (cx < 3 || cy < 3 || cz < 3) break;
+        if (levels >= 2 && static_cast<int64_t>(cx) * cy * cz < 8192) break;
+        nx = cx;
+        ny = cy;
+        nz = cz;
+        ++levels;
+    }
+    return levels;
 }
 
 // Coarse grids: node i of level l+1 sits on node 2i of level l.
@@ -192,7 +212,7 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     if ((st = alloc(S, &p, static_cast<size_t>(N) * nrhs * sizeof(double2)))) return st;
     S->r64 = static_cast<double2*>(p);
     S->max_blocks = 1024;
-    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1 > 8 ? m + 1 : 8) * S->max_blocks * 2 * sizeof(double))))
+    if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 2 > 8 ? m + 2 : 8) * S->max_blocks * 2 * sizeof(double))))
         return st;
     S->d_partial = static_cast<double*>(p);
     const int ldh = m + 1;
@@ -202,8 +222,8 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->d_htmp = static_cast<double2*>(p);
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * ldh * sizeof(double2)))) return st;
     S->d_y = static_cast<double2*>(p);
-    double* dd[5];
-    for (int k = 0; k < 5; ++k) {
+    double* dd[7];
+    for (int k = 0; k < 7; ++k) {
         if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * sizeof(double)))) return st;
         dd[k] = static_cast<double*>(p);
     }
@@ -212,6 +232,8 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->d_est = dd[2];
     S->d_rn = dd[3];
     S->d_bn = dd[4];
+    S->d_n0 = dd[5];
+    S->d_n1 = dd[6];
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1) * m * sizeof(double2)))) return st;
     S->d_H = static_cast<double2*>(p);
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * m * sizeof(double)))) return st;
@@ -280,7 +302,7 @@ static int vcycle(const Ctx& c, int l, const void* b, void** out) {
 // z = M^-1 v (or z = v without preconditioner); returns the result buffer.
 template <typename R>
 static int precond(const Ctx& c, const void* v, void** z) {
-    if (c.S->levels <= 0 || c.o->mg_levels <= 0) {
+    if (c.S->levels <= 0 || c.o->mg_levels == 0) {
         *z = const_cast<void*>(v);
         return HELM27_OK;
     }
@@ -288,7 +310,7 @@ static int precond(const Ctx& c, const void* v, void** z) {
 }
 
 static bool use_vgraph(const Ctx& c) {
-    return c.o->use_graph && c.S->levels > 0 && c.o->mg_levels > 0 && !c.S->graph_failed;
+    return c.o->use_graph && c.S->levels > 0 && c.o->mg_levels != 0 && !c.S->graph_failed;
 }
 
 // The V-cycle on S->vin replayed from one hipGraph: the launch sequence
@@ -397,19 +419,22 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             void* z = nullptr;
             if ((st = g ? precond_vin<R>(c, &z) : precond<R>(c, vj, &z))) return st;
             if ((st = launch_stencil<R>(G, MODE_APPLY, 1.0, 0.0, z, S->w, nullptr, 0.0, nrhs, c.s))) return st;
-            // classical Gram-Schmidt, two passes: h = V^H w; w -= V h; h2 = V^H w
-            // (h += h2 in the same reduction); w -= V h2 with ||w|| in the same pass
+            // classical Gram-Schmidt: h = V^H w (and ||w||); w -= V h (and ||w||);
+            // then, per right-hand side only where the first pass cancelled
+            // more than 1 - 1/sqrt(2) of the norm: h2 = V^H w (h += h2 in the
+            // reduction) and w -= V h2; ||w|| of the result in the last pass
             if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_hcol, nullptr, ldh,
-                              c.s)))
+                              c.s, S->d_n0)))
                 return st;
             if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_hcol, ldh, S->w, N, nrhs, S->d_partial, S->max_blocks,
-                                    nullptr, c.s)))
+                                    S->d_n1, c.s)))
                 return st;
+            const double* g0 = c.o->reorth_always ? nullptr : S->d_n0;
             if ((st = mdot<R>(S->V, vstride, j + 1, S->w, N, nrhs, S->d_partial, S->max_blocks, S->d_htmp, S->d_hcol,
-                              ldh, c.s)))
+                              ldh, c.s, nullptr, g0, S->d_n1)))
                 return st;
             if ((st = cgs_update<R>(S->V, vstride, j + 1, S->d_htmp, ldh, S->w, N, nrhs, S->d_partial, S->max_blocks,
-                                    S->d_nrm, c.s)))
+                                    S->d_nrm, c.s, g0, S->d_n1)))
                 return st;
             void* vj1 = static_cast<char*>(S->V) + static_cast<size_t>(j + 1) * vstride * eb;
             if ((st = scale_by_norm<R, R>(S->w, vj1, N, nrhs, S->d_nrm, 0, c.s, g && j + 1 < m ? S->vin : nullptr)))
@@ -453,7 +478,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
 static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, const helm27_solve_opts* o,
                       helm27_solve_stats* stats, hipStream_t s) {
     SolverState* S = static_cast<SolverState*>(op->solver);
-    const int want_levels = o->mg_levels > 0 ? o->mg_levels : 0;
+    const int want_levels = o->mg_levels > 0 ? o->mg_levels : (o->mg_levels < 0 ? auto_levels(op->g) : 0);
     if (want_levels != S->req_levels) {
         free_workspace(S);
         free_hierarchy(S);
@@ -549,21 +574,22 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->max_outer = 10;
     o->inner_tol = 1e-4;
     o->precision = HELM27_C64;
-    o->mg_levels = 4;
-    o->mg_shift = 1.0;
-    o->mg_shift_re = 0.5;
+    o->mg_levels = -1;
+    o->mg_shift = 0.8;
+    o->mg_shift_re = 0.4;
     o->mg_pre = 2;
     o->mg_post = 2;
     o->mg_omega = 0.6;
     o->mg_coarse_sweeps = 5;
     o->use_graph = 1;
+    o->reorth_always = 0;
     o->verbose = 0;
 }
 
 static int check_opts(const helm27_solve_opts* o) {
     if (!(o->tol > 0) || o->restart < 1 || o->restart > 63 || o->max_inner < 1 || o->max_outer < 0 ||
         !(o->inner_tol > 0) || o->inner_tol >= 1 || (o->precision != HELM27_C64 && o->precision != HELM27_C128) ||
-        o->mg_levels < 0 || o->mg_levels > 8 || o->mg_pre < 0 || o->mg_post < 0 || o->mg_coarse_sweeps < 0 ||
+        o->mg_levels < -1 || o->mg_levels > 8 || o->mg_pre < 0 || o->mg_post < 0 || o->mg_coarse_sweeps < 0 ||
         !(o->mg_omega > 0) || !std::isfinite(o->mg_shift) || !std::isfinite(o->mg_shift_re))
         return HELM27_EINVAL;
     return HELM27_OK;
@@ -659,10 +685,11 @@ size_t h27::solve_footprint(int64_t N, int nrhs, int restart, int precision, int
     const double n = static_cast<double>(N) * nrhs;
     double bytes = n * e * (restart + 1 + 5);                   // Krylov basis, w, e, rin, tmp, vin
     double lv = 0, f = 1;
+    if (levels < 0) levels = 8;                                 // automatic depth: bound
     for (int l = 0; l < levels; ++l, f /= 8) lv += f * (l == 0 ? 3 : 4);
     bytes += n * e * lv;                                        // multigrid vectors
     bytes += n * 16.0 * 2;                                      // FP64 residual and right-hand side
     bytes += static_cast<double>(N) * 7.0;                      // coarse grids (velocity + index + ...)
-    bytes += static_cast<double>(nrhs) * (restart + 1) * 1024 * 16;   // reduction partials
+    bytes += static_cast<double>(nrhs) * (restart + 2) * 1024 * 16;   // reduction partials
     return static_cast<size_t>(bytes * 1.05) + (16u << 20);
 }
