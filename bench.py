@@ -58,40 +58,44 @@ def _ensure_lib():
         build()
 
 
-def apply_timing(op, torch, nrhs=1, reps=200, dtype=None):
-    """Average duration of helm27_apply (recompute) over `reps` launches
-    bracketed by HIP events on the stream the kernels run on."""
+def apply_timing(op, torch, nrhs=1, reps=200, dtype=None, variant="recompute"):
+    """Average duration of helm27_apply over `reps` launches bracketed by HIP
+    events on the stream the kernels run on, and the algorithmic bytes of one
+    launch (recompute: idx u16 + c f32 per point; stored: 27 complex
+    coefficients per point; plus u in and y out per right-hand side)."""
     dtype = dtype or torch.complex64
     stream = torch.cuda.current_stream()
     u = torch.randn((nrhs, op.N), dtype=dtype, device="cuda")
     y = torch.empty_like(u)
     for _ in range(5):
-        op.apply(u, y, stream=stream)
+        op.apply(u, y, variant=variant, stream=stream)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        op.apply(u, y, stream=stream)
+        op.apply(u, y, variant=variant, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) * 1e-3 / reps
     vb = 8 if dtype == torch.complex64 else 16
-    alg_bytes = (2 + 4 + 2 * vb * nrhs) * op.N        # idx u16 + c f32 + u in + y out
+    per_point = (2 + 4) if variant == "recompute" else 27 * vb
+    alg_bytes = (per_point + 2 * vb * nrhs) * op.N
     return sec, alg_bytes
 
 
-def large_apply(ctx, torch, synth, dims, nrhs=1, reps=50, dtype="c64"):
-    """Recompute apply on a large grid (working set well beyond the 256 MB
-    MALL): seeded random-field model, h = 25 m, f = 10 Hz, 8-node PML."""
+def large_apply(ctx, torch, synth, dims, nrhs=1, reps=50, dtype="c64", variant="recompute"):
+    """Apply on a large grid (working set well beyond the 256 MB MALL): seeded
+    random-field model, h = 25 m, f = 10 Hz, 8-node PML."""
     h, f, npml = 25.0, 10.0, 8
     c = synth.random_field_model(dims, h, seed=3)
     tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
-    op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, f, npml=npml)
+    store = () if variant == "recompute" else (dtype,)
+    op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, f, npml=npml, store=store)
     dt = torch.complex64 if dtype == "c64" else torch.complex128
-    sec, alg = apply_timing(op, torch, nrhs=nrhs, reps=reps, dtype=dt)
+    sec, alg = apply_timing(op, torch, nrhs=nrhs, reps=reps, dtype=dt, variant=variant)
     achieved = alg / sec / 1e9
-    return {"grid": list(dims), "nrhs": nrhs, "dtype": dtype, "apply_us": sec * 1e6,
+    return {"grid": list(dims), "nrhs": nrhs, "dtype": dtype, "variant": variant, "apply_us": sec * 1e6,
             "gpts": op.N * nrhs / sec / 1e9, "alg_bytes": alg, "GBs": achieved, "frac": achieved / HBM_PEAK_GBS}
 
 
@@ -108,7 +112,8 @@ def apply_only(args, torch, api, synth):
     dims = tuple(int(v) for v in args.grid.split(","))
     ctx = api.Context(0)
     calibration_copy(torch)
-    print(json.dumps(large_apply(ctx, torch, synth, dims, args.nrhs, args.apply_reps, args.apply_dtype)), flush=True)
+    print(json.dumps(large_apply(ctx, torch, synth, dims, args.nrhs, args.apply_reps, args.apply_dtype,
+                                 args.apply_variant)), flush=True)
 
 
 def serving(args, torch, api, synth):
@@ -202,6 +207,7 @@ def main():
     ap.add_argument("--grid", type=str, default="400,400,200")
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--apply-dtype", choices=("c64", "c128"), default="c64")
+    ap.add_argument("--apply-variant", choices=("recompute", "stored"), default="recompute")
     ap.add_argument("--no-large", action="store_true", help="skip the 400x400x200 apply roofline")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving-mix requests (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="serving-mix Poisson arrival rate (1/s)")
@@ -298,11 +304,26 @@ def main():
                      "kernel": "helm27_apply recompute FP32, 1 RHS (wave27 kernel, box and PML frame in one launch)",
                      "alg_bytes_per_launch": alg},
     }
+    # the same apply with fixed (non-adaptive) weights and with stored coefficients
+    variants = {"recompute_adaptive": {"gpts": op.N / sec / 1e9, "us": sec * 1e6}}
+    op_f = ctx.assemble(tab, c_dev, h, f, npml=npml, weights="fixed")
+    sf, _ = apply_timing(op_f, torch, nrhs=1, reps=args.apply_reps)
+    variants["recompute_fixed_weights"] = {"gpts": op.N / sf / 1e9, "us": sf * 1e6}
+    del op_f
+    op_s = ctx.assemble(tab, c_dev, h, f, npml=npml, store=("c64",))
+    ss, alg_s = apply_timing(op_s, torch, nrhs=1, reps=args.apply_reps, variant="stored")
+    variants["stored_c64"] = {"gpts": op.N / ss / 1e9, "us": ss * 1e6, "alg_bytes": alg_s,
+                              "GBs": alg_s / ss / 1e9, "frac": alg_s / ss / 1e9 / HBM_PEAK_GBS}
+    del op_s
+    out["apply_variants"] = variants
     del op, tab
     if not args.no_large:
         out["roofline_large"] = dict(large_apply(ctx, torch, synth, (400, 400, 200), reps=50), bound="hbm",
                                      peak=HBM_PEAK_GBS, unit="GB/s",
                                      traffic=measured_traffic("large_400x400x200"))
+        out["roofline_stored_large"] = dict(large_apply(ctx, torch, synth, (400, 400, 200), reps=20,
+                                                        variant="stored"), bound="hbm", peak=HBM_PEAK_GBS,
+                                            unit="GB/s")
     if args.serve_requests > 0:
         out["serving"] = serving(args, torch, api, synth)
     if not args.no_cpu_baseline:
