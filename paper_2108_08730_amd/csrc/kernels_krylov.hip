@@ -584,93 +584,104 @@ int upper_solve(int k, int m, int nrhs, const double2* H, const double2* g, doub
 template <typename R>
 __global__ void restrict_kernel(const typename V2<R>::T* __restrict__ f, int nx, int ny, int nz,
                                 typename V2<R>::T* __restrict__ c, int cx, int cy, int cz, int nrhs) {
-    const int64_t Nc = static_cast<int64_t>(cx) * cy * cz, Nf = static_cast<int64_t>(nx) * ny * nz;
-    const int64_t total = Nc * nrhs;
-    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
-         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int rhs = static_cast<int>(t / Nc);
-        const int64_t ic = t - static_cast<int64_t>(rhs) * Nc;
-        const int i = static_cast<int>(ic % cx), j = static_cast<int>((ic / cx) % cy), k = static_cast<int>(ic / (static_cast<int64_t>(cx) * cy));
-        const typename V2<R>::T* fr = f + static_cast<int64_t>(rhs) * Nf;
-        R sx = 0, sy = 0;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int z = 2 * k + dz;
-            if (z < 0 || z >= nz) continue;
-            const R wz = dz == 0 ? R(0.5) : R(0.25);
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int y = 2 * j + dy;
-                if (y < 0 || y >= ny) continue;
-                const R wy = wz * (dy == 0 ? R(0.5) : R(0.25));
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int x = 2 * i + dx;
-                    if (x < 0 || x >= nx) continue;
-                    const R w = wy * (dx == 0 ? R(0.5) : R(0.25));
-                    const typename V2<R>::T v = fr[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)];
-                    sx += w * v.x;
-                    sy += w * v.y;
-                }
+    // one coarse node per thread: x from the block's 64-wide strip, y and
+    // (z, rhs) from the grid (no integer division per thread)
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z % cz, rhs = blockIdx.z / cz;
+    if (i >= cx) return;
+    const int64_t Nf = static_cast<int64_t>(nx) * ny * nz;
+    const typename V2<R>::T* fr = f + static_cast<int64_t>(rhs) * Nf;
+    R sx = 0, sy = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = 2 * k + dz;
+        if (z < 0 || z >= nz) continue;
+        const R wz = dz == 0 ? R(0.5) : R(0.25);
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = 2 * j + dy;
+            if (y < 0 || y >= ny) continue;
+            const R wy = wz * (dy == 0 ? R(0.5) : R(0.25));
+            const typename V2<R>::T* row = fr + (static_cast<int64_t>(z) * ny + y) * nx;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = 2 * i + dx;
+                if (x < 0 || x >= nx) continue;
+                const R w = wy * (dx == 0 ? R(0.5) : R(0.25));
+                const typename V2<R>::T v = row[x];
+                sx += w * v.x;
+                sy += w * v.y;
             }
         }
-        typename V2<R>::T o;
-        o.x = sx;
-        o.y = sy;
-        c[t] = o;
     }
+    typename V2<R>::T o;
+    o.x = sx;
+    o.y = sy;
+    c[static_cast<int64_t>(rhs) * cx * cy * cz + (static_cast<int64_t>(k) * cy + j) * cx + i] = o;
 }
 
 template <typename R>
 __global__ void prolong_add_kernel(const typename V2<R>::T* __restrict__ c, int cx, int cy, int cz,
                                    typename V2<R>::T* __restrict__ f, int nx, int ny, int nz, int nrhs) {
-    const int64_t Nc = static_cast<int64_t>(cx) * cy * cz, Nf = static_cast<int64_t>(nx) * ny * nz;
-    const int64_t total = Nf * nrhs;
-    for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
-         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int rhs = static_cast<int>(t / Nf);
-        const int64_t iff = t - static_cast<int64_t>(rhs) * Nf;
-        const int x = static_cast<int>(iff % nx), y = static_cast<int>((iff / nx) % ny), z = static_cast<int>(iff / (static_cast<int64_t>(nx) * ny));
-        const typename V2<R>::T* cr = c + static_cast<int64_t>(rhs) * Nc;
-        // per axis: even -> one coarse node (weight 1), odd -> two (1/2 each)
-        int ix[2], iy[2], iz[2];
-        R wx[2], wy[2], wz[2];
-        int nxs, nys, nzs;
-        if (x % 2 == 0) { ix[0] = x / 2; wx[0] = 1; nxs = 1; } else { ix[0] = x / 2; ix[1] = x / 2 + 1; wx[0] = wx[1] = R(0.5); nxs = 2; }
-        if (y % 2 == 0) { iy[0] = y / 2; wy[0] = 1; nys = 1; } else { iy[0] = y / 2; iy[1] = y / 2 + 1; wy[0] = wy[1] = R(0.5); nys = 2; }
-        if (z % 2 == 0) { iz[0] = z / 2; wz[0] = 1; nzs = 1; } else { iz[0] = z / 2; iz[1] = z / 2 + 1; wz[0] = wz[1] = R(0.5); nzs = 2; }
-        R sx = 0, sy = 0;
-        for (int a = 0; a < nzs; ++a) {
-            if (iz[a] >= cz) continue;
-            for (int b = 0; b < nys; ++b) {
-                if (iy[b] >= cy) continue;
-                for (int e = 0; e < nxs; ++e) {
-                    if (ix[e] >= cx) continue;
-                    const R w = wz[a] * wy[b] * wx[e];
-                    const typename V2<R>::T v = cr[ix[e] + static_cast<int64_t>(cx) * (iy[b] + static_cast<int64_t>(cy) * iz[a])];
-                    sx += w * v.x;
-                    sy += w * v.y;
-                }
+    // one fine node per thread (trilinear interpolation of the coarse
+    // correction); x from the block's strip, y and (z, rhs) from the grid
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z % nz, rhs = blockIdx.z / nz;
+    if (x >= nx) return;
+    const typename V2<R>::T* cr = c + static_cast<int64_t>(rhs) * cx * cy * cz;
+    // per axis: even -> one coarse node (weight 1), odd -> two (1/2 each)
+    const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+    const int nxs = (x & 1) ? 2 : 1, nys = (y & 1) ? 2 : 1, nzs = (z & 1) ? 2 : 1;
+    const R w = ((x & 1) ? R(0.5) : R(1)) * ((y & 1) ? R(0.5) : R(1)) * ((z & 1) ? R(0.5) : R(1));
+    R sx = 0, sy = 0;
+    for (int a = 0; a < nzs; ++a) {
+        if (z0 + a >= cz) continue;
+        for (int b = 0; b < nys; ++b) {
+            if (y0 + b >= cy) continue;
+            const typename V2<R>::T* row = cr + (static_cast<int64_t>(z0 + a) * cy + y0 + b) * cx;
+            for (int e = 0; e < nxs; ++e) {
+                if (x0 + e >= cx) continue;
+                const typename V2<R>::T v = row[x0 + e];
+                sx += w * v.x;
+                sy += w * v.y;
             }
         }
-        typename V2<R>::T o = f[t];
-        o.x += sx;
-        o.y += sy;
-        f[t] = o;
     }
+    typename V2<R>::T* fp = f + static_cast<int64_t>(rhs) * nx * ny * nz + (static_cast<int64_t>(z) * ny + y) * nx + x;
+    typename V2<R>::T o = *fp;
+    o.x += sx;
+    o.y += sy;
+    *fp = o;
 }
 
 template <typename R>
 int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s) {
-    const int64_t total = static_cast<int64_t>(cx) * cy * cz * nrhs;
-    H27_CHECK_HIP(launch(restrict_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
-                         static_cast<const typename V2<R>::T*>(f), nx, ny, nz, static_cast<typename V2<R>::T*>(c), cx,
-                         cy, cz, nrhs));
+    using V = typename V2<R>::T;
+    if (static_cast<int64_t>(cx) * cy * cz * nrhs <= 0) return HELM27_OK;
+    if (cy > 65535 || cz > 65535) return HELM27_EINVAL;
+    const int per = 65535 / cz;   // right-hand sides per launch (grid z = cz * count)
+    const int64_t Nf = static_cast<int64_t>(nx) * ny * nz, Nc = static_cast<int64_t>(cx) * cy * cz;
+    for (int r0 = 0; r0 < nrhs; r0 += per) {
+        const int n = nrhs - r0 < per ? nrhs - r0 : per;
+        H27_CHECK_HIP(launch(restrict_kernel<R>, dim3((cx + 63) / 64, cy, cz * n), dim3(64), 0, s,
+                             static_cast<const V*>(f) + r0 * Nf, nx, ny, nz, static_cast<V*>(c) + r0 * Nc, cx, cy, cz,
+                             n));
+    }
     return HELM27_OK;
 }
 template <typename R>
 int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int ny, int nz, int nrhs, hipStream_t s) {
-    const int64_t total = static_cast<int64_t>(nx) * ny * nz * nrhs;
-    H27_CHECK_HIP(launch(prolong_add_kernel<R>, dim3(grid_for(total, 1)), dim3(kRedBlock), 0, s,
-                         static_cast<const typename V2<R>::T*>(c), cx, cy, cz, static_cast<typename V2<R>::T*>(f), nx,
-                         ny, nz, nrhs));
+    using V = typename V2<R>::T;
+    if (static_cast<int64_t>(nx) * ny * nz * nrhs <= 0) return HELM27_OK;
+    if (ny > 65535 || nz > 65535) return HELM27_EINVAL;
+    const int per = 65535 / nz;   // right-hand sides per launch (grid z = nz * count)
+    const int64_t Nf = static_cast<int64_t>(nx) * ny * nz, Nc = static_cast<int64_t>(cx) * cy * cz;
+    for (int r0 = 0; r0 < nrhs; r0 += per) {
+        const int n = nrhs - r0 < per ? nrhs - r0 : per;
+        H27_CHECK_HIP(launch(prolong_add_kernel<R>, dim3((nx + 63) / 64, ny, nz * n), dim3(64), 0, s,
+                             static_cast<const V*>(c) + r0 * Nc, cx, cy, cz, static_cast<V*>(f) + r0 * Nf, nx, ny,
+                             nz, n));
+    }
     return HELM27_OK;
 }
 template int mg_restrict<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
