@@ -184,12 +184,14 @@ int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int
 /* Tuning of the recompute kernel's tile shape (output rows per wavefront in
  * the unstretched box, 1..4; more rows reuse more loaded data, fewer rows
  * leave registers for more wavefronts in flight).  helm27_set_tuning sets
- * it for one precision; helm27_tune times every choice on the operator with
- * nrhs zero right-hand sides (device scratch allocated and freed inside),
- * keeps the fastest and returns it in *best_rows (may be NULL).  Every choice
- * computes the same sums per output; the compiler may fuse multiply-adds
- * differently per choice, so results agree to rounding (not bit for bit)
- * across choices, and bit for bit across runs of one choice.
+ * it for one precision; helm27_tune times every rows choice with each z
+ * chunk in {automatic, 8, 16, 32, 64} (helm27_set_zchunk) on the operator
+ * with nrhs zero right-hand sides (device scratch allocated and freed
+ * inside), keeps the fastest pair and returns its rows in *best_rows (may be
+ * NULL).  Every choice computes the same sums per output; the compiler may
+ * fuse multiply-adds differently per choice, so results agree to rounding
+ * (not bit for bit) across choices, and bit for bit across runs of one
+ * choice.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave);
 int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows);
@@ -200,8 +202,8 @@ int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows
 int helm27_set_kernel_variant(helm27_op* op, int variant);
 /* z planes per work item of the wavefront kernel (each item marches its
  * chunk of planes; two extra planes are read per chunk): 0 = automatic
- * (about 4096 work items, 2..32 planes each), else 2..4096.  Results do not
- * depend on it.  Errors: EINVAL. */
+ * (about 4096 work items, 2..32 planes each), else 2..4096.  Results agree
+ * to rounding across choices.  Errors: EINVAL. */
 int helm27_set_zchunk(helm27_op* op, int zchunk);
 
 /* ---- (c) solve ------------------------------------------------------------ */

@@ -488,23 +488,32 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
     if (hipMemsetAsync(u, 0, bytes, s) != hipSuccess) st = HELM27_EDEVICE;
     const int slot = dtype == HELM27_C64 ? 0 : 1;
     float best = 1e30f;
-    int best_ry = op->g.plain_ry[slot];
+    int best_ry = op->g.plain_ry[slot], best_zc = op->g.wave_zchunk;
+    const int zchunks[5] = {0, 8, 16, 32, 64};   // 0 = automatic
     for (int ry = 1; ry <= 4 && st == HELM27_OK; ++ry) {
-        op->g.plain_ry[slot] = ry;
-        for (int w = 0; w < 2 && st == HELM27_OK; ++w) st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
-        (void)hipEventRecord(e0, s);
-        const int reps = 10;
-        for (int r = 0; r < reps && st == HELM27_OK; ++r) st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) st = HELM27_EDEVICE;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (st == HELM27_OK && ms < best) {
-            best = ms;
-            best_ry = ry;
+        for (int zi = 0; zi < 5 && st == HELM27_OK; ++zi) {
+            if (zchunks[zi] > op->g.nz) continue;
+            op->g.plain_ry[slot] = ry;
+            op->g.wave_zchunk = zchunks[zi];
+            for (int w = 0; w < 2 && st == HELM27_OK; ++w)
+                st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
+            (void)hipEventRecord(e0, s);
+            const int reps = 10;
+            for (int r = 0; r < reps && st == HELM27_OK; ++r)
+                st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) st = HELM27_EDEVICE;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (st == HELM27_OK && ms < best) {
+                best = ms;
+                best_ry = ry;
+                best_zc = zchunks[zi];
+            }
         }
     }
     op->g.plain_ry[slot] = best_ry;
+    op->g.wave_zchunk = best_zc;
     if (best_rows) *best_rows = best_ry;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -219,6 +219,36 @@ def test_apply_tile_shapes_agree(ctx, table, oracle_table, dims, npml, kind, f, 
     assert op.tune(2, "c64") in (1, 2, 3, 4)
 
 
+@pytest.mark.parametrize("dims,npml,kind,f,h", [CASES[1], CASES[4]])
+def test_apply_zchunks_bit_identical(ctx, table, oracle_table, dims, npml, kind, f, h):
+    """The z chunk of the work items (automatic, 2, 3, 7, the whole depth)
+    changes only which wavefront computes a plane: every choice matches the
+    oracle, the choices agree with each other to rounding (the unrolled z
+    steps may fuse multiply-adds differently), and a repeated launch is bit
+    for bit the same."""
+    c = _model(kind, dims, h)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    A = _oracle_rows(c, f, h, npml, oracle_table[2])
+    u = synth.random_vectors(int(np.prod(dims)), 2, seed=14)
+    y_ref = (A @ u.T).T
+    ud = torch.from_numpy(u).cuda()
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-5)):
+        outs = []
+        for zc in (0, 2, 3, 7, dims[2]):
+            op.set_zchunk(zc)
+            outs.append(op.apply(ud.to(dt)).cpu().numpy())
+        again = op.apply(ud.to(dt)).cpu().numpy()
+        assert np.array_equal(again, outs[-1])
+        for o in outs:
+            for r in range(2):
+                assert _relerr(o[r], y_ref[r]) <= tol
+                assert _relerr(o[r], outs[0][r]) <= tol
+    op.set_zchunk(0)
+    from paper_2108_08730_amd import _lib as L
+    with pytest.raises(L.Helm27Error):
+        op.set_zchunk(1)
+
+
 @pytest.mark.parametrize("dims,npml,kind,f,h", [CASES[1], CASES[3], CASES[4]])
 def test_kernel_variants_agree(ctx, table, oracle_table, dims, npml, kind, f, h):
     """The wavefront-per-tile and the LDS-tiled kernels both match the oracle
