@@ -185,10 +185,12 @@ int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int
  * the unstretched box, 1..4; more rows reuse more loaded data, fewer rows
  * leave registers for more wavefronts in flight).  helm27_set_tuning sets
  * it for one precision; helm27_tune times every rows choice with each z
- * chunk in {automatic, 8, 16, 32, 64} (helm27_set_zchunk) on the operator
- * with nrhs zero right-hand sides (device scratch allocated and freed
- * inside), keeps the fastest pair and returns its rows in *best_rows (may be
- * NULL).  Every choice computes the same sums per output; the compiler may
+ * chunk in {automatic, 8, 16, 32, 64} (helm27_set_zchunk) and kernel
+ * variants 0 and 2 (helm27_set_kernel_variant) on the operator with nrhs
+ * zero right-hand sides (device scratch allocated and freed inside), keeps
+ * the fastest and returns its rows in *best_rows (may be NULL).  Operators
+ * of 2^23 points or more start at variant 2, 1 row, 16-plane chunks; smaller
+ * ones at variant 0, 2 rows (FP32) / 1 row (FP64), automatic chunks.  Every choice computes the same sums per output; the compiler may
  * fuse multiply-adds differently per choice, so results agree to rounding
  * (not bit for bit) across choices, and bit for bit across runs of one
  * choice.
@@ -197,8 +199,9 @@ int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave);
 int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows);
 /* Kernel family of the recompute stencil: 0 = one wavefront per tile, box and
  * PML frame in one launch (default); 1 = LDS-tiled blocks (one block per
- * 64 x 8 or 16 x 16 column tile).  Both compute the same operator.
- * Errors: EINVAL. */
+ * 64 x 8 or 16 x 16 column tile); 2 = as 0, with the box tiles in groups of
+ * four stacked tiles per block that share their plane rows through LDS.
+ * All compute the same operator.  Errors: EINVAL. */
 int helm27_set_kernel_variant(helm27_op* op, int variant);
 /* z planes per work item of the wavefront kernel (each item marches its
  * chunk of planes; two extra planes are read per chunk): 0 = automatic

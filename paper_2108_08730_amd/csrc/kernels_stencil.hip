@@ -405,9 +405,11 @@ bool stencil_wave_path(const GridOp& g, bool fp64) {
     const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
     // the wavefront kernel addresses one right-hand side with 32-bit buffer
     // offsets: its byte size must stay below 2^31
-    return g.kernel_variant == 0 && n_tab > 0 &&
+    const int ry = g.plain_ry[fp64 ? 1 : 0];
+    const size_t ring = g.kernel_variant == 2 ? static_cast<size_t>(2 * (4 * ry + 2) * 64) * (fp64 ? 16 : 8) : 0;
+    return (g.kernel_variant == 0 || g.kernel_variant == 2) && n_tab > 0 &&
            static_cast<int64_t>(g.N) * (fp64 ? 16 : 8) < (int64_t(1) << 31) &&
-           wave_lds_bytes(g.d_row_f ? 0 : n_tab, g.nz, fp64) <= 64 * 1024;
+           wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= 64 * 1024;
 }
 
 template <typename R>
@@ -448,8 +450,11 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         const int RY = g.plain_ry[sizeof(R) == 8 ? 1 : 0];
         const int RQ = frame_rows<R>();
         w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
+        // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
+        w.blk = g.kernel_variant == 2 ? 1 : 0;
+        const int rows_per_tile = w.blk ? 4 * RY : RY;
         w.ntx = w.pw > 0 ? (w.pw + kWaveCols - 1) / kWaveCols : 0;
-        w.nty = w.ph > 0 ? (w.ph + RY - 1) / RY : 0;
+        w.nty = w.ph > 0 ? (w.ph + rows_per_tile - 1) / rows_per_tile : 0;
         w.n_plain = w.ntx * w.nty;
         int accf = 0;
         for (int k = 0; k < 4; ++k) {
@@ -469,9 +474,12 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         }
         w.fstart[4] = accf;
         w.n_frame = accf;
-        const int64_t tiles = static_cast<int64_t>(w.n_plain + w.n_frame) * nrhs;
+        // work items: wavefront items (variant 0) or block items of 4 wavefronts (variant 2)
+        const int64_t tiles = static_cast<int64_t>(w.blk ? (w.n_frame + 3) / 4 + w.n_plain : w.n_plain + w.n_frame) *
+                              nrhs;
         if (tiles <= 0) return HELM27_OK;
-        int64_t nzc = (4096 + tiles - 1) / tiles;
+        const int64_t target = w.blk ? 1024 : 4096;
+        int64_t nzc = (target + tiles - 1) / tiles;
         int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
         zc = std::max(2, std::min(32, zc));
         if (g.wave_zchunk > 0) zc = g.wave_zchunk;

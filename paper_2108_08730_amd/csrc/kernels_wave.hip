@@ -259,29 +259,45 @@ struct ItemBuf {
 };
 
 // ---------------------------------------------------------------------------
-// unstretched-box tile
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC>
+// unstretched-box tile.  BLK = false: one wavefront per tile of RY rows, which
+// loads its RY + 2 rows per plane.  BLK = true: the block's 4 wavefronts take
+// 4 stacked tiles of RY rows; each loads its own RY rows (wavefront 0 also the
+// row below the block, wavefront 3 the row above) and passes them to the
+// others through a two-plane LDS ring, so each row is read from memory once
+// per block instead of once per tile that needs it (1 + 2/(4 RY) instead of
+// 1 + 2/RY loads per output row), at one barrier per plane.
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK>
 __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
-                                         int tile, int zc, int rhs, int lane) {
+                                         typename V2<R>::T* ring, int tile, int zc, int rhs, int wave, int lane) {
     using V = typename V2<R>::T;
     constexpr unsigned SV = sizeof(V);
+    constexpr int NL = BLK ? RY + 1 : RY + 2;   // rows this wavefront loads per plane
+    constexpr int KB = 4 * RY + 2;              // rows of a block plane in the ring
     const GridData<R>& g = a.g;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx = a.px0 + tx * kWaveCols - 1 + lane;
     const bool inx = gx >= 0 && gx < g.nx;
     const bool outx = lane >= 1 && lane <= kWaveCols && gx < a.px0 + a.pw;
     const int gxc = min(max(gx, 0), g.nx - 1);
-    const int y0 = a.py0 + ty * RY;
+    const int yb = a.py0 + ty * (BLK ? 4 * RY : RY);   // first output row of the tile (block)
+    const int y0 = yb + (BLK ? wave * RY : 0);          // first output row of this wavefront
     const int z0 = zc * a.zchunk;
     const int z1 = min(z0 + a.zchunk, g.nz);
     const int yend = a.py0 + a.ph;
-    unsigned lo[RY + 2];      // byte offsets of the loaded rows (kOff outside the grid)
+    unsigned lo[NL];          // byte offsets of the loaded rows (kOff outside the grid)
     unsigned so[RY];          // byte offsets of the stored rows (kOff: no output)
     unsigned mo[RY];          // element offsets of the output rows (clamped, always valid)
 #pragma unroll
-    for (int k = 0; k < RY + 2; ++k) {
-        const int yy = y0 - 1 + k;
-        lo[k] = (inx && yy >= 0 && yy < g.ny) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
+    for (int k = 0; k < NL; ++k) {
+        int yy;
+        bool use = true;
+        if (BLK) {   // own rows, then the block's halo row (wavefronts 0 and 3)
+            yy = k < RY ? y0 + k : (wave == 0 ? yb - 1 : yb + 4 * RY);
+            use = k < RY || wave == 0 || wave == 3;
+        } else {
+            yy = y0 - 1 + k;
+        }
+        lo[k] = (use && inx && yy >= 0 && yy < g.ny) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -380,14 +396,29 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     // the per-point data of plane q + 1 are loaded two steps ahead of their
     // use; past the chunk the last plane is loaded again, so every step issues
     // the same loads and the waits stay exact.
-    auto step = [&](int q, bool out, const V (&Lc)[RY + 2], V (&Ln)[RY + 2], const BoxPlane<R, RY>& A,
+    auto step = [&](int q, bool out, const V (&Lc)[NL], V (&Ln)[NL], const BoxPlane<R, RY>& A,
                     const BoxPlane<R, RY>& B, BoxPlane<R, RY>& C, const Meta<R, RY>& Mc, Meta<R, RY>& Mn)
                     __attribute__((always_inline)) {
         B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
         B_.template load_meta<RY, ROWC>(min(q + 1, z1 - 1), mo, Mn);
         Cx<R> U[RY + 2];
+        if constexpr (BLK) {
+            // ring[slot][row of the block plane][lane]; slot alternates with q
+            V* pl = ring + ((q & 1) * KB) * 64;
 #pragma unroll
-        for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
+            for (int k = 0; k < RY; ++k) pl[(1 + wave * RY + k) * 64 + lane] = Lc[k];
+            if (wave == 0) pl[lane] = Lc[RY];
+            if (wave == 3) pl[(KB - 1) * 64 + lane] = Lc[RY];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < RY + 2; ++k) {
+                const V v = pl[(wave * RY + k) * 64 + lane];
+                U[k] = Cx<R>{v.x, v.y};
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
+        }
         Cx<R> sx[RY + 2];
 #pragma unroll
         for (int k = 0; k < RY + 2; ++k) sx[k] = nxt_g<64>(U[k]) + prv_g<64>(U[k]);
@@ -402,9 +433,10 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
 
     // slot k % 3 (k = q - z0 + 1) holds the loads, the plane sums and the
     // per-point data of plane q
-    V L0[RY + 2], L1[RY + 2], L2[RY + 2];
+    V L0[NL], L1[NL], L2[NL];
     BoxPlane<R, RY> P0, P1, P2;
     Meta<R, RY> M0, M1, M2;
+    if (BLK) __syncthreads();   // the previous item's last ring reads are done
     B_.load_plane(z0 - 1, g.nz, lo, L0);
     B_.load_plane(z0, g.nz, lo, L1);
     // planes z0 - 1 and z0 enter without an output; then one output per step
@@ -609,7 +641,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
 }
 
 // register budget: 4 waves per SIMD (128 VGPRs) for FP32, 2 for FP64
-template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC>
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 void wave27_kernel(WaveArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -629,6 +661,10 @@ void wave27_kernel(WaveArgs<R> a) {
         tab[t] = e;
     }
     for (int t = threadIdx.x; t < g.nz; t += kBlock) zn[t] = g.az[t];
+    // row ring after the table slice and the z nodes, 16-byte aligned (as wave_ring_offset)
+    const size_t ring_off = (static_cast<size_t>(n_tab) * sizeof(TabEntry<R>) +
+                             static_cast<size_t>(g.nz) * sizeof(AxisNode<R>) + 15) & ~static_cast<size_t>(15);
+    typename V2<R>::T* ring = reinterpret_cast<typename V2<R>::T*>(smem_raw + ring_off);
     __syncthreads();
     // XCD-contiguous block order: block b runs on XCD b % 8; the grid is at
     // most one resident wave per slot and each wave strides over the items
@@ -638,22 +674,49 @@ void wave27_kernel(WaveArgs<R> a) {
     const int lb = xcd * q8 + min(xcd, r8) + (bx >> 3);
     const int wave = uni(static_cast<int>(threadIdx.x) >> 6);
     const int lane = static_cast<int>(threadIdx.x) & 63;
-    const int ntile = a.n_frame + a.n_plain;
-    for (int item = lb * (kBlock / 64) + wave; item < a.n_items; item += nb * (kBlock / 64)) {
-        // item order: right-hand side fastest, then tile, then z chunk
-        const int rhs = item % a.nrhs;
-        const int t = item / a.nrhs;
-        const int tile = t % ntile;
-        const int zc = t / ntile;
-        if (tile < a.n_frame) {
-            int k = 0;
-            while (k < 3 && tile >= a.fstart[k + 1]) ++k;
-            if (a.flx[k])
-                frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
-            else
-                frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
-        } else {
-            box_item<R, MODE, SHIFTED, RY, ROWC>(a, tab, zn, tile - a.n_frame, zc, rhs, lane);
+    if (!BLK) {
+        const int ntile = a.n_frame + a.n_plain;
+        for (int item = lb * (kBlock / 64) + wave; item < a.n_items; item += nb * (kBlock / 64)) {
+            // item order: right-hand side fastest, then tile, then z chunk
+            const int rhs = item % a.nrhs;
+            const int t = item / a.nrhs;
+            const int tile = t % ntile;
+            const int zc = t / ntile;
+            if (tile < a.n_frame) {
+                int k = 0;
+                while (k < 3 && tile >= a.fstart[k + 1]) ++k;
+                if (a.flx[k])
+                    frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                else
+                    frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+            } else {
+                box_item<R, MODE, SHIFTED, RY, ROWC, false>(a, tab, zn, ring, tile - a.n_frame, zc, rhs, wave,
+                                                            lane);
+            }
+        }
+    } else {
+        // block items: 4 frame tiles (one per wavefront) or one box block
+        // tile (4 stacked tiles sharing rows through the LDS ring)
+        const int nfb = (a.n_frame + 3) / 4;
+        const int nbt = nfb + a.n_plain;   // n_plain counts box block tiles here
+        for (int bi = lb; bi < a.n_items; bi += nb) {
+            const int rhs = bi % a.nrhs;
+            const int t = bi / a.nrhs;
+            const int bt = t % nbt;
+            const int zc = t / nbt;
+            if (bt < nfb) {
+                const int tile = bt * 4 + wave;
+                if (tile < a.n_frame) {
+                    int k = 0;
+                    while (k < 3 && tile >= a.fstart[k + 1]) ++k;
+                    if (a.flx[k])
+                        frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                    else
+                        frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                }
+            } else {
+                box_item<R, MODE, SHIFTED, RY, ROWC, true>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
+            }
         }
     }
 }
@@ -682,23 +745,28 @@ static int resident_blocks(const void* fn, size_t lds) {
     return blocks;
 }
 
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC>
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK>
 static int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
     constexpr int RQ = FrameRows<R>::value;
-    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC>);
-    const size_t lds = wave_lds_bytes(ROWC ? 0 : a.n_tab, a.g.nz, sizeof(R) == 8);
-    int blocks = (a.n_items + (kBlock / 64) - 1) / (kBlock / 64);
+    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK>);
+    const int n_tab = ROWC ? 0 : a.n_tab;
+    const size_t lds = wave_ring_offset(n_tab, a.g.nz, sizeof(R) == 8) +
+                       (BLK ? static_cast<size_t>(2 * (4 * RY + 2) * 64) * sizeof(typename V2<R>::T) : 0);
+    int blocks = BLK ? a.n_items : (a.n_items + (kBlock / 64) - 1) / (kBlock / 64);
     const int cap = resident_blocks(fn, lds);
     if (cap <= 0) return HELM27_EDEVICE;
     if (blocks > cap) blocks = cap;
-    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC>, dim3(blocks), dim3(kBlock), lds, s, a));
+    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK>, dim3(blocks), dim3(kBlock), lds, s, a));
     return HELM27_OK;
 }
 
 template <typename R, int MODE, bool SHIFTED, int RY>
 static int launch_wave_ry(const WaveArgs<R>& a, hipStream_t s) {
-    return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true>(a, s)
-                       : launch_wave_k<R, MODE, SHIFTED, RY, false>(a, s);
+    if (a.blk)
+        return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true, true>(a, s)
+                           : launch_wave_k<R, MODE, SHIFTED, RY, false, true>(a, s);
+    return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true, false>(a, s)
+                       : launch_wave_k<R, MODE, SHIFTED, RY, false, false>(a, s);
 }
 
 template <typename R, int MODE, bool SHIFTED>
@@ -740,6 +808,11 @@ template <typename R>
 int frame_rows() { return FrameRows<R>::value; }
 template int frame_rows<float>();
 template int frame_rows<double>();
+
+// byte offset of the LDS row ring (after the table slice and the z nodes, 16-byte aligned)
+size_t wave_ring_offset(int n_tab, int nz, bool fp64) {
+    return (wave_lds_bytes(n_tab, nz, fp64) + 15) & ~static_cast<size_t>(15);
+}
 
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64) {
     return fp64 ? static_cast<size_t>(n_tab) * sizeof(TabEntry<double>) + static_cast<size_t>(nz) * sizeof(AxisNode<double>)

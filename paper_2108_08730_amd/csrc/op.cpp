@@ -337,6 +337,15 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     op->n_clamped = static_cast<int64_t>(cnt[0]);
 
     if ((st = grid_setup(&g, t->w7.data(), t->n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
+    // large grids (HBM-bound): box rows shared across the block, one row per
+    // wavefront, 16-plane chunks (measured on 400x400x200: 187 us against
+    // 203 us for the per-wavefront tiles); smaller grids keep the latency-
+    // friendlier per-wavefront tiles
+    if (g.N >= (int64_t(1) << 23)) {
+        g.kernel_variant = 2;
+        g.plain_ry[0] = 1;
+        g.wave_zchunk = 16;
+    }
     // idx is non-decreasing in c, so the smallest / largest velocities give its range
     g.idx_lo = host_index(cmin, fh, t->g_min, t->dg, t->n_g);
     g.idx_hi = host_index(cmax, fh, t->g_min, t->dg, t->n_g);
@@ -488,13 +497,17 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
     if (hipMemsetAsync(u, 0, bytes, s) != hipSuccess) st = HELM27_EDEVICE;
     const int slot = dtype == HELM27_C64 ? 0 : 1;
     float best = 1e30f;
-    int best_ry = op->g.plain_ry[slot], best_zc = op->g.wave_zchunk;
+    int best_ry = op->g.plain_ry[slot], best_zc = op->g.wave_zchunk, best_var = op->g.kernel_variant;
     const int zchunks[5] = {0, 8, 16, 32, 64};   // 0 = automatic
+    const int variants[2] = {0, 2};
+    for (int vi = 0; vi < 2 && st == HELM27_OK; ++vi)
     for (int ry = 1; ry <= 4 && st == HELM27_OK; ++ry) {
         for (int zi = 0; zi < 5 && st == HELM27_OK; ++zi) {
             if (zchunks[zi] > op->g.nz) continue;
+            op->g.kernel_variant = variants[vi];
             op->g.plain_ry[slot] = ry;
             op->g.wave_zchunk = zchunks[zi];
+            if (!stencil_wave_path(op->g, dtype == HELM27_C128)) continue;
             for (int w = 0; w < 2 && st == HELM27_OK; ++w)
                 st = helm27_apply(op, u, y, nrhs, dtype, HELM27_RECOMPUTE, s);
             (void)hipEventRecord(e0, s);
@@ -509,11 +522,13 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
                 best = ms;
                 best_ry = ry;
                 best_zc = zchunks[zi];
+                best_var = variants[vi];
             }
         }
     }
     op->g.plain_ry[slot] = best_ry;
     op->g.wave_zchunk = best_zc;
+    op->g.kernel_variant = best_var;
     if (best_rows) *best_rows = best_ry;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -523,7 +538,7 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
 }
 
 extern "C" int helm27_set_kernel_variant(helm27_op* op, int variant) {
-    if (!op || variant < 0 || variant > 1) return HELM27_EINVAL;
+    if (!op || variant < 0 || variant > 2) return HELM27_EINVAL;
     op->g.kernel_variant = variant;
     return HELM27_OK;
 }

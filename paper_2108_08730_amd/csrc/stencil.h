@@ -65,6 +65,7 @@ struct WaveArgs {
     int fnl[4], fnq[4];            // tiles along x and along y
     int fstart[5], n_frame;        // prefix sums of frame tiles
     int nzc, zchunk, nrhs, n_items;
+    int blk;                       // 1: box tiles in block items of 4 stacked tiles (LDS row ring)
     int tab_lo, n_tab;             // table slice [tab_lo, tab_lo + n_tab)
     const typename V2<R>::T* u;
     typename V2<R>::T* y;
@@ -84,5 +85,6 @@ int frame_rows();
 // LDS bytes of the wavefront kernel: the staged weight-table slice (n_tab
 // entries; 0 with per-row coefficients) and the z-axis PML nodes
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64);
+size_t wave_ring_offset(int n_tab, int nz, bool fp64);
 
 }  // namespace h27

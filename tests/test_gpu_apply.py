@@ -251,20 +251,25 @@ def test_apply_zchunks_bit_identical(ctx, table, oracle_table, dims, npml, kind,
 
 @pytest.mark.parametrize("dims,npml,kind,f,h", [CASES[1], CASES[3], CASES[4]])
 def test_kernel_variants_agree(ctx, table, oracle_table, dims, npml, kind, f, h):
-    """The wavefront-per-tile and the LDS-tiled kernels both match the oracle
-    in every mode (apply, and through the solver: residual and Jacobi)."""
+    """The wavefront-per-tile kernel (alone and with box rows shared across
+    the block in LDS) and the LDS-tiled kernel all match the oracle, for every
+    rows-per-wavefront choice of the shared variant."""
     c = _model(kind, dims, h)
     op = ctx.assemble(table, c, h, f, npml=npml)
     A = _oracle_rows(c, f, h, npml, oracle_table[2])
     u = synth.random_vectors(int(np.prod(dims)), 2, seed=13)
     y_ref = (A @ u.T).T
     ud = torch.from_numpy(u).cuda()
-    for v in (0, 1):
+    for v in (0, 1, 2):
         op.set_kernel_variant(v)
         for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-5)):
-            y = op.apply(ud.to(dt)).cpu().numpy()
-            for r in range(2):
-                assert _relerr(y[r], y_ref[r]) <= tol
+            for ry in ((1, 2, 3, 4) if v == 2 else (2,)):
+                op.set_tuning("c64" if dt == torch.complex64 else "c128", ry)
+                y = op.apply(ud.to(dt)).cpu().numpy()
+                for r in range(2):
+                    assert _relerr(y[r], y_ref[r]) <= tol
+    op.set_tuning("c64", 2)
+    op.set_tuning("c128", 1)
     op.set_kernel_variant(0)
 
 
