@@ -142,56 +142,120 @@ __device__ __forceinline__ bool second_pass(const double* nrm0, const double* nr
 }
 
 // Multi-vector dot products h[rhs][j] = sum_i conj(V_j[rhs][i]) w[rhs][i] for
-// all j < J in one launch (8 basis vectors per pass over the block's
-// elements), plus |w|^2 in slot J when self_norm is set.  V is [m+1][nrhs][N];
-// partial is [nrhs][J + self_norm][nb] (complex as 2 doubles).  With the gate
-// (nrm0, nrm1) a right-hand side that needs no second pass writes zeros.
+// all j < J in one launch, plus |w|^2 in slot J when self_norm is set.  V is
+// [m+1][nrhs][N]; partial is [nrhs][J + self_norm][nb] (complex as 2 doubles).
+//
+// One pass over the elements for up to 32 slots: the block's four wavefronts
+// split the slots into G groups (slot j goes to group j mod G) and, when there
+// are fewer than four slots, the element strips too (E = 4 / G parts).  A
+// wavefront walks 64-element strips and, per pair of strips, issues the loads
+// of all its slots and of w before it uses any of them (2 NK + 2 loads in
+// flight); its FP64 accumulators stay in registers.  The four wavefronts read
+// the same w strips, which the CU's cache serves after the first.  With the
+// gate (nrm0, nrm1) a right-hand side that needs no second pass exits at once;
+// the reduction kernel writes its zeros.
+template <typename R, int NK>
+__device__ __forceinline__ void mdot_wave(const typename V2<R>::T* const (&src)[8], const typename V2<R>::T* wr,
+                                          int64_t N, int64_t s0, int64_t sstep, int lane, double (&acc)[16]) {
+    using V = typename V2<R>::T;
+    const int64_t nfull = N / 64;   // strips with 64 elements
+    int64_t st = s0;
+    for (; st + sstep < nfull; st += 2 * sstep) {
+        const int64_t i0 = st * 64 + lane, i1 = (st + sstep) * 64 + lane;
+        const V w0 = wr[i0], w1 = wr[i1];
+        V a[NK], b[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            a[k] = src[k][i0];
+            b[k] = src[k][i1];
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {   // conj(v) * w
+            acc[2 * k] += static_cast<double>(a[k].x) * w0.x + static_cast<double>(a[k].y) * w0.y;
+            acc[2 * k + 1] += static_cast<double>(a[k].x) * w0.y - static_cast<double>(a[k].y) * w0.x;
+            acc[2 * k] += static_cast<double>(b[k].x) * w1.x + static_cast<double>(b[k].y) * w1.y;
+            acc[2 * k + 1] += static_cast<double>(b[k].x) * w1.y - static_cast<double>(b[k].y) * w1.x;
+        }
+    }
+    for (; st * 64 < N; st += sstep) {   // at most two strips, the last possibly partial
+        const int64_t i0 = st * 64 + lane;
+        if (i0 < N) {
+            const V w0 = wr[i0];
+            V a[NK];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) a[k] = src[k][i0];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                acc[2 * k] += static_cast<double>(a[k].x) * w0.x + static_cast<double>(a[k].y) * w0.y;
+                acc[2 * k + 1] += static_cast<double>(a[k].x) * w0.y - static_cast<double>(a[k].y) * w0.x;
+            }
+        }
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride,
                                                                  int J, const typename V2<R>::T* __restrict__ w,
                                                                  int64_t N, double* __restrict__ partial, int self_norm,
                                                                  const double* __restrict__ nrm0,
                                                                  const double* __restrict__ nrm1) {
-    __shared__ double sh[16 * 4];
+    using VT = typename V2<R>::T;
+    __shared__ double sh[32 * 4 * 2];   // [slot][part][re, im]
     const int rhs = blockIdx.y;
     const int JS = J + self_norm;
-    if (!second_pass(nrm0, nrm1, rhs)) {
-        if (threadIdx.x < JS) {
-            double* p = partial + ((static_cast<int64_t>(rhs) * JS + threadIdx.x) * gridDim.x + blockIdx.x) * 2;
-            p[0] = 0.0;
-            p[1] = 0.0;
+    if (!second_pass(nrm0, nrm1, rhs)) return;
+    const VT* wr = w + static_cast<int64_t>(rhs) * N;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int sb = 0; sb < JS; sb += 32) {
+        const int ns = JS - sb < 32 ? JS - sb : 32;                  // slots of this pass
+        const int G = ns >= 4 ? 4 : (ns >= 2 ? 2 : 1), E = 4 / G;    // slot groups, element parts
+        const int g = wave % G, e = wave / G;
+        const int nk = (ns - g + G - 1) / G;                         // slots of this wavefront
+        const VT* src[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int j = sb + g + G * k;
+            if (j >= sb + ns) j = sb + ns - 1;   // unused, kept in range
+            src[k] = j < J ? V + static_cast<int64_t>(j) * vstride + static_cast<int64_t>(rhs) * N : wr;
         }
-        return;
-    }
-    const typename V2<R>::T* wr = w + static_cast<int64_t>(rhs) * N;
-    for (int j0 = 0; j0 < JS; j0 += 8) {
-        const int jn = JS - j0 < 8 ? JS - j0 : 8;
         double acc[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-        for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
-             i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
-            const typename V2<R>::T wv = wr[i];
+        const int64_t s0 = static_cast<int64_t>(blockIdx.x) * E + e, sstep = static_cast<int64_t>(gridDim.x) * E;
+        switch (nk) {
+            case 1: mdot_wave<R, 1>(src, wr, N, s0, sstep, lane, acc); break;
+            case 2: mdot_wave<R, 2>(src, wr, N, s0, sstep, lane, acc); break;
+            case 3: mdot_wave<R, 3>(src, wr, N, s0, sstep, lane, acc); break;
+            case 4: mdot_wave<R, 4>(src, wr, N, s0, sstep, lane, acc); break;
+            case 5: mdot_wave<R, 5>(src, wr, N, s0, sstep, lane, acc); break;
+            case 6: mdot_wave<R, 6>(src, wr, N, s0, sstep, lane, acc); break;
+            case 7: mdot_wave<R, 7>(src, wr, N, s0, sstep, lane, acc); break;
+            default: mdot_wave<R, 8>(src, wr, N, s0, sstep, lane, acc); break;
+        }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k < jn) {
-                    const int j = j0 + k;
-                    const typename V2<R>::T v =
-                        j < J ? V[static_cast<int64_t>(j) * vstride + static_cast<int64_t>(rhs) * N + i] : wv;
-                    // conj(v) * w
-                    acc[2 * k] += static_cast<double>(v.x) * wv.x + static_cast<double>(v.y) * wv.y;
-                    acc[2 * k + 1] += static_cast<double>(v.x) * wv.y - static_cast<double>(v.y) * wv.x;
+        for (int k = 0; k < 8; ++k) {
+            if (k < nk) {
+                const double re = wave_sum(acc[2 * k]), im = wave_sum(acc[2 * k + 1]);
+                if (lane == 0) {
+                    const int t = g + G * k;   // slot within the pass
+                    sh[(t * 4 + e) * 2] = re;
+                    sh[(t * 4 + e) * 2 + 1] = im;
                 }
             }
         }
-        block_sum<16>(acc, sh);
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < jn; ++k) {
-                double* p = partial + ((static_cast<int64_t>(rhs) * JS + j0 + k) * gridDim.x + blockIdx.x) * 2;
-                p[0] = acc[2 * k];
-                p[1] = acc[2 * k + 1];
+        __syncthreads();
+        if (threadIdx.x < ns) {
+            const int t = threadIdx.x;
+            double re = 0.0, im = 0.0;
+            for (int q = 0; q < E; ++q) {
+                re += sh[(t * 4 + q) * 2];
+                im += sh[(t * 4 + q) * 2 + 1];
             }
+            double* p = partial + ((static_cast<int64_t>(rhs) * JS + sb + t) * gridDim.x + blockIdx.x) * 2;
+            p[0] = re;
+            p[1] = im;
         }
+        __syncthreads();
     }
 }
 
@@ -200,15 +264,18 @@ __global__ __launch_bounds__(kRedBlock) void mdot_partial_kernel(const typename 
 // real part.  One block per (rhs, slot), summed in a fixed order.
 __global__ void mdot_reduce_kernel(const double* __restrict__ partial, int nb, int J, int self_norm,
                                    double2* __restrict__ h, double2* __restrict__ hsum, int ldh,
-                                   double* __restrict__ selfn) {
+                                   double* __restrict__ selfn, const double* __restrict__ nrm0,
+                                   const double* __restrict__ nrm1) {
     __shared__ double sh[8];
     const int JS = J + self_norm;
     const int rhs = blockIdx.x / JS, j = blockIdx.x % JS;
     double acc[2] = {0.0, 0.0};
-    const double* p = partial + (static_cast<int64_t>(rhs) * JS + j) * nb * 2;
-    for (int b = threadIdx.x; b < nb; b += kRedBlock) {
-        acc[0] += p[2 * b];
-        acc[1] += p[2 * b + 1];
+    if (second_pass(nrm0, nrm1, rhs)) {   // a gated-off right-hand side sums to zero
+        const double* p = partial + (static_cast<int64_t>(rhs) * JS + j) * nb * 2;
+        for (int b = threadIdx.x; b < nb; b += kRedBlock) {
+            acc[0] += p[2 * b];
+            acc[1] += p[2 * b + 1];
+        }
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
@@ -239,7 +306,7 @@ int mdot(const void* V, int64_t vstride, int J, const void* w, int64_t N, int nr
                        static_cast<const typename V2<R>::T*>(V), vstride, J,
                        static_cast<const typename V2<R>::T*>(w), N, d_partial, self_norm, d_gate0, d_gate1);
     hipLaunchKernelGGL(mdot_reduce_kernel, dim3(nrhs * (J + self_norm)), dim3(kRedBlock), 0, s, d_partial,
-                       static_cast<int>(nb), J, self_norm, d_h, d_hsum, ldh, d_selfnrm);
+                       static_cast<int>(nb), J, self_norm, d_h, d_hsum, ldh, d_selfnrm, d_gate0, d_gate1);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
