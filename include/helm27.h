@@ -212,7 +212,7 @@ int helm27_set_zchunk(helm27_op* op, int zchunk);
 /* ---- (c) solve ------------------------------------------------------------ */
 typedef struct {
     double tol;          /* relative residual ||b - A u|| / ||b|| per RHS (default 1e-6) */
-    int    restart;      /* GMRES(m) restart length, 1..63 (default 30) */
+    int    restart;      /* GMRES(m) restart length, 1..63 (default 20) */
     int    max_inner;    /* Arnoldi steps per refinement step (default 600) */
     int    max_outer;    /* FP64 refinement steps (default 10) */
     double inner_tol;    /* relative reduction asked of each inner solve (default 1e-4) */
@@ -224,7 +224,7 @@ typedef struct {
     double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 0.8) */
     int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
     double mg_omega;     /* Jacobi damping (default 0.6) */
-    int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 5) */
+    int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 3) */
     int    use_graph;    /* replay each multigrid V-cycle from one captured hipGraph
                             (captured on first use, kept with the workspace; the
                             same kernels as the eager launches, so the same

@@ -530,24 +530,27 @@ __global__ void givens_kernel(int j, int m, int nrhs, const double2* __restrict_
     double2* s = sn + static_cast<int64_t>(r) * m;
     double2* gr = g + static_cast<int64_t>(r) * (m + 1);
     double2* col = Hr + static_cast<int64_t>(j) * (m + 1);
-    for (int i = 0; i <= j; ++i) col[i] = hcol[static_cast<int64_t>(r) * ldh + i];
-    col[j + 1].x = nrm[r];
-    col[j + 1].y = 0.0;
-    // previous rotations: [a; b] <- [c a + s b; -conj(s) a + c b]
+    const double2* hc = hcol + static_cast<int64_t>(r) * ldh;
+    // previous rotations on the new column (entries 0..j of hcol, then
+    // ||w||): [a; b] <- [c a + s b; -conj(s) a + c b].  Entry i + 1 enters
+    // unrotated, entry i carries the previous rotation's second output, so only
+    // the carry is a dependence; the loads are independent of it.
+    double2 carry = hc[0];
     for (int i = 0; i < j; ++i) {
-        const double2 a = col[i], b = col[i + 1];
+        const double2 a = carry, b = hc[i + 1];
         const double ci = c[i];
         const double2 si = s[i];
         double2 t;
         t.x = ci * a.x + (si.x * b.x - si.y * b.y);
         t.y = ci * a.y + (si.x * b.y + si.y * b.x);
-        double2 u;
-        u.x = -(si.x * a.x + si.y * a.y) + ci * b.x;
-        u.y = -(si.x * a.y - si.y * a.x) + ci * b.y;
+        carry.x = -(si.x * a.x + si.y * a.y) + ci * b.x;
+        carry.y = -(si.x * a.y - si.y * a.x) + ci * b.y;
         col[i] = t;
-        col[i + 1] = u;
     }
-    const double2 a = col[j], b = col[j + 1];
+    const double2 a = carry;
+    double2 b;
+    b.x = nrm[r];
+    b.y = 0.0;
     const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
     const double rho = hypot(na, nb);
     double cj;
@@ -648,76 +651,97 @@ int upper_solve(int k, int m, int nrhs, const double2* H, const double2* g, doub
 // ((nx+1)/2, ...): coarse node i sits on fine node 2i.  Full weighting
 // (1/4, 1/2, 1/4 per axis, fine nodes outside the grid count as zero) and its
 // adjoint up to a factor 8, trilinear interpolation.
+constexpr int kXferRows = 4;   // y rows per transfer block (one wavefront each)
+
 template <typename R>
-__global__ void restrict_kernel(const typename V2<R>::T* __restrict__ f, int nx, int ny, int nz,
-                                typename V2<R>::T* __restrict__ c, int cx, int cy, int cz, int nrhs) {
-    // one coarse node per thread: x from the block's 64-wide strip, y and
-    // (z, rhs) from the grid (no integer division per thread)
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y;
+__global__ __launch_bounds__(64 * kXferRows) void restrict_kernel(const typename V2<R>::T* __restrict__ f, int nx,
+                                                                 int ny, int nz, typename V2<R>::T* __restrict__ c,
+                                                                 int cx, int cy, int cz, int nrhs) {
+    // one coarse node per thread: x from the block's 64-wide strip, y from the
+    // block's rows, (z, rhs) from the grid (no integer division per thread).
+    // The 27 fine loads use clamped indices (weight 0 outside the grid), so
+    // every one of them is issued before the first is used.
+    using V = typename V2<R>::T;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * kXferRows + (threadIdx.x >> 6);
     const int k = blockIdx.z % cz, rhs = blockIdx.z / cz;
-    if (i >= cx) return;
+    if (i >= cx || j >= cy) return;
     const int64_t Nf = static_cast<int64_t>(nx) * ny * nz;
-    const typename V2<R>::T* fr = f + static_cast<int64_t>(rhs) * Nf;
-    R sx = 0, sy = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int z = 2 * k + dz;
-        if (z < 0 || z >= nz) continue;
-        const R wz = dz == 0 ? R(0.5) : R(0.25);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = 2 * j + dy;
-            if (y < 0 || y >= ny) continue;
-            const R wy = wz * (dy == 0 ? R(0.5) : R(0.25));
-            const typename V2<R>::T* row = fr + (static_cast<int64_t>(z) * ny + y) * nx;
+    const V* fr = f + static_cast<int64_t>(rhs) * Nf;
+    int xs[3], ys[3], zs[3];
+    R wx[3], wy[3], wz[3];
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = 2 * i + dx;
-                if (x < 0 || x >= nx) continue;
-                const R w = wy * (dx == 0 ? R(0.5) : R(0.25));
-                const typename V2<R>::T v = row[x];
-                sx += w * v.x;
-                sy += w * v.y;
+    for (int d = 0; d < 3; ++d) {
+        const R wd = d == 1 ? R(0.5) : R(0.25);
+        const int x = 2 * i + d - 1, y = 2 * j + d - 1, z = 2 * k + d - 1;
+        wx[d] = x >= 0 && x < nx ? wd : R(0);
+        wy[d] = y >= 0 && y < ny ? wd : R(0);
+        wz[d] = z >= 0 && z < nz ? wd : R(0);
+        xs[d] = min(max(x, 0), nx - 1);
+        ys[d] = min(max(y, 0), ny - 1);
+        zs[d] = min(max(z, 0), nz - 1);
+    }
+    V v[27];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const V* row = fr + (static_cast<int64_t>(zs[a]) * ny + ys[b]) * nx;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) v[(a * 3 + b) * 3 + d] = row[xs[d]];
+        }
+    R sx = 0, sy = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const R wab = wz[a] * wy[b];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const R w = wab * wx[d];
+                sx += w * v[(a * 3 + b) * 3 + d].x;
+                sy += w * v[(a * 3 + b) * 3 + d].y;
             }
         }
-    }
-    typename V2<R>::T o;
+    V o;
     o.x = sx;
     o.y = sy;
     c[static_cast<int64_t>(rhs) * cx * cy * cz + (static_cast<int64_t>(k) * cy + j) * cx + i] = o;
 }
 
 template <typename R>
-__global__ void prolong_add_kernel(const typename V2<R>::T* __restrict__ c, int cx, int cy, int cz,
-                                   typename V2<R>::T* __restrict__ f, int nx, int ny, int nz, int nrhs) {
+__global__ __launch_bounds__(64 * kXferRows) void prolong_add_kernel(const typename V2<R>::T* __restrict__ c, int cx,
+                                                                    int cy, int cz, typename V2<R>::T* __restrict__ f,
+                                                                    int nx, int ny, int nz, int nrhs) {
     // one fine node per thread (trilinear interpolation of the coarse
-    // correction); x from the block's strip, y and (z, rhs) from the grid
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y;
+    // correction); x from the block's strip, y from the block's rows, (z, rhs)
+    // from the grid.  Per axis an even node takes one coarse node (weight 1),
+    // an odd node two (1/2 each); the second node's index is clamped and its
+    // weight is 0 where it is not used, so all eight loads are issued at once.
+    using V = typename V2<R>::T;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * kXferRows + (threadIdx.x >> 6);
     const int z = blockIdx.z % nz, rhs = blockIdx.z / nz;
-    if (x >= nx) return;
-    const typename V2<R>::T* cr = c + static_cast<int64_t>(rhs) * cx * cy * cz;
-    // per axis: even -> one coarse node (weight 1), odd -> two (1/2 each)
+    if (x >= nx || y >= ny) return;
+    const V* cr = c + static_cast<int64_t>(rhs) * cx * cy * cz;
     const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-    const int nxs = (x & 1) ? 2 : 1, nys = (y & 1) ? 2 : 1, nzs = (z & 1) ? 2 : 1;
-    const R w = ((x & 1) ? R(0.5) : R(1)) * ((y & 1) ? R(0.5) : R(1)) * ((z & 1) ? R(0.5) : R(1));
-    R sx = 0, sy = 0;
-    for (int a = 0; a < nzs; ++a) {
-        if (z0 + a >= cz) continue;
-        for (int b = 0; b < nys; ++b) {
-            if (y0 + b >= cy) continue;
-            const typename V2<R>::T* row = cr + (static_cast<int64_t>(z0 + a) * cy + y0 + b) * cx;
-            for (int e = 0; e < nxs; ++e) {
-                if (x0 + e >= cx) continue;
-                const typename V2<R>::T v = row[x0 + e];
-                sx += w * v.x;
-                sy += w * v.y;
-            }
-        }
-    }
-    typename V2<R>::T* fp = f + static_cast<int64_t>(rhs) * nx * ny * nz + (static_cast<int64_t>(z) * ny + y) * nx + x;
-    typename V2<R>::T o = *fp;
-    o.x += sx;
-    o.y += sy;
+    const int x1 = min(x0 + 1, cx - 1), y1 = min(y0 + 1, cy - 1), z1 = min(z0 + 1, cz - 1);
+    const R hx = (x & 1) && x0 + 1 < cx ? R(0.5) : R(0), hy = (y & 1) && y0 + 1 < cy ? R(0.5) : R(0),
+            hz = (z & 1) && z0 + 1 < cz ? R(0.5) : R(0);
+    const R gx = (x & 1) ? R(0.5) : R(1), gy = (y & 1) ? R(0.5) : R(1), gz = (z & 1) ? R(0.5) : R(1);
+    V* fp = f + static_cast<int64_t>(rhs) * nx * ny * nz + (static_cast<int64_t>(z) * ny + y) * nx + x;
+    const V* r00 = cr + (static_cast<int64_t>(z0) * cy + y0) * cx;
+    const V* r01 = cr + (static_cast<int64_t>(z0) * cy + y1) * cx;
+    const V* r10 = cr + (static_cast<int64_t>(z1) * cy + y0) * cx;
+    const V* r11 = cr + (static_cast<int64_t>(z1) * cy + y1) * cx;
+    const V a0 = r00[x0], a1 = r00[x1], b0 = r01[x0], b1 = r01[x1];
+    const V c0 = r10[x0], c1 = r10[x1], d0 = r11[x0], d1 = r11[x1];
+    V o = *fp;
+    const R w00 = gz * gy, w01 = gz * hy, w10 = hz * gy, w11 = hz * hy;
+    o.x += w00 * (gx * a0.x + hx * a1.x) + w01 * (gx * b0.x + hx * b1.x) + w10 * (gx * c0.x + hx * c1.x) +
+           w11 * (gx * d0.x + hx * d1.x);
+    o.y += w00 * (gx * a0.y + hx * a1.y) + w01 * (gx * b0.y + hx * b1.y) + w10 * (gx * c0.y + hx * c1.y) +
+           w11 * (gx * d0.y + hx * d1.y);
     *fp = o;
 }
 
@@ -730,7 +754,8 @@ int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, 
     const int64_t Nf = static_cast<int64_t>(nx) * ny * nz, Nc = static_cast<int64_t>(cx) * cy * cz;
     for (int r0 = 0; r0 < nrhs; r0 += per) {
         const int n = nrhs - r0 < per ? nrhs - r0 : per;
-        H27_CHECK_HIP(launch(restrict_kernel<R>, dim3((cx + 63) / 64, cy, cz * n), dim3(64), 0, s,
+        H27_CHECK_HIP(launch(restrict_kernel<R>, dim3((cx + 63) / 64, (cy + kXferRows - 1) / kXferRows, cz * n),
+                             dim3(64 * kXferRows), 0, s,
                              static_cast<const V*>(f) + r0 * Nf, nx, ny, nz, static_cast<V*>(c) + r0 * Nc, cx, cy, cz,
                              n));
     }
@@ -745,7 +770,8 @@ int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int n
     const int64_t Nf = static_cast<int64_t>(nx) * ny * nz, Nc = static_cast<int64_t>(cx) * cy * cz;
     for (int r0 = 0; r0 < nrhs; r0 += per) {
         const int n = nrhs - r0 < per ? nrhs - r0 : per;
-        H27_CHECK_HIP(launch(prolong_add_kernel<R>, dim3((nx + 63) / 64, ny, nz * n), dim3(64), 0, s,
+        H27_CHECK_HIP(launch(prolong_add_kernel<R>, dim3((nx + 63) / 64, (ny + kXferRows - 1) / kXferRows, nz * n),
+                             dim3(64 * kXferRows), 0, s,
                              static_cast<const V*>(c) + r0 * Nc, cx, cy, cz, static_cast<V*>(f) + r0 * Nf, nx, ny,
                              nz, n));
     }

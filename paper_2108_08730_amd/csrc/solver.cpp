@@ -569,7 +569,7 @@ void solver_free(helm27_op* op) {
 extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     if (!o) return;
     o->tol = 1e-6;
-    o->restart = 30;
+    o->restart = 20;
     o->max_inner = 600;
     o->max_outer = 10;
     o->inner_tol = 1e-4;
@@ -580,7 +580,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->mg_pre = 2;
     o->mg_post = 2;
     o->mg_omega = 0.6;
-    o->mg_coarse_sweeps = 5;
+    o->mg_coarse_sweeps = 3;
     o->use_graph = 1;
     o->reorth_always = 0;
     o->verbose = 0;
