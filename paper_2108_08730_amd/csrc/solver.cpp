@@ -50,6 +50,10 @@ struct SolverState {
     double* d_n1 = nullptr;
     double* d_beta = nullptr;
     double* d_est = nullptr;
+    // residual estimates copied to pinned host memory each Arnoldi step, two
+    // slots [2][nrhs] so the host checks step j - 1 while step j runs
+    double* h_est = nullptr;
+    hipEvent_t est_ev[2] = {nullptr, nullptr};
     double* d_rn = nullptr;
     double* d_bn = nullptr;
     double2* d_H = nullptr;
@@ -79,6 +83,8 @@ static void drop_graph(SolverState* S) {
 static void free_workspace(SolverState* S) {
     drop_graph(S);
     S->vin = nullptr;
+    if (S->h_est) hipHostFree(S->h_est);
+    S->h_est = nullptr;
     for (void* p : S->bufs) hipFree(p);
     S->bufs.clear();
     S->X.clear();
@@ -234,6 +240,13 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->d_bn = dd[4];
     S->d_n0 = dd[5];
     S->d_n1 = dd[6];
+    if (hipHostMalloc(reinterpret_cast<void**>(&S->h_est), 2 * static_cast<size_t>(nrhs) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        S->h_est = nullptr;
+        return HELM27_ENOMEM;
+    }
+    for (int k = 0; k < 2; ++k)
+        if (!S->est_ev[k]) H27_CHECK_HIP(hipEventCreateWithFlags(&S->est_ev[k], hipEventDisableTiming));
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1) * m * sizeof(double2)))) return st;
     S->d_H = static_cast<double2*>(p);
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * m * sizeof(double)))) return st;
@@ -366,6 +379,22 @@ static int read_host(std::vector<double>* h, const double* d, int n, hipStream_t
     return HELM27_OK;
 }
 
+// Waits for the pinned copy of Arnoldi step j's residual estimates; done when
+// every right-hand side is at or below its threshold.
+static int check_est(const Ctx& c, int j, const std::vector<double>& thr, const std::vector<double>& bn, int it,
+                     bool* done) {
+    H27_CHECK_HIP(hipEventSynchronize(c.S->est_ev[j & 1]));
+    const double* est = c.S->h_est + (j & 1) * c.nrhs;
+    *done = true;
+    for (int q = 0; q < c.nrhs; ++q) {
+        if (!std::isfinite(est[q])) return HELM27_ENUMERIC;
+        if (est[q] > thr[q] * bn[q]) *done = false;
+    }
+    if (c.o->verbose)
+        std::fprintf(stderr, "helm27: gmres it %d est[0] %.3e (target %.3e)\n", it, est[0], thr[0] * bn[0]);
+    return HELM27_OK;
+}
+
 // GMRES(m) on A x = rhs (inner precision R), x starting at zero.  Stops when
 // every right-hand side's residual estimate is <= thr[rhs] * ||rhs||.
 template <typename R>
@@ -380,7 +409,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
     const size_t eb = 2 * sizeof(R);
     int st;
     if ((st = fill_zero(x, vbytes, c.s))) return st;
-    std::vector<double> bn, est;
+    std::vector<double> bn;
     if ((st = norms<R>(rhs, N, nrhs, S->d_partial, S->max_blocks, S->d_nrm, c.s))) return st;
     if ((st = read_host(&bn, S->d_nrm, nrhs, c.s))) return st;
     for (double v : bn)
@@ -443,18 +472,30 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
                 return st;
             ++it;
             k = j + 1;
-            if ((st = read_host(&est, S->d_est, nrhs, c.s))) return st;
-            bool done = true;
-            for (int q = 0; q < nrhs; ++q) {
-                if (!std::isfinite(est[q])) return HELM27_ENUMERIC;
-                if (est[q] > thr[q] * bn[q]) done = false;
+            // the estimate of step j goes to pinned memory; the host then
+            // checks step j - 1, whose copy is normally complete while step j
+            // runs, so the device never waits for the host between steps.  If
+            // step j - 1 converged, step j is dropped (k = j): its kernels
+            // touched only column j, g[j..j+1] and v_{j+1}, none of which the
+            // solution update with k = j reads.
+            H27_CHECK_HIP(hipMemcpyAsync(S->h_est + (j & 1) * nrhs, S->d_est, nrhs * sizeof(double),
+                                         hipMemcpyDeviceToHost, c.s));
+            H27_CHECK_HIP(hipEventRecord(S->est_ev[j & 1], c.s));
+            if (j > 0) {
+                bool done = false;
+                if ((st = check_est(c, j - 1, thr, bn, it - 1, &done))) return st;
+                if (done) {
+                    --it;
+                    k = j;
+                    cyc_conv = true;
+                    break;
+                }
             }
-            if (c.o->verbose)
-                std::fprintf(stderr, "helm27: gmres it %d est[0] %.3e (target %.3e)\n", it, est[0], thr[0] * bn[0]);
-            if (done) {
-                cyc_conv = true;
-                break;
-            }
+        }
+        if (!cyc_conv && k > 0) {
+            bool done = false;
+            if ((st = check_est(c, k - 1, thr, bn, it, &done))) return st;
+            cyc_conv = done;
         }
         if ((st = upper_solve(k, m, nrhs, S->d_H, S->d_g, S->d_y, ldh, c.s))) return st;
         void* z = nullptr;
@@ -559,6 +600,8 @@ void solver_free(helm27_op* op) {
     SolverState* S = static_cast<SolverState*>(op->solver);
     free_workspace(S);
     free_hierarchy(S);
+    for (hipEvent_t e : S->est_ev)
+        if (e) hipEventDestroy(e);
     hipFree(S->d_lin);
     hipFree(S->d_amp);
     hipFree(S->d_b);
