@@ -68,6 +68,61 @@ int fill_zero(void* p, int64_t bytes, hipStream_t s) {
     return HELM27_OK;
 }
 
+// y = d * v (complex) with a fixed operation order (explicit fused
+// multiply-adds), so every kernel that forms the first Jacobi sweep
+// omega D^-1 b from the stored omega D^-1 gets the same bits.
+template <typename V>
+__device__ __forceinline__ V dmul(V d, V v) {
+    V y;
+    y.x = fma(d.x, v.x, -(d.y * v.y));
+    y.y = fma(d.x, v.y, d.y * v.x);
+    return y;
+}
+
+template <typename R>
+__global__ void fill_one_kernel(typename V2<R>::T* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        typename V2<R>::T o;
+        o.x = R(1);
+        o.y = R(0);
+        p[i] = o;
+    }
+}
+
+template <typename R>
+int fill_one(void* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return HELM27_OK;
+    H27_CHECK_HIP(launch(fill_one_kernel<R>, dim3(grid_for(n)), dim3(kRedBlock), 0, s,
+                         static_cast<typename V2<R>::T*>(p), n));
+    return HELM27_OK;
+}
+template int fill_one<float>(void*, int64_t, hipStream_t);
+template int fill_one<double>(void*, int64_t, hipStream_t);
+
+// y[rhs] = dinv * b[rhs] per point (the first damped-Jacobi sweep from a zero
+// iterate, with dinv = omega D^-1 stored once per level)
+template <typename R>
+__global__ void dinv_scale_kernel(const typename V2<R>::T* __restrict__ dinv, const typename V2<R>::T* __restrict__ b,
+                                  typename V2<R>::T* __restrict__ y, int64_t N) {
+    const int rhs = blockIdx.y;
+    const typename V2<R>::T* br = b + static_cast<int64_t>(rhs) * N;
+    typename V2<R>::T* yr = y + static_cast<int64_t>(rhs) * N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * kRedBlock)
+        yr[i] = dmul(dinv[i], br[i]);
+}
+
+template <typename R>
+int dinv_scale(const void* dinv, const void* b, void* y, int64_t N, int nrhs, hipStream_t s) {
+    using V = typename V2<R>::T;
+    H27_CHECK_HIP(launch(dinv_scale_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
+                         static_cast<const V*>(dinv), static_cast<const V*>(b), static_cast<V*>(y), N));
+    return HELM27_OK;
+}
+template int dinv_scale<float>(const void*, const void*, void*, int64_t, int, hipStream_t);
+template int dinv_scale<double>(const void*, const void*, void*, int64_t, int, hipStream_t);
+
 // b[s][lin_s] = amp_s / h^3 (paper Sec. 3.1: delta source on a grid node)
 __global__ void inject_kernel(double2* __restrict__ b, int64_t N, const int64_t* __restrict__ lin,
                               const double2* __restrict__ amp, int nsrc, double inv_h3) {
@@ -387,13 +442,15 @@ template int cgs_update<double>(const void*, int64_t, int, const double2*, int, 
 template <typename Ri, typename Ro>
 __global__ void scale_kernel(const typename V2<Ri>::T* __restrict__ x, typename V2<Ro>::T* __restrict__ out,
                              typename V2<Ro>::T* __restrict__ out2, int64_t N, const double* __restrict__ nrm,
-                             int mode) {
+                             int mode, const typename V2<Ro>::T* __restrict__ dinv,
+                             typename V2<Ro>::T* __restrict__ yout) {
     const int rhs = blockIdx.y;
     const double n = nrm[rhs];
     const double f = mode == 0 ? (n > 0 ? 1.0 / n : 0.0) : n;
     const typename V2<Ri>::T* xr = x + static_cast<int64_t>(rhs) * N;
     typename V2<Ro>::T* orr = out + static_cast<int64_t>(rhs) * N;
     typename V2<Ro>::T* orr2 = out2 ? out2 + static_cast<int64_t>(rhs) * N : nullptr;
+    typename V2<Ro>::T* yr = yout ? yout + static_cast<int64_t>(rhs) * N : nullptr;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kRedBlock) + threadIdx.x; i < N;
          i += static_cast<int64_t>(gridDim.x) * kRedBlock) {
         const typename V2<Ri>::T v = xr[i];
@@ -402,21 +459,26 @@ __global__ void scale_kernel(const typename V2<Ri>::T* __restrict__ x, typename 
         o.y = static_cast<Ro>(static_cast<double>(v.y) * f);
         orr[i] = o;
         if (orr2) orr2[i] = o;
+        if (yr) yr[i] = dmul(dinv[i], o);
     }
 }
 
 template <typename Ri, typename Ro>
 int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s,
-                  void* out2) {
+                  void* out2, const void* dinv, void* yout) {
+    using Vo = typename V2<Ro>::T;
     hipLaunchKernelGGL((scale_kernel<Ri, Ro>), dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
-                       static_cast<const typename V2<Ri>::T*>(x), static_cast<typename V2<Ro>::T*>(out),
-                       static_cast<typename V2<Ro>::T*>(out2), N, d_nrm, mode);
+                       static_cast<const typename V2<Ri>::T*>(x), static_cast<Vo*>(out), static_cast<Vo*>(out2), N,
+                       d_nrm, mode, static_cast<const Vo*>(dinv), dinv ? static_cast<Vo*>(yout) : nullptr);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
-template int scale_by_norm<float, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*);
-template int scale_by_norm<double, double>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*);
-template int scale_by_norm<double, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*);
+template int scale_by_norm<float, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*,
+                                          const void*, void*);
+template int scale_by_norm<double, double>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*,
+                                          const void*, void*);
+template int scale_by_norm<double, float>(const void*, void*, int64_t, int, const double*, int, hipStream_t, void*,
+                                          const void*, void*);
 
 // u64[rhs] += nrm[rhs] * e[rhs]  (refinement update, e in the inner precision)
 template <typename R>
@@ -450,7 +512,9 @@ template int refine_update<double>(double2*, const void*, int64_t, int, const do
 template <typename R>
 __global__ __launch_bounds__(kRedBlock) void combine_kernel(const typename V2<R>::T* __restrict__ V, int64_t vstride, int k,
                                                             const double2* __restrict__ y, int ldy,
-                                                            typename V2<R>::T* __restrict__ x, int64_t N, int accumulate) {
+                                                            typename V2<R>::T* __restrict__ x, int64_t N, int accumulate,
+                                                            const typename V2<R>::T* __restrict__ dinv,
+                                                            typename V2<R>::T* __restrict__ yout) {
     __shared__ R ys[2 * 64];
     const int rhs = blockIdx.y;
     for (int j = threadIdx.x; j < k; j += kRedBlock) {
@@ -476,21 +540,25 @@ __global__ __launch_bounds__(kRedBlock) void combine_kernel(const typename V2<R>
             acc.y += v.x * yi + v.y * yr;
         }
         xr[i] = acc;
+        if (yout) yout[static_cast<int64_t>(rhs) * N + i] = dmul(dinv[i], acc);
     }
 }
 
 template <typename R>
 int combine(const void* V, int64_t vstride, int k, const double2* d_y, int ldy, void* x, int64_t N, int nrhs,
-            int accumulate, hipStream_t s) {
+            int accumulate, hipStream_t s, const void* dinv, void* yout) {
+    using VT = typename V2<R>::T;
     if (k > 64) return HELM27_EINVAL;
-    hipLaunchKernelGGL(combine_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s,
-                       static_cast<const typename V2<R>::T*>(V), vstride, k, d_y, ldy,
-                       static_cast<typename V2<R>::T*>(x), N, accumulate);
+    hipLaunchKernelGGL(combine_kernel<R>, dim3(grid_for(N), nrhs), dim3(kRedBlock), 0, s, static_cast<const VT*>(V),
+                       vstride, k, d_y, ldy, static_cast<VT*>(x), N, accumulate, static_cast<const VT*>(dinv),
+                       dinv ? static_cast<VT*>(yout) : nullptr);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
-template int combine<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, int, hipStream_t);
-template int combine<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, int, hipStream_t);
+template int combine<float>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, int, hipStream_t,
+                            const void*, void*);
+template int combine<double>(const void*, int64_t, int, const double2*, int, void*, int64_t, int, int, hipStream_t,
+                             const void*, void*);
 
 // x[rhs] += y[rhs]
 template <typename R>
@@ -656,7 +724,9 @@ constexpr int kXferRows = 4;   // y rows per transfer block (one wavefront each)
 template <typename R>
 __global__ __launch_bounds__(64 * kXferRows) void restrict_kernel(const typename V2<R>::T* __restrict__ f, int nx,
                                                                  int ny, int nz, typename V2<R>::T* __restrict__ c,
-                                                                 int cx, int cy, int cz, int nrhs) {
+                                                                 int cx, int cy, int cz, int nrhs,
+                                                                 const typename V2<R>::T* __restrict__ dinv,
+                                                                 typename V2<R>::T* __restrict__ yout) {
     // one coarse node per thread: x from the block's 64-wide strip, y from the
     // block's rows, (z, rhs) from the grid (no integer division per thread).
     // The 27 fine loads use clamped indices (weight 0 outside the grid), so
@@ -706,7 +776,9 @@ __global__ __launch_bounds__(64 * kXferRows) void restrict_kernel(const typename
     V o;
     o.x = sx;
     o.y = sy;
-    c[static_cast<int64_t>(rhs) * cx * cy * cz + (static_cast<int64_t>(k) * cy + j) * cx + i] = o;
+    const int64_t pc = (static_cast<int64_t>(k) * cy + j) * cx + i;
+    c[static_cast<int64_t>(rhs) * cx * cy * cz + pc] = o;
+    if (yout) yout[static_cast<int64_t>(rhs) * cx * cy * cz + pc] = dmul(dinv[pc], o);   // first coarse sweep
 }
 
 template <typename R>
@@ -746,7 +818,8 @@ __global__ __launch_bounds__(64 * kXferRows) void prolong_add_kernel(const typen
 }
 
 template <typename R>
-int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s) {
+int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s,
+                const void* dinv, void* yout) {
     using V = typename V2<R>::T;
     if (static_cast<int64_t>(cx) * cy * cz * nrhs <= 0) return HELM27_OK;
     if (cy > 65535 || cz > 65535) return HELM27_EINVAL;
@@ -757,7 +830,7 @@ int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, 
         H27_CHECK_HIP(launch(restrict_kernel<R>, dim3((cx + 63) / 64, (cy + kXferRows - 1) / kXferRows, cz * n),
                              dim3(64 * kXferRows), 0, s,
                              static_cast<const V*>(f) + r0 * Nf, nx, ny, nz, static_cast<V*>(c) + r0 * Nc, cx, cy, cz,
-                             n));
+                             n, static_cast<const V*>(dinv), dinv ? static_cast<V*>(yout) + r0 * Nc : nullptr));
     }
     return HELM27_OK;
 }
@@ -777,8 +850,9 @@ int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int n
     }
     return HELM27_OK;
 }
-template int mg_restrict<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
-template int mg_restrict<double>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
+template int mg_restrict<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t, const void*, void*);
+template int mg_restrict<double>(const void*, int, int, int, void*, int, int, int, int, hipStream_t, const void*,
+                                 void*);
 template int mg_prolong_add<float>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
 template int mg_prolong_add<double>(const void*, int, int, int, void*, int, int, int, int, hipStream_t);
 

@@ -30,23 +30,34 @@ int cgs_update(const void* V, int64_t vstride, int J, const double2* d_hc, int l
                double* d_partial, int max_blocks, double* d_nrm, hipStream_t s, const double* d_gate0 = nullptr,
                const double* d_gate1 = nullptr);
 // out = x / nrm (mode 0) or x * nrm (mode 1), per right-hand side; the same
-// values also to out2 when it is not null
+// values also to out2 when it is not null, and dinv * out to yout when dinv is
+// not null (dinv: one value per point, shared by the right-hand sides)
 template <typename Ri, typename Ro>
 int scale_by_norm(const void* x, void* out, int64_t N, int nrhs, const double* d_nrm, int mode, hipStream_t s,
-                  void* out2 = nullptr);
+                  void* out2 = nullptr, const void* dinv = nullptr, void* yout = nullptr);
+// p[0..n) = 1 (complex)
+template <typename R>
+int fill_one(void* p, int64_t n, hipStream_t s);
+// y[rhs] = dinv * b[rhs] per point: the first damped-Jacobi sweep from a zero
+// iterate when dinv = omega D^-1
+template <typename R>
+int dinv_scale(const void* dinv, const void* b, void* y, int64_t N, int nrhs, hipStream_t s);
 template <typename R>
 int refine_update(double2* u, const void* e, int64_t N, int nrhs, const double* d_nrm, hipStream_t s);
+// x[rhs] (+)= sum_{j<k} V_j[rhs] y[rhs][j]; with dinv also yout = dinv * x
 template <typename R>
 int combine(const void* V, int64_t vstride, int k, const double2* d_y, int ldy, void* x, int64_t N, int nrhs,
-            int accumulate, hipStream_t s);
+            int accumulate, hipStream_t s, const void* dinv = nullptr, void* yout = nullptr);
 template <typename R>
 int add_inplace(void* x, const void* y, int64_t n, hipStream_t s);
 int givens_init(double2* g, int m, int nrhs, const double* beta, hipStream_t s);
 int givens_step(int j, int m, int nrhs, const double2* hcol, int ldh, const double* nrm, double2* H, double* cs,
                 double2* sn, double2* g, double* est, hipStream_t s);
 int upper_solve(int k, int m, int nrhs, const double2* H, const double2* g, double2* y, int ldy, hipStream_t s);
+// full-weighting restriction f -> c; with dinv (coarse grid) also yout = dinv * c
 template <typename R>
-int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s);
+int mg_restrict(const void* f, int nx, int ny, int nz, void* c, int cx, int cy, int cz, int nrhs, hipStream_t s,
+                const void* dinv = nullptr, void* yout = nullptr);
 template <typename R>
 int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int ny, int nz, int nrhs, hipStream_t s);
 int inject_velocity(const float* f, int nx, int ny, float* c, int cx, int cy, int cz, hipStream_t s);

@@ -40,6 +40,13 @@ struct SolverState {
     void* rin = nullptr;
     void* tmp = nullptr;
     std::vector<void*> X, T, B, Rr;  // per level
+    // per level, one value per point: omega D^-1 of the shifted operator (the
+    // first damped-Jacobi sweep from zero is dinv * b); null where the level
+    // runs without the wavefront kernel.  Keyed by shift, omega, precision.
+    std::vector<void*> Dv;
+    bool dv_ok = false;
+    double dv_key[3] = {0, 0, 0};
+    void* vy = nullptr;              // dinv * vin, the V-cycle graph's first iterate
     double2* r64 = nullptr;
     double* d_partial = nullptr;
     int max_blocks = 1024;
@@ -85,6 +92,9 @@ static void free_workspace(SolverState* S) {
     S->vin = nullptr;
     if (S->h_est) hipHostFree(S->h_est);
     S->h_est = nullptr;
+    S->Dv.clear();
+    S->dv_ok = false;
+    S->vy = nullptr;
     for (void* p : S->bufs) hipFree(p);
     S->bufs.clear();
     S->X.clear();
@@ -199,6 +209,8 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     if ((st = alloc(S, &S->rin, vec))) return st;
     if ((st = alloc(S, &S->tmp, vec))) return st;
     if ((st = alloc(S, &S->vin, vec))) return st;
+    if ((st = alloc(S, &S->vy, vec))) return st;
+    S->Dv.assign(S->levels, nullptr);
     S->X.resize(S->levels);
     S->T.resize(S->levels);
     S->B.resize(S->levels);
@@ -213,6 +225,9 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
         } else {
             S->B[l] = nullptr;
         }
+        const GridOp& Gl = level_grid(op, S, l);
+        if (stencil_wave_path(Gl, prec == 8))
+            if ((st = alloc(S, &S->Dv[l], static_cast<size_t>(Gl.N) * vb))) return st;
     }
     void* p;
     if ((st = alloc(S, &p, static_cast<size_t>(N) * nrhs * sizeof(double2)))) return st;
@@ -270,10 +285,36 @@ struct Ctx {
     int nrhs;
 };
 
-// One V-cycle on level l for right-hand side b (inner precision R); returns
-// the buffer that holds the result.
+// omega D^-1 of the shifted operator on every level that has a Dv buffer:
+// the first-sweep kernel applied to b = 1 (recomputed when the shift, omega
+// or the precision change).  Runs outside any graph recording.
 template <typename R>
-static int vcycle(const Ctx& c, int l, const void* b, void** out) {
+static int ensure_dinv(const Ctx& c) {
+    SolverState* S = c.S;
+    const double key[3] = {c.o->mg_shift_re, c.o->mg_shift, c.o->mg_omega};
+    if (S->dv_ok && key[0] == S->dv_key[0] && key[1] == S->dv_key[1] && key[2] == S->dv_key[2]) return HELM27_OK;
+    int st;
+    for (int l = 0; l < S->levels && l < static_cast<int>(S->Dv.size()); ++l) {
+        if (!S->Dv[l]) continue;
+        const GridOp& G = level_grid(c.op, S, l);
+        if ((st = fill_one<R>(S->Rr[l], G.N, c.s))) return st;
+        if ((st = launch_stencil<R>(G, MODE_JACOBI0, key[0], key[1], nullptr, S->Dv[l], S->Rr[l], key[2], 1, c.s)))
+            return st;
+    }
+    for (int k = 0; k < 3; ++k) S->dv_key[k] = key[k];
+    S->dv_ok = true;
+    return HELM27_OK;
+}
+
+static int level_pre(const Ctx& c, int l) {
+    return l == c.S->levels - 1 ? c.o->mg_coarse_sweeps : c.o->mg_pre;
+}
+
+// One V-cycle on level l for right-hand side b (inner precision R); returns
+// the buffer that holds the result.  y0 (optional) holds the first sweep
+// dinv * b, formed by the kernel that produced b.
+template <typename R>
+static int vcycle(const Ctx& c, int l, const void* b, void** out, void* y0 = nullptr) {
     SolverState* S = c.S;
     const GridOp& G = level_grid(c.op, S, l);
     const int64_t bytes = G.N * c.nrhs * static_cast<int64_t>(2 * sizeof(R));
@@ -282,13 +323,15 @@ static int vcycle(const Ctx& c, int l, const void* b, void** out) {
     int st;
     const bool coarsest = l == S->levels - 1;
     const double a = c.o->mg_shift_re, bshift = c.o->mg_shift;
-    const int pre = coarsest ? c.o->mg_coarse_sweeps : c.o->mg_pre;
-    // the iterate starts at zero: the first sweep is omega D^-1 b
-    const bool zero_sweep = pre > 0 && stencil_wave_path(G, sizeof(R) == 8);
+    const int pre = level_pre(c, l);
+    // the iterate starts at zero: the first sweep is omega D^-1 b = dinv * b
+    const bool zero_sweep = pre > 0 && S->Dv[l];
     if (zero_sweep) {
-        if ((st = launch_stencil<R>(G, MODE_JACOBI0, a, bshift, nullptr, t, b, c.o->mg_omega, c.nrhs, c.s)))
+        if (y0) {
+            x = y0;
+        } else if ((st = dinv_scale<R>(S->Dv[l], b, x, G.N, c.nrhs, c.s))) {
             return st;
-        std::swap(x, t);
+        }
     } else if ((st = fill_zero(x, bytes, c.s))) {
         return st;
     }
@@ -299,9 +342,13 @@ static int vcycle(const Ctx& c, int l, const void* b, void** out) {
     if (!coarsest) {
         const GridOp& Gc = level_grid(c.op, S, l + 1);
         if ((st = launch_stencil<R>(G, MODE_RESID, a, bshift, x, S->Rr[l], b, 0.0, c.nrhs, c.s))) return st;
-        if ((st = mg_restrict<R>(S->Rr[l], G.nx, G.ny, G.nz, S->B[l + 1], Gc.nx, Gc.ny, Gc.nz, c.nrhs, c.s))) return st;
+        // the restriction also forms the coarse level's first sweep
+        void* yc = level_pre(c, l + 1) > 0 && S->Dv[l + 1] ? S->X[l + 1] : nullptr;
+        if ((st = mg_restrict<R>(S->Rr[l], G.nx, G.ny, G.nz, S->B[l + 1], Gc.nx, Gc.ny, Gc.nz, c.nrhs, c.s,
+                                 yc ? S->Dv[l + 1] : nullptr, yc)))
+            return st;
         void* xc = nullptr;
-        if ((st = vcycle<R>(c, l + 1, S->B[l + 1], &xc))) return st;
+        if ((st = vcycle<R>(c, l + 1, S->B[l + 1], &xc, yc))) return st;
         if ((st = mg_prolong_add<R>(xc, Gc.nx, Gc.ny, Gc.nz, x, G.nx, G.ny, G.nz, c.nrhs, c.s))) return st;
         for (int k = 0; k < c.o->mg_post; ++k) {
             if ((st = launch_stencil<R>(G, MODE_JACOBI, a, bshift, x, t, b, c.o->mg_omega, c.nrhs, c.s))) return st;
@@ -320,6 +367,12 @@ static int precond(const Ctx& c, const void* v, void** z) {
         return HELM27_OK;
     }
     return vcycle<R>(c, 0, v, z);
+}
+
+// dinv * vin is formed by the kernels that write vin when the finest level
+// has a Dv buffer and a pre-sweep
+static void* vin_y0(const Ctx& c) {
+    return level_pre(c, 0) > 0 && !c.S->Dv.empty() && c.S->Dv[0] ? c.S->vy : nullptr;
 }
 
 static bool use_vgraph(const Ctx& c) {
@@ -351,7 +404,7 @@ static int precond_vin(const Ctx& c, void** z) {
         }
         void* out = nullptr;
         graph_rec() = &rec;
-        const int st = vcycle<R>(c, 0, S->vin, &out);
+        const int st = vcycle<R>(c, 0, S->vin, &out, vin_y0(c));
         graph_rec() = nullptr;
         hipGraphExec_t ex = nullptr;
         if (st || rec.err != hipSuccess || hipGraphInstantiate(&ex, rec.graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -409,6 +462,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
     const size_t eb = 2 * sizeof(R);
     int st;
     if ((st = fill_zero(x, vbytes, c.s))) return st;
+    if ((st = ensure_dinv<R>(c))) return st;
     std::vector<double> bn;
     if ((st = norms<R>(rhs, N, nrhs, S->d_partial, S->max_blocks, S->d_nrm, c.s))) return st;
     if ((st = read_host(&bn, S->d_nrm, nrhs, c.s))) return st;
@@ -439,7 +493,9 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
         }
         first = false;
         const bool g = use_vgraph(c);
-        if ((st = scale_by_norm<R, R>(r, S->V, N, nrhs, S->d_beta, 0, c.s, g ? S->vin : nullptr))) return st;
+        void* y0 = g ? vin_y0(c) : nullptr;
+        const void* dv0 = y0 ? S->Dv[0] : nullptr;
+        if ((st = scale_by_norm<R, R>(r, S->V, N, nrhs, S->d_beta, 0, c.s, g ? S->vin : nullptr, dv0, y0))) return st;
         if ((st = givens_init(S->d_g, m, nrhs, S->d_beta, c.s))) return st;
         int k = 0;
         bool cyc_conv = false;
@@ -466,7 +522,9 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
                                     S->d_nrm, c.s, g0, S->d_n1)))
                 return st;
             void* vj1 = static_cast<char*>(S->V) + static_cast<size_t>(j + 1) * vstride * eb;
-            if ((st = scale_by_norm<R, R>(S->w, vj1, N, nrhs, S->d_nrm, 0, c.s, g && j + 1 < m ? S->vin : nullptr)))
+            const bool feed = g && j + 1 < m;   // v_{j+1} is the next V-cycle's input
+            if ((st = scale_by_norm<R, R>(S->w, vj1, N, nrhs, S->d_nrm, 0, c.s, feed ? S->vin : nullptr,
+                                          feed ? dv0 : nullptr, feed ? y0 : nullptr)))
                 return st;
             if ((st = givens_step(j, m, nrhs, S->d_hcol, ldh, S->d_nrm, S->d_H, S->d_cs, S->d_sn, S->d_g, S->d_est, c.s)))
                 return st;
@@ -500,7 +558,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
         if ((st = upper_solve(k, m, nrhs, S->d_H, S->d_g, S->d_y, ldh, c.s))) return st;
         void* z = nullptr;
         if (g) {
-            if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->vin, N, nrhs, 0, c.s))) return st;
+            if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->vin, N, nrhs, 0, c.s, dv0, y0))) return st;
             if ((st = precond_vin<R>(c, &z))) return st;
         } else {
             if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->tmp, N, nrhs, 0, c.s))) return st;
