@@ -139,6 +139,7 @@ struct GridOp {
     int n_g = 0;
     int idx_lo = 0, idx_hi = 0;                // range of table indices in use
     int fixed = 0;                             // entry 0 on every row
+    void* d_setup = nullptr;                   // one allocation holding the entry and axis arrays below
     EntryCoef<float>* d_entry_f = nullptr;     // [n_g]
     EntryCoef<double>* d_entry_d = nullptr;
     EntryCoef<float>* d_row_f = nullptr;       // GAm: per-row averaged entries [N]

@@ -111,14 +111,9 @@ void make_tiling(int nx, int ny, const int plo[2], const int phi[2], Tiling* t, 
 void grid_free(GridOp* g) {
     hipFree(g->d_c);
     hipFree(g->d_idx);
-    hipFree(g->d_entry_f);
-    hipFree(g->d_entry_d);
+    hipFree(g->d_setup);   // entry and axis arrays
     hipFree(g->d_row_f);
     hipFree(g->d_row_d);
-    for (int a = 0; a < 3; ++a) {
-        hipFree(g->d_ax_f[a]);
-        hipFree(g->d_ax_d[a]);
-    }
     *g = GridOp{};
 }
 
@@ -144,14 +139,6 @@ static EntryCoef<R> entry_from_w7(const double* w) {
     return e;
 }
 
-template <typename T>
-static int upload(T** dptr, const T* host, size_t n, size_t* bytes) {
-    if (hipMalloc(reinterpret_cast<void**>(dptr), n * sizeof(T)) != hipSuccess) return HELM27_ENOMEM;
-    *bytes += n * sizeof(T);
-    H27_CHECK_HIP(hipMemcpy(*dptr, host, n * sizeof(T), hipMemcpyHostToDevice));
-    return HELM27_OK;
-}
-
 // The same binary64 formula as the device index selection.
 int host_index(float c, double fh, double gmin, double dg, int n_g) {
     const double G = static_cast<double>(c) / fh;
@@ -167,15 +154,25 @@ int host_index(float c, double fh, double gmin, double dg, int n_g) {
 int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
     g->n_g = n_g;
     g->fixed = fixed;
+    // the table entries (FP32, FP64) and the three axes' PML nodes (FP64,
+    // FP32) go to the device in one allocation and one copy, each array at a
+    // 256-byte aligned offset
+    std::vector<unsigned char> host;
+    auto put = [&host](const void* src, size_t bytes) {
+        const size_t off = (host.size() + 255) & ~static_cast<size_t>(255);
+        host.resize(off + bytes);
+        std::memcpy(host.data() + off, src, bytes);
+        return off;
+    };
     std::vector<EntryCoef<float>> ef(n_g);
     std::vector<EntryCoef<double>> ed(n_g);
     for (int i = 0; i < n_g; ++i) {
         ef[i] = entry_from_w7<float>(w7 + 7 * i);
         ed[i] = entry_from_w7<double>(w7 + 7 * i);
     }
-    int st;
-    if ((st = upload(&g->d_entry_f, ef.data(), ef.size(), &g->bytes))) return st;
-    if ((st = upload(&g->d_entry_d, ed.data(), ed.size(), &g->bytes))) return st;
+    const size_t o_ef = put(ef.data(), ef.size() * sizeof(ef[0]));
+    const size_t o_ed = put(ed.data(), ed.size() * sizeof(ed[0]));
+    size_t o_axd[3], o_axf[3];
     const int dims[3] = {g->nx, g->ny, g->nz};
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
@@ -190,9 +187,22 @@ int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
                                     static_cast<float>(s.um_re), static_cast<float>(s.um_im),
                                     static_cast<float>(s.up_re), static_cast<float>(s.up_im), s.plain, 0};
         }
-        if ((st = upload(&g->d_ax_d[a], nd.data(), nd.size(), &g->bytes))) return st;
-        if ((st = upload(&g->d_ax_f[a], nf.data(), nf.size(), &g->bytes))) return st;
+        o_axd[a] = put(nd.data(), nd.size() * sizeof(nd[0]));
+        o_axf[a] = put(nf.data(), nf.size() * sizeof(nf[0]));
         plain_range(nd, &lo[a], &hi[a]);
+    }
+    if (hipMalloc(&g->d_setup, host.size()) != hipSuccess) {
+        g->d_setup = nullptr;
+        return HELM27_ENOMEM;
+    }
+    g->bytes += host.size();
+    H27_CHECK_HIP(hipMemcpy(g->d_setup, host.data(), host.size(), hipMemcpyHostToDevice));
+    unsigned char* base = static_cast<unsigned char*>(g->d_setup);
+    g->d_entry_f = reinterpret_cast<EntryCoef<float>*>(base + o_ef);
+    g->d_entry_d = reinterpret_cast<EntryCoef<double>*>(base + o_ed);
+    for (int a = 0; a < 3; ++a) {
+        g->d_ax_d[a] = reinterpret_cast<AxisNode<double>*>(base + o_axd[a]);
+        g->d_ax_f[a] = reinterpret_cast<AxisNode<float>*>(base + o_axf[a]);
     }
     make_tiling(g->nx, g->ny, lo, hi, &g->tiling, 0, g->nz);
     return HELM27_OK;

@@ -47,6 +47,9 @@ struct SolverState {
     bool dv_ok = false;
     double dv_key[3] = {0, 0, 0};
     void* vy = nullptr;              // dinv * vin, the V-cycle graph's first iterate
+    void* arena = nullptr;           // the workspace's one device allocation (in bufs)
+    size_t arena_size = 0, arena_used = 0;
+    bool arena_plan = false;
     double2* r64 = nullptr;
     double* d_partial = nullptr;
     int max_blocks = 1024;
@@ -95,6 +98,8 @@ static void free_workspace(SolverState* S) {
     S->Dv.clear();
     S->dv_ok = false;
     S->vy = nullptr;
+    S->arena = nullptr;
+    S->arena_size = S->arena_used = 0;
     for (void* p : S->bufs) hipFree(p);
     S->bufs.clear();
     S->X.clear();
@@ -111,12 +116,23 @@ static void free_hierarchy(SolverState* S) {
     S->levels = 0;
 }
 
+// Workspace buffers are carved from one device allocation (one hipMalloc
+// and one hipFree per workspace instead of one per buffer): the layout runs
+// once to size the arena (plan) and once to hand out 256-byte aligned
+// sub-ranges.
 static int alloc(SolverState* S, void** p, size_t bytes) {
-    if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+    bytes = ((bytes ? bytes : 16) + 255) & ~static_cast<size_t>(255);
+    if (S->arena_plan) {
+        *p = nullptr;
+        S->arena_size += bytes;
+        return HELM27_OK;
+    }
+    if (S->arena_used + bytes > S->arena_size) {
         *p = nullptr;
         return HELM27_ENOMEM;
     }
-    S->bufs.push_back(*p);
+    *p = static_cast<char*>(S->arena) + S->arena_used;
+    S->arena_used += bytes;
     return HELM27_OK;
 }
 
@@ -194,11 +210,43 @@ static const GridOp& level_grid(const helm27_op* op, const SolverState* S, int l
     return l == 0 ? op->g : S->coarse[l - 1];
 }
 
+static int workspace_layout(helm27_op* op, SolverState* S, int nrhs, int m, int prec);
+
 static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int prec) {
     if (S->nrhs == nrhs && S->m == m && S->prec == prec && S->N == op->g.N &&
         static_cast<int>(S->X.size()) == S->levels)
         return HELM27_OK;
     free_workspace(S);
+    S->arena_plan = true;
+    S->arena_size = 0;
+    int st = workspace_layout(op, S, nrhs, m, prec);
+    S->arena_plan = false;
+    if (st) return st;
+    if (hipMalloc(&S->arena, S->arena_size) != hipSuccess) {
+        S->arena = nullptr;
+        S->arena_size = 0;
+        return HELM27_ENOMEM;
+    }
+    S->bufs.push_back(S->arena);
+    S->arena_used = 0;
+    if ((st = workspace_layout(op, S, nrhs, m, prec))) return st;
+    if (hipHostMalloc(reinterpret_cast<void**>(&S->h_est), 2 * static_cast<size_t>(nrhs) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        S->h_est = nullptr;
+        return HELM27_ENOMEM;
+    }
+    for (int k = 0; k < 2; ++k)
+        if (!S->est_ev[k]) H27_CHECK_HIP(hipEventCreateWithFlags(&S->est_ev[k], hipEventDisableTiming));
+    S->nrhs = nrhs;
+    S->m = m;
+    S->prec = prec;
+    S->N = op->g.N;
+    return HELM27_OK;
+}
+
+// The workspace layout: every device buffer of the solver for nrhs
+// right-hand sides, restart m and inner precision prec (bytes per real).
+static int workspace_layout(helm27_op* op, SolverState* S, int nrhs, int m, int prec) {
     const int64_t N = op->g.N;
     const size_t vb = static_cast<size_t>(2 * prec);   // complex element bytes
     const size_t vec = static_cast<size_t>(N) * nrhs * vb;
@@ -255,13 +303,6 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->d_bn = dd[4];
     S->d_n0 = dd[5];
     S->d_n1 = dd[6];
-    if (hipHostMalloc(reinterpret_cast<void**>(&S->h_est), 2 * static_cast<size_t>(nrhs) * sizeof(double),
-                      hipHostMallocDefault) != hipSuccess) {
-        S->h_est = nullptr;
-        return HELM27_ENOMEM;
-    }
-    for (int k = 0; k < 2; ++k)
-        if (!S->est_ev[k]) H27_CHECK_HIP(hipEventCreateWithFlags(&S->est_ev[k], hipEventDisableTiming));
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1) * m * sizeof(double2)))) return st;
     S->d_H = static_cast<double2*>(p);
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * m * sizeof(double)))) return st;
@@ -270,10 +311,6 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->d_sn = static_cast<double2*>(p);
     if ((st = alloc(S, &p, static_cast<size_t>(nrhs) * (m + 1) * sizeof(double2)))) return st;
     S->d_g = static_cast<double2*>(p);
-    S->nrhs = nrhs;
-    S->m = m;
-    S->prec = prec;
-    S->N = N;
     return HELM27_OK;
 }
 
