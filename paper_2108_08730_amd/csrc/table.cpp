@@ -65,11 +65,13 @@ namespace {
 // entry (j, j + k), k < bw.
 class BandedLS {
   public:
+    static constexpr int kMaxBw = 16;   // 5 weights x (difference order + 1) <= 15
     BandedLS(int n, int bw) : n_(n), bw_(bw), R_(static_cast<size_t>(n) * bw, 0.0), qtb_(n, 0.0), filled_(n, 0) {}
 
     // Add the row (vals[0..bw) at columns c0..c0+bw) with right-hand side rhs.
     void add_row(int c0, const double* vals, double rhs) {
-        std::vector<double> r(vals, vals + bw_);
+        double r[kMaxBw];
+        for (int k = 0; k < bw_; ++k) r[k] = vals[k];
         double b = rhs;
         int off = c0;  // column of r[0]
         for (int j = off; j < n_; ++j) {
@@ -200,6 +202,39 @@ bool minnorm_ls(std::vector<double> A, const std::vector<double>& b, int m, int 
 
 using namespace h27;
 
+// In-place Householder QR of a dense m x 5 block (row-major A) applied to b
+// as well: on return rows 0..min(m,5)-1 of A hold the upper triangle R and
+// b[0..) the first entries of Q^T b.  Returns the number of triangle rows.
+static int householder_rows(double* A, double* b, int m) {
+    const int n = 5, nk = m < n ? m : n;
+    for (int k = 0; k < nk; ++k) {
+        double nrm2 = 0.0;
+        for (int i = k; i < m; ++i) nrm2 += A[5 * i + k] * A[5 * i + k];
+        const double nrm = std::sqrt(nrm2);
+        if (nrm == 0.0) continue;
+        const double akk = A[5 * k + k];
+        const double alpha = akk > 0 ? -nrm : nrm;   // the new diagonal, no cancellation
+        // v = x - alpha e_k, stored over column k below the diagonal; v^T v = 2 nrm (nrm + |akk|)
+        const double v0 = akk - alpha;
+        const double vtv = 2.0 * nrm * (nrm + std::fabs(akk));
+        for (int j = k + 1; j < n; ++j) {
+            double d = v0 * A[5 * k + j];
+            for (int i = k + 1; i < m; ++i) d += A[5 * i + k] * A[5 * i + j];
+            const double f = 2.0 * d / vtv;
+            A[5 * k + j] -= f * v0;
+            for (int i = k + 1; i < m; ++i) A[5 * i + j] -= f * A[5 * i + k];
+        }
+        double d = v0 * b[k];
+        for (int i = k + 1; i < m; ++i) d += A[5 * i + k] * b[i];
+        const double f = 2.0 * d / vtv;
+        b[k] -= f * v0;
+        for (int i = k + 1; i < m; ++i) b[i] -= f * A[5 * i + k];
+        A[5 * k + k] = alpha;
+        for (int i = k + 1; i < m; ++i) A[5 * i + k] = 0.0;
+    }
+    return nk;
+}
+
 extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, double dg, double lambda,
                                   const helm27_table_opts* opts, helm27_table** out) {
     (void)ctx;
@@ -250,16 +285,24 @@ extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, d
     BandedLS ls(n, bw);
     std::vector<double> row(bw);
     const double sl = std::sqrt(lambda);
+    const int m_ang = n_ang * n_ang;
+    std::vector<double> Ab(static_cast<size_t>(m_ang) * 5), bb(m_ang);
     for (int i = 0; i < n_g; ++i) {
         const double G = g_min + i * dg;
+        // the block's dispersion rows touch only its own five columns: reduce
+        // them to a 5 x 5 triangle (and Q^T b) by Householder reflections
+        // first; an orthogonal transformation leaves the least-squares
+        // solution unchanged, and the banded factorisation then absorbs 5 rows
+        // instead of n_ang^2
+        int r = 0;
         for (int jp = 0; jp < n_ang; ++jp)
-            for (int jt = 0; jt < n_ang; ++jt) {
-                double H[5], g;
-                dispersion_rows(G, ang[jt], ang[jp], H, &g);
-                std::fill(row.begin(), row.end(), 0.0);
-                for (int l = 0; l < 5; ++l) row[l] = H[l];
-                ls.add_row(5 * i, row.data(), g);
-            }
+            for (int jt = 0; jt < n_ang; ++jt, ++r) dispersion_rows(G, ang[jt], ang[jp], &Ab[5 * r], &bb[r]);
+        const int nk = householder_rows(Ab.data(), bb.data(), m_ang);
+        for (int k = 0; k < nk; ++k) {
+            std::fill(row.begin(), row.end(), 0.0);
+            for (int l = k; l < 5; ++l) row[l - k] = Ab[5 * k + l];
+            ls.add_row(5 * i + k, row.data(), bb[k]);
+        }
         // smoothing rows whose first column lies in block i
         if (lambda > 0 && i + order < n_g) {
             for (int l = 0; l < 5; ++l) {
