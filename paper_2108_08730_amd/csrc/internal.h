@@ -196,8 +196,10 @@ int grid_setup(GridOp* g, const double* w7, int n_g, int fixed);
 int host_index(float c, double fh, double gmin, double dg, int n_g);
 
 // kernels (kernels_*.hip): host-side launchers
+// d_counts: 4 entries, initialised by the caller to {0, 0, bits of +inf, 0}:
+// clamped points, invalid velocities, min / max bit pattern of the valid ones
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
-                        int n_g, unsigned long long* d_nclamp, hipStream_t s);
+                        int n_g, unsigned long long* d_counts, hipStream_t s);
 // y = A u (MODE_APPLY), y = b - A u (MODE_RESID), y = u + omega_j D^-1 (b - A u)
 // (MODE_JACOBI) or y = omega_j D^-1 b (MODE_JACOBI0, u not read; wavefront
 // kernel only) with A's mass scaled by (shift_re + i shift_im); (1, 0) is the

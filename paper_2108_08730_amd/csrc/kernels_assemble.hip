@@ -9,17 +9,27 @@ namespace h27 {
 
 // idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, n_g - 1)   (paper Sec. 3.1:
 // every row picks the table entry of its local G = c/(f h); nearest entry,
-// ties upwards).  Counts clamped points and invalid velocities.
+// ties upwards).  counts[0] += clamped points, counts[1] += invalid velocities,
+// counts[2] / counts[3] = min / max bit pattern of the valid velocities (the
+// bits of positive floats order like the values; the caller initialises them
+// to +inf and 0).
 __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __restrict__ idx, int64_t N,
                                     double fh, double gmin, double dg, int n_g,
                                     unsigned long long* __restrict__ counts) {
     __shared__ unsigned long long red[2][kBlock / 64];
+    __shared__ float rmm[2][kBlock / 64];
     unsigned long long ncl = 0, nbad = 0;
+    float vmin = __builtin_inff(), vmax = 0.0f;
     const double top = static_cast<double>(n_g - 1);
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const float cv = c[i];
-        if (!(cv > 0.0f) || !isfinite(cv)) ++nbad;
+        if (!(cv > 0.0f) || !isfinite(cv)) {
+            ++nbad;
+        } else {
+            vmin = fminf(vmin, cv);
+            vmax = fmaxf(vmax, cv);
+        }
         const double G = static_cast<double>(cv) / fh;
         const double t = (G - gmin) / dg;
         const double raw = floor(t + 0.5);
@@ -39,21 +49,30 @@ __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __res
     for (int off = 32; off > 0; off >>= 1) {
         ncl += __shfl_down(ncl, off, 64);
         nbad += __shfl_down(nbad, off, 64);
+        vmin = fminf(vmin, __shfl_down(vmin, off, 64));
+        vmax = fmaxf(vmax, __shfl_down(vmax, off, 64));
     }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (l == 0) {
         red[0][w] = ncl;
         red[1][w] = nbad;
+        rmm[0][w] = vmin;
+        rmm[1][w] = vmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long a = 0, b = 0;
+        float mn = __builtin_inff(), mx = 0.0f;
         for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) {
             a += red[0][k];
             b += red[1][k];
+            mn = fminf(mn, rmm[0][k]);
+            mx = fmaxf(mx, rmm[1][k]);
         }
         if (a) atomicAdd(counts, a);
         if (b) atomicAdd(counts + 1, b);
+        atomicMin(counts + 2, static_cast<unsigned long long>(__float_as_uint(mn)));
+        atomicMax(counts + 3, static_cast<unsigned long long>(__float_as_uint(mx)));
     }
 }
 

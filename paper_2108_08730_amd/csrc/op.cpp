@@ -253,15 +253,6 @@ extern "C" const char* helm27_strerror(int st) {
     }
 }
 
-static bool is_device_ptr(const void* p) {
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return attr.type == hipMemoryTypeDevice;
-}
-
 namespace h27 {
 // Assembly on a given stream (the serving workers use their own streams).
 int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, int ny, int nz, double h,
@@ -280,21 +271,6 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     H27_CHECK_HIP(hipSetDevice(ctx->device));
 
     const int64_t N = static_cast<int64_t>(nx) * ny * nz;
-    std::vector<float> hc(N);
-    const bool dev = is_device_ptr(vel);
-    if (dev) {
-        H27_CHECK_HIP(hipMemcpyAsync(hc.data(), vel, N * sizeof(float), hipMemcpyDeviceToHost, stream));
-        H27_CHECK_HIP(hipStreamSynchronize(stream));
-    } else {
-        std::memcpy(hc.data(), vel, N * sizeof(float));
-    }
-    float cmin = std::numeric_limits<float>::infinity(), cmax = 0.0f;
-    for (int64_t i = 0; i < N; ++i) {
-        const float v = hc[i];
-        if (!(v > 0.0f) || !std::isfinite(v)) return HELM27_EINVAL;
-        cmin = std::min(cmin, v);
-        cmax = std::max(cmax, v);
-    }
     helm27_op* op = new (std::nothrow) helm27_op;
     if (!op) return HELM27_ENOMEM;
     op->ctx = ctx;
@@ -309,17 +285,12 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
         g.pml_hi[a] = (dims[a] - 1 - P.npml[a]) * h;
     }
     g.R = P.R;
-    g.c_ref = P.c_ref > 0 ? P.c_ref : static_cast<double>(cmax);
     op->freq = freq;
     op->flags = flags;
     op->w7 = t->w7;
     op->table_gmin = t->g_min;
     op->table_dg = t->dg;
     const double fh = freq * h;
-    op->cmin = cmin;
-    op->cmax = cmax;
-    op->g_min_model = static_cast<double>(cmin) / fh;
-    op->g_max_model = static_cast<double>(cmax) / fh;
 
     int st = HELM27_OK;
     unsigned long long* d_cnt = nullptr;
@@ -328,16 +299,19 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
         helm27_op_destroy(op);
         return s;
     };
+    // the velocity goes to the device as given (host or device pointer); the
+    // index kernel validates it and finds its range on the device
     if (hipMalloc(&g.d_c, N * sizeof(float)) != hipSuccess) return fail(HELM27_ENOMEM);
     if (hipMalloc(&g.d_idx, N * sizeof(uint16_t)) != hipSuccess) return fail(HELM27_ENOMEM);
     g.bytes += N * (sizeof(float) + sizeof(uint16_t));
-    if (hipMemcpyAsync(g.d_c, hc.data(), N * sizeof(float), hipMemcpyHostToDevice, stream) != hipSuccess)
+    if (hipMemcpyAsync(g.d_c, vel, N * sizeof(float), hipMemcpyDefault, stream) != hipSuccess)
         return fail(HELM27_EDEVICE);
-    if (hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)) != hipSuccess) return fail(HELM27_ENOMEM);
-    if (hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess) return fail(HELM27_EDEVICE);
+    unsigned long long cnt[4] = {0, 0, 0x7F800000ull, 0};   // clamped, invalid, min bits (+inf), max bits
+    if (hipMalloc(&d_cnt, sizeof(cnt)) != hipSuccess) return fail(HELM27_ENOMEM);
+    if (hipMemcpyAsync(d_cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return fail(HELM27_EDEVICE);
     if ((st = launch_select_index(g.d_c, g.d_idx, N, fh, t->g_min, t->dg, t->n_g, d_cnt, stream)))
         return fail(st);
-    unsigned long long cnt[2] = {0, 0};
     if (hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
         return fail(HELM27_EDEVICE);
@@ -345,6 +319,17 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     d_cnt = nullptr;
     if (cnt[1] != 0) return fail(HELM27_EINVAL);
     op->n_clamped = static_cast<int64_t>(cnt[0]);
+    float cmin, cmax;
+    {
+        const unsigned lo = static_cast<unsigned>(cnt[2]), hi = static_cast<unsigned>(cnt[3]);
+        std::memcpy(&cmin, &lo, sizeof(float));
+        std::memcpy(&cmax, &hi, sizeof(float));
+    }
+    op->cmin = cmin;
+    op->cmax = cmax;
+    op->g_min_model = static_cast<double>(cmin) / fh;
+    op->g_max_model = static_cast<double>(cmax) / fh;
+    g.c_ref = P.c_ref > 0 ? P.c_ref : static_cast<double>(cmax);
 
     if ((st = grid_setup(&g, t->w7.data(), t->n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
     // large grids (HBM-bound): box rows shared across the block, one row per

@@ -158,8 +158,8 @@ static int auto_levels(const GridOp& g) {
 static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_t s) {
     free_hierarchy(S);
     const GridOp* prev = &op->g;
-    unsigned long long* d_cnt = nullptr;
-    if (hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)) != hipSuccess) return HELM27_ENOMEM;
+    unsigned long long* d_cnt = nullptr;   // select-index counters (4 entries; only the layout matters here)
+    if (hipMalloc(&d_cnt, 4 * sizeof(unsigned long long)) != hipSuccess) return HELM27_ENOMEM;
     int st = HELM27_OK;
     S->coarse.reserve(levels > 1 ? levels - 1 : 0);
     for (int l = 1; l < levels; ++l) {
@@ -189,7 +189,7 @@ static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_
         c.bytes += c.N * (sizeof(float) + sizeof(uint16_t));
         if ((st = inject_velocity(prev->d_c, prev->nx, prev->ny, c.d_c, cx, cy, cz, s))) break;
         const double fh = op->freq * c.h;
-        if (hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), s) != hipSuccess) {
+        if (hipMemsetAsync(d_cnt, 0, 4 * sizeof(unsigned long long), s) != hipSuccess) {
             st = HELM27_EDEVICE;
             break;
         }
