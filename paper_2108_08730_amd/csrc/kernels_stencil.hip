@@ -450,6 +450,25 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         const int RY = g.plain_ry[sizeof(R) == 8 ? 1 : 0];
         const int RQ = frame_rows<R>();
         w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
+        Rect fr[4] = {t.frame[0], t.frame[1], t.frame[2], t.frame[3]};
+        // The box is cut into 62-column tiles; a last partial tile costs as
+        // much as a full one.  When the left / right strips (14-column lane
+        // groups) have room for those leftover columns in the groups they
+        // already use, they take them (the general formula holds for
+        // unstretched columns too) and the box becomes whole tiles
+        // (400 wide with an 8-node PML: 6 tiles instead of 6 + 12 columns).
+        if (w.pw > kWaveCols && fr[2].w > 0 && fr[3].w > 0) {
+            const int left = w.pw % kWaveCols;
+            const int capl = 14 * ((fr[2].w + 13) / 14) - fr[2].w, capr = 14 * ((fr[3].w + 13) / 14) - fr[3].w;
+            if (left > 0 && left <= capl + capr) {
+                const int a = std::min(left, capl);
+                w.px0 += a;
+                w.pw -= left;
+                fr[2].w += a;
+                fr[3].x0 = w.px0 + w.pw;
+                fr[3].w = g.nx - fr[3].x0;
+            }
+        }
         // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
         w.blk = g.kernel_variant == 2 ? 1 : 0;
         const int rows_per_tile = w.blk ? 4 * RY : RY;
@@ -458,7 +477,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         w.n_plain = w.ntx * w.nty;
         int accf = 0;
         for (int k = 0; k < 4; ++k) {
-            const Rect& r = t.frame[k];
+            const Rect& r = fr[k];
             w.fx0[k] = r.x0; w.fy0[k] = r.y0; w.fw[k] = r.w; w.fh[k] = r.h;
             // lanes always run along x: whole-wave groups (62 columns) for strips
             // spanning x (bottom / top, or the whole grid), 16-lane groups (14

@@ -65,6 +65,10 @@ CASES = [
     ((66, 10, 9), (0, 0, 0), "random", 6.0, 25.0),
     ((20, 5, 6), (2, 2, 2), "gradient", 5.0, 25.0),
     ((131, 70, 11), (8, 8, 3), "random", 8.0, 25.0),
+    # box of 2 x 62 + 12 columns: both 8-column x strips take 6 of the
+    # leftover columns into their 14-column lane groups (as 77 x 37 x 19 does
+    # on one side)
+    ((152, 12, 10), (8, 3, 2), "random", 6.0, 25.0),
 ]
 
 
