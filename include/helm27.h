@@ -188,9 +188,15 @@ int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int
  * chunk in {automatic, 8, 16, 32, 64} (helm27_set_zchunk) and kernel
  * variants 0 and 2 (helm27_set_kernel_variant) on the operator with nrhs
  * zero right-hand sides (device scratch allocated and freed inside), keeps
- * the fastest and returns its rows in *best_rows (may be NULL).  Operators
- * of 2^23 points or more start at variant 2, 1 row, 16-plane chunks; smaller
- * ones at variant 0, 2 rows (FP32) / 1 row (FP64), automatic chunks.  Every choice computes the same sums per output; the compiler may
+ * the fastest and returns its rows in *best_rows (may be NULL).  Until one
+ * of helm27_set_tuning, helm27_tune, helm27_set_kernel_variant or
+ * helm27_set_zchunk is called, every launch chooses its own shape from its
+ * work size: 2^23 or more point-RHS pairs take variant 2 with 16-plane
+ * chunks and 1 row (one RHS) or 2 rows (several, FP32), smaller launches
+ * variant 0 with 2 rows (FP32) / 1 row (FP64) and automatic chunks.  After
+ * such a call the operator keeps its explicit settings (operators of 2^23
+ * points or more start from variant 2, 1 row, 16-plane chunks; smaller ones
+ * from variant 0, 2 / 1 rows, automatic chunks).  Every choice computes the same sums per output; the compiler may
  * fuse multiply-adds differently per choice, so results agree to rounding
  * (not bit for bit) across choices, and bit for bit across runs of one
  * choice.
@@ -201,12 +207,14 @@ int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows
  * PML frame in one launch (default); 1 = LDS-tiled blocks (one block per
  * 64 x 8 or 16 x 16 column tile); 2 = as 0, with the box tiles in groups of
  * four stacked tiles per block that share their plane rows through LDS.
- * All compute the same operator.  Errors: EINVAL. */
+ * All compute the same operator.  Switches off the per-launch choice (see
+ * helm27_tune).  Errors: EINVAL. */
 int helm27_set_kernel_variant(helm27_op* op, int variant);
 /* z planes per work item of the wavefront kernel (each item marches its
  * chunk of planes; two extra planes are read per chunk): 0 = automatic
- * (about 4096 work items, 2..32 planes each), else 2..4096.  Results agree
- * to rounding across choices.  Errors: EINVAL. */
+ * (about 4096 work items, 2..16 planes each), else 2..4096.  Results agree
+ * to rounding across choices.  Switches off the per-launch choice (see
+ * helm27_tune).  Errors: EINVAL. */
 int helm27_set_zchunk(helm27_op* op, int zchunk);
 
 /* ---- (c) solve ------------------------------------------------------------ */

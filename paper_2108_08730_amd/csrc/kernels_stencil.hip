@@ -447,7 +447,25 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     if (use_wave) {
         WaveArgs<R> w{};
         w.g = a.g;
-        const int RY = g.plain_ry[sizeof(R) == 8 ? 1 : 0];
+        constexpr bool fp64 = sizeof(R) == 8;
+        int RY = g.plain_ry[fp64 ? 1 : 0], variant = g.kernel_variant, zc_set = g.wave_zchunk;
+        if (g.auto_tile) {
+            // HBM-bound launches (2^23 or more point-RHS pairs): box rows shared
+            // across the block (variant 2) in 16-plane chunks, one row per
+            // wavefront for one RHS and two for several (400x400x200: 187-198 us
+            // against 203-213 us for variant 0; 201x201x101 x 16 RHS: 390 us
+            // against 431 us); smaller launches keep the latency-friendlier
+            // per-wavefront tiles with automatic chunks
+            const bool big = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23);
+            RY = fp64 ? g.plain_ry[1] : (big && nrhs >= 2 ? 2 : (big ? 1 : 2));
+            variant = 0;
+            zc_set = 0;
+            const size_t ring = static_cast<size_t>(2 * (4 * RY + 2) * 64) * sizeof(typename V2<R>::T);
+            if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= 64 * 1024) {
+                variant = 2;
+                zc_set = 16;
+            }
+        }
         const int RQ = frame_rows<R>();
         w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
         Rect fr[4] = {t.frame[0], t.frame[1], t.frame[2], t.frame[3]};
@@ -470,7 +488,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
             }
         }
         // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
-        w.blk = g.kernel_variant == 2 ? 1 : 0;
+        w.blk = variant == 2 ? 1 : 0;
         const int rows_per_tile = w.blk ? 4 * RY : RY;
         w.ntx = w.pw > 0 ? (w.pw + kWaveCols - 1) / kWaveCols : 0;
         w.nty = w.ph > 0 ? (w.ph + rows_per_tile - 1) / rows_per_tile : 0;
@@ -500,8 +518,8 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         const int64_t target = w.blk ? 1024 : 4096;
         int64_t nzc = (target + tiles - 1) / tiles;
         int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
-        zc = std::max(2, std::min(32, zc));
-        if (g.wave_zchunk > 0) zc = g.wave_zchunk;
+        zc = std::max(2, std::min(16, zc));
+        if (zc_set > 0) zc = zc_set;
         w.zchunk = std::min(zc, g.nz);
         w.nzc = (g.nz + w.zchunk - 1) / w.zchunk;
         w.nrhs = nrhs;

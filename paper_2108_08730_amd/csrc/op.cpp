@@ -332,10 +332,8 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     g.c_ref = P.c_ref > 0 ? P.c_ref : static_cast<double>(cmax);
 
     if ((st = grid_setup(&g, t->w7.data(), t->n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
-    // large grids (HBM-bound): box rows shared across the block, one row per
-    // wavefront, 16-plane chunks (measured on 400x400x200: 187 us against
-    // 203 us for the per-wavefront tiles); smaller grids keep the latency-
-    // friendlier per-wavefront tiles
+    // the explicit tile shape a large grid starts from when one of its
+    // settings is changed (launches choose per call while auto_tile is set)
     if (g.N >= (int64_t(1) << 23)) {
         g.kernel_variant = 2;
         g.plain_ry[0] = 1;
@@ -471,6 +469,7 @@ extern "C" int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave) {
     if (dtype == HELM27_C64) op->g.plain_ry[0] = rows_per_wave;
     else if (dtype == HELM27_C128) op->g.plain_ry[1] = rows_per_wave;
     else return HELM27_EINVAL;
+    op->g.auto_tile = false;
     return HELM27_OK;
 }
 
@@ -493,6 +492,7 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
     const int slot = dtype == HELM27_C64 ? 0 : 1;
     float best = 1e30f;
     int best_ry = op->g.plain_ry[slot], best_zc = op->g.wave_zchunk, best_var = op->g.kernel_variant;
+    op->g.auto_tile = false;   // the tuner measures explicit shapes and keeps the fastest
     const int zchunks[5] = {0, 8, 16, 32, 64};   // 0 = automatic
     const int variants[2] = {0, 2};
     for (int vi = 0; vi < 2 && st == HELM27_OK; ++vi)
@@ -535,11 +535,13 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
 extern "C" int helm27_set_kernel_variant(helm27_op* op, int variant) {
     if (!op || variant < 0 || variant > 2) return HELM27_EINVAL;
     op->g.kernel_variant = variant;
+    op->g.auto_tile = false;
     return HELM27_OK;
 }
 
 extern "C" int helm27_set_zchunk(helm27_op* op, int zchunk) {
     if (!op || zchunk < 0 || zchunk == 1 || zchunk > 4096) return HELM27_EINVAL;
     op->g.wave_zchunk = zchunk;
+    op->g.auto_tile = false;
     return HELM27_OK;
 }

@@ -80,7 +80,7 @@ struct SolverState {
     hipGraphExec_t vgraph = nullptr;
     void* vgraph_out = nullptr;
     double gkey_d[3] = {0, 0, 0};
-    int gkey_i[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int gkey_i[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     bool graph_failed = false;
 };
 
@@ -427,11 +427,11 @@ static int precond_vin(const Ctx& c, void** z) {
     SolverState* S = c.S;
     const GridOp& G = c.op->g;
     const double kd[3] = {c.o->mg_shift_re, c.o->mg_shift, c.o->mg_omega};
-    const int ki[9] = {c.nrhs, static_cast<int>(sizeof(R)), c.o->mg_pre, c.o->mg_post, c.o->mg_coarse_sweeps,
-                       G.plain_ry[0], G.plain_ry[1], G.kernel_variant, G.wave_zchunk};
+    const int ki[10] = {c.nrhs, static_cast<int>(sizeof(R)), c.o->mg_pre, c.o->mg_post, c.o->mg_coarse_sweeps,
+                        G.plain_ry[0], G.plain_ry[1], G.kernel_variant, G.wave_zchunk, G.auto_tile ? 1 : 0};
     bool same = S->vgraph != nullptr;
     for (int k = 0; k < 3 && same; ++k) same = S->gkey_d[k] == kd[k];
-    for (int k = 0; k < 9 && same; ++k) same = S->gkey_i[k] == ki[k];
+    for (int k = 0; k < 10 && same; ++k) same = S->gkey_i[k] == ki[k];
     if (!same) {
         drop_graph(S);
         GraphRec rec;
@@ -455,7 +455,7 @@ static int precond_vin(const Ctx& c, void** z) {
         S->vgraph = ex;
         S->vgraph_out = out;
         for (int k = 0; k < 3; ++k) S->gkey_d[k] = kd[k];
-        for (int k = 0; k < 9; ++k) S->gkey_i[k] = ki[k];
+        for (int k = 0; k < 10; ++k) S->gkey_i[k] = ki[k];
     }
     H27_CHECK_HIP(hipGraphLaunch(S->vgraph, c.s));
     *z = S->vgraph_out;
