@@ -67,8 +67,14 @@ def apply_timing(op, torch, nrhs=1, reps=200, dtype=None, variant="recompute"):
     stream = torch.cuda.current_stream()
     u = torch.randn((nrhs, op.N), dtype=dtype, device="cuda")
     y = torch.empty_like(u)
-    for _ in range(5):
+    # warm-up: at least 5 launches and 50 ms (clocks and caches settle)
+    t0 = time.perf_counter()
+    k = 0
+    while k < 5 or time.perf_counter() - t0 < 0.05:
         op.apply(u, y, variant=variant, stream=stream)
+        k += 1
+        if k % 5 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
