@@ -71,8 +71,12 @@ __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __res
         }
         if (a) atomicAdd(counts, a);
         if (b) atomicAdd(counts + 1, b);
-        atomicMin(counts + 2, static_cast<unsigned long long>(__float_as_uint(mn)));
-        atomicMax(counts + 3, static_cast<unsigned long long>(__float_as_uint(mx)));
+        // min / max only change monotonically, so an earlier value read
+        // without the atomic safely rules out most updates (thousands of
+        // blocks contending for one address otherwise serialise)
+        const unsigned long long lo = __float_as_uint(mn), hi = __float_as_uint(mx);
+        if (lo < __hip_atomic_load(counts + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(counts + 2, lo);
+        if (hi > __hip_atomic_load(counts + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(counts + 3, hi);
     }
 }
 
