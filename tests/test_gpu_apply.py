@@ -175,6 +175,37 @@ def test_apply_full_size_gradient_sampled(ctx, table, oracle_table):
         assert _relerr(y32[r], y_ref[r]) <= 1e-5
 
 
+def test_apply_many_rhs_block_tiles_sampled(ctx, table, oracle_table):
+    """64^3 random field, 6-node PML, 32 right-hand sides in one launch
+    (2^23 point-RHS pairs: the launch takes the block-tile kernel with two
+    rows per wavefront and 16-plane chunks): FP64 and FP32 applies on sampled
+    rows of every right-hand side against the oracle, and each right-hand
+    side equal to its own single-RHS launch (per-wavefront tiles) to FP32
+    rounding."""
+    dims, npml, f, h = (64, 64, 64), 6, 8.0, 25.0
+    c = synth.random_field_model(dims, h, seed=31)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    N = int(np.prod(dims))
+    nrhs = 32
+    assert N * nrhs >= 2 ** 23
+    idx_o, _ = O.select_index(c, f, h, 3.0, 0.05, 341)
+    rows = np.unique(np.random.default_rng(4).integers(0, N, 400))
+    w = O.row_weights("GA", idx_o, oracle_table[2])
+    A = O.assemble_rows(c, f, h, npml, w[rows], rows)
+    u = synth.random_vectors(N, nrhs, seed=12)
+    y_ref = (A @ u.T).T
+    ud = torch.from_numpy(u).cuda()
+    y64 = op.apply(ud).cpu().numpy()
+    u32 = ud.to(torch.complex64)
+    y32 = op.apply(u32).cpu().numpy()
+    for r in range(nrhs):
+        assert _relerr(y64[r, rows], y_ref[r]) <= 1e-12
+        assert _relerr(y32[r, rows], y_ref[r]) <= 1e-5
+    for r in (0, 17, 31):
+        y1 = op.apply(u32[r:r + 1].contiguous()).cpu().numpy()[0]
+        assert _relerr(y32[r], y1) <= 1e-5
+
+
 def test_apply_large_random_field_sampled(ctx, table, oracle_table):
     """201 x 201 x 101 heterogeneous model, 8-node PML, f = 8 Hz, 4 right-hand
     sides: sampled rows against the oracle."""
