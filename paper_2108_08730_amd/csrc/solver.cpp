@@ -61,9 +61,12 @@ struct SolverState {
     double* d_beta = nullptr;
     double* d_est = nullptr;
     // residual estimates copied to pinned host memory each Arnoldi step, two
-    // slots [2][nrhs] so the host checks step j - 1 while step j runs
+    // slots [2][nrhs] so the host checks step j - 1 while step j runs, then
+    // one slot [nrhs] for the restart residual norms (checked after the
+    // cycle's first step is queued)
     double* h_est = nullptr;
     hipEvent_t est_ev[2] = {nullptr, nullptr};
+    hipEvent_t beta_ev = nullptr;
     double* d_rn = nullptr;
     double* d_bn = nullptr;
     double2* d_H = nullptr;
@@ -230,13 +233,14 @@ static int ensure_workspace(helm27_op* op, SolverState* S, int nrhs, int m, int 
     S->bufs.push_back(S->arena);
     S->arena_used = 0;
     if ((st = workspace_layout(op, S, nrhs, m, prec))) return st;
-    if (hipHostMalloc(reinterpret_cast<void**>(&S->h_est), 2 * static_cast<size_t>(nrhs) * sizeof(double),
+    if (hipHostMalloc(reinterpret_cast<void**>(&S->h_est), 3 * static_cast<size_t>(nrhs) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         S->h_est = nullptr;
         return HELM27_ENOMEM;
     }
     for (int k = 0; k < 2; ++k)
         if (!S->est_ev[k]) H27_CHECK_HIP(hipEventCreateWithFlags(&S->est_ev[k], hipEventDisableTiming));
+    if (!S->beta_ev) H27_CHECK_HIP(hipEventCreateWithFlags(&S->beta_ev, hipEventDisableTiming));
     S->nrhs = nrhs;
     S->m = m;
     S->prec = prec;
@@ -517,17 +521,14 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             r = S->w;
         }
         if ((st = norms<R>(r, N, nrhs, S->d_partial, S->max_blocks, S->d_beta, c.s))) return st;
-        std::vector<double> beta;
-        if ((st = read_host(&beta, S->d_beta, nrhs, c.s))) return st;
-        bool all = true;
-        for (int k = 0; k < nrhs; ++k) {
-            if (!std::isfinite(beta[k])) return HELM27_ENUMERIC;
-            if (beta[k] > thr[k] * bn[k]) all = false;
-        }
-        if (all) {
-            *conv = true;
-            break;
-        }
+        // the restart norms go to pinned memory; the host checks them once the
+        // cycle's first Arnoldi step is queued (no device idle for the round
+        // trip).  If they already meet the thresholds, that step is dropped
+        // and x stays as it is.
+        double* h_beta = S->h_est + 2 * nrhs;
+        H27_CHECK_HIP(hipMemcpyAsync(h_beta, S->d_beta, nrhs * sizeof(double), hipMemcpyDeviceToHost, c.s));
+        H27_CHECK_HIP(hipEventRecord(S->beta_ev, c.s));
+        bool beta_checked = false, beta_conv = false;
         first = false;
         const bool g = use_vgraph(c);
         void* y0 = g ? vin_y0(c) : nullptr;
@@ -576,6 +577,19 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             H27_CHECK_HIP(hipMemcpyAsync(S->h_est + (j & 1) * nrhs, S->d_est, nrhs * sizeof(double),
                                          hipMemcpyDeviceToHost, c.s));
             H27_CHECK_HIP(hipEventRecord(S->est_ev[j & 1], c.s));
+            if (!beta_checked) {
+                beta_checked = true;
+                H27_CHECK_HIP(hipEventSynchronize(S->beta_ev));
+                beta_conv = true;
+                for (int q = 0; q < nrhs; ++q) {
+                    if (!std::isfinite(h_beta[q])) return HELM27_ENUMERIC;
+                    if (h_beta[q] > thr[q] * bn[q]) beta_conv = false;
+                }
+                if (beta_conv) {
+                    --it;
+                    break;
+                }
+            }
             if (j > 0) {
                 bool done = false;
                 if ((st = check_est(c, j - 1, thr, bn, it - 1, &done))) return st;
@@ -586,6 +600,20 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
                     break;
                 }
             }
+        }
+        if (beta_conv) {   // converged before this cycle: x is final
+            *conv = true;
+            break;
+        }
+        if (!beta_checked) {   // no step ran (max_it reached): check the restart norms
+            H27_CHECK_HIP(hipEventSynchronize(S->beta_ev));
+            bool all = true;
+            for (int q = 0; q < nrhs; ++q) {
+                if (!std::isfinite(h_beta[q])) return HELM27_ENUMERIC;
+                if (h_beta[q] > thr[q] * bn[q]) all = false;
+            }
+            if (all) *conv = true;
+            break;
         }
         if (!cyc_conv && k > 0) {
             bool done = false;
@@ -697,6 +725,7 @@ void solver_free(helm27_op* op) {
     free_hierarchy(S);
     for (hipEvent_t e : S->est_ev)
         if (e) hipEventDestroy(e);
+    if (S->beta_ev) hipEventDestroy(S->beta_ev);
     hipFree(S->d_lin);
     hipFree(S->d_amp);
     hipFree(S->d_b);
