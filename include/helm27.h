@@ -229,7 +229,7 @@ typedef struct {
     int    mg_levels;    /* multigrid levels, 1..8; -1 (default) = halve while the coarser
                             grid keeps >= 8192 points (4 levels for 400x400x200, 3 for
                             101^3, 2 for 41^3); 0 = no preconditioner */
-    double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 0.8) */
+    double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 1.0) */
     int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
     double mg_omega;     /* Jacobi damping (default 0.6) */
     int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 3) */
