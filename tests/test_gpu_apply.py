@@ -323,3 +323,24 @@ def test_apply_rejects_bad_arguments(ctx, table):
                               L.STORED, None) == L.EINVAL
     assert L.lib.helm27_apply(op.handle, C.c_void_p(u.data_ptr()), C.c_void_p(y.data_ptr()), 0, L.C64,
                               L.RECOMPUTE, None) == L.EINVAL
+
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_assemble_validates_velocity(ctx, table, on_device):
+    """The model's range and validity are found on the device: G range from
+    the exact float min / max, and a zero, negative, infinite or NaN velocity
+    anywhere in the grid is rejected, from a host array or a device tensor."""
+    from paper_2108_08730_amd import _lib as L
+    dims, f, h = (30, 22, 17), 6.0, 25.0
+    c = synth.random_field_model(dims, h, seed=8)
+    src = torch.from_numpy(c).cuda() if on_device else c
+    info = ctx.assemble(table, src, h, f, npml=3).info()
+    assert info["g_min_model"] == float(c.min()) / (f * h)
+    assert info["g_max_model"] == float(c.max()) / (f * h)
+    for bad in (0.0, -1500.0, float("inf"), float("nan")):
+        cb = c.copy()
+        cb[9, 13, 21] = bad
+        srcb = torch.from_numpy(cb).cuda() if on_device else cb
+        with pytest.raises(L.Helm27Error) as e:
+            ctx.assemble(table, srcb, h, f, npml=3)
+        assert e.value.status == L.EINVAL
