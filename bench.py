@@ -122,6 +122,32 @@ def apply_only(args, torch, api, synth):
                                  args.apply_variant)), flush=True)
 
 
+def solve_only(args, torch, api, synth):
+    """One multi-RHS solve on the heterogeneous random-field model (the
+    family of the 201x201x101 x 64-source and 400x400x200 x 16-source
+    configurations): sources on a surface line, relative residual 1e-6,
+    mixed precision; prints one JSON line with the solver statistics."""
+    dims = tuple(int(v) for v in args.grid.split(","))
+    h, npml = 25.0, 8
+    ctx = api.Context(0)
+    tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
+    c = synth.random_field_model(dims, h, seed=1)
+    op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, args.freq, npml=npml)
+    info = op.info()
+    xs = np.linspace(npml + 2, dims[0] - npml - 3, args.nrhs).astype(int)
+    src = [(int(x), dims[1] // 2, npml + 2) for x in xs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, st = op.solve(src, tol=1e-6, max_inner=args.max_inner, verbose=1)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    print(json.dumps({"grid": list(dims), "nrhs": args.nrhs, "freq": args.freq, "h": h, "npml": npml,
+                      "g_range": [info["g_min_model"], info["g_max_model"]], "solve_s": sec,
+                      "rhs_per_s": args.nrhs / sec, "inner_iters": st["inner_iters"],
+                      "outer_iters": st["outer_iters"], "max_relres": st["max_relres"],
+                      "converged": bool(st["converged"])}), flush=True)
+
+
 def serving(args, torch, api, synth):
     """Serving mix: Poisson arrivals of solve requests over seeded random-field
     models (frequencies 2.5-10 Hz, h = 1500 / (4 f) so the smallest G is about
@@ -215,6 +241,10 @@ def main():
     ap.add_argument("--apply-dtype", choices=("c64", "c128"), default="c64")
     ap.add_argument("--apply-variant", choices=("recompute", "stored"), default="recompute")
     ap.add_argument("--no-large", action="store_true", help="skip the 400x400x200 apply roofline")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="one multi-RHS solve on --grid with --nrhs surface sources at --freq")
+    ap.add_argument("--freq", type=float, default=10.0)
+    ap.add_argument("--max-inner", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=16, help="serving-mix requests (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="serving-mix Poisson arrival rate (1/s)")
     args = ap.parse_args()
@@ -230,6 +260,9 @@ def main():
 
     if args.apply_only:
         apply_only(args, torch, api, synth)
+        return
+    if args.solve_only:
+        solve_only(args, torch, api, synth)
         return
 
     wl = WORKLOAD
