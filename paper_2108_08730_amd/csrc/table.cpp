@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -285,23 +286,49 @@ extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, d
     BandedLS ls(n, bw);
     std::vector<double> row(bw);
     const double sl = std::sqrt(lambda);
+    // Each G block's dispersion rows touch only its own five columns: they
+    // are reduced to a 5 x 5 triangle (and Q^T b) by Householder reflections
+    // first; an orthogonal transformation leaves the least-squares solution
+    // unchanged, and the banded factorisation then absorbs 5 rows instead of
+    // n_ang^2.  The blocks are independent, so their reductions run on a few
+    // host threads (each block's arithmetic is the same on any thread).
     const int m_ang = n_ang * n_ang;
-    std::vector<double> Ab(static_cast<size_t>(m_ang) * 5), bb(m_ang);
+    std::vector<double> Rt(static_cast<size_t>(n_g) * 25), qt(static_cast<size_t>(n_g) * 5);
+    std::vector<int> nkb(n_g);
+    auto reduce_blocks = [&](int i0, int i1) {
+        std::vector<double> Ab(static_cast<size_t>(m_ang) * 5), bb(m_ang);
+        for (int i = i0; i < i1; ++i) {
+            const double G = g_min + i * dg;
+            int r = 0;
+            for (int jp = 0; jp < n_ang; ++jp)
+                for (int jt = 0; jt < n_ang; ++jt, ++r) dispersion_rows(G, ang[jt], ang[jp], &Ab[5 * r], &bb[r]);
+            const int nk = householder_rows(Ab.data(), bb.data(), m_ang);
+            nkb[i] = nk;
+            for (int k = 0; k < nk; ++k) {
+                for (int l = 0; l < 5; ++l) Rt[25 * static_cast<size_t>(i) + 5 * k + l] = Ab[5 * k + l];
+                qt[5 * static_cast<size_t>(i) + k] = bb[k];
+            }
+        }
+    };
+    {
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int nt = std::max(1, std::min({static_cast<int>(hw ? hw : 1), 8, n_g / 64}));
+        std::vector<std::thread> pool;
+        const int per = (n_g + nt - 1) / nt;
+        try {
+            for (int t = 1; t < nt; ++t) pool.emplace_back(reduce_blocks, std::min(n_g, t * per), std::min(n_g, (t + 1) * per));
+        } catch (...) {
+            for (std::thread& th : pool) th.join();
+            return HELM27_ENOMEM;
+        }
+        reduce_blocks(0, std::min(n_g, per));
+        for (std::thread& th : pool) th.join();
+    }
     for (int i = 0; i < n_g; ++i) {
-        const double G = g_min + i * dg;
-        // the block's dispersion rows touch only its own five columns: reduce
-        // them to a 5 x 5 triangle (and Q^T b) by Householder reflections
-        // first; an orthogonal transformation leaves the least-squares
-        // solution unchanged, and the banded factorisation then absorbs 5 rows
-        // instead of n_ang^2
-        int r = 0;
-        for (int jp = 0; jp < n_ang; ++jp)
-            for (int jt = 0; jt < n_ang; ++jt, ++r) dispersion_rows(G, ang[jt], ang[jp], &Ab[5 * r], &bb[r]);
-        const int nk = householder_rows(Ab.data(), bb.data(), m_ang);
-        for (int k = 0; k < nk; ++k) {
+        for (int k = 0; k < nkb[i]; ++k) {
             std::fill(row.begin(), row.end(), 0.0);
-            for (int l = k; l < 5; ++l) row[l - k] = Ab[5 * k + l];
-            ls.add_row(5 * i + k, row.data(), bb[k]);
+            for (int l = k; l < 5; ++l) row[l - k] = Rt[25 * static_cast<size_t>(i) + 5 * k + l];
+            ls.add_row(5 * i + k, row.data(), qt[5 * static_cast<size_t>(i) + k]);
         }
         // smoothing rows whose first column lies in block i
         if (lambda > 0 && i + order < n_g) {
