@@ -328,7 +328,7 @@ def main():
             "workload": "gradz101: 101^3 grid, c(z)=1500+0.7z m/s, h=25 m, f=5 Hz (G 12..26), 10-node PML, "
                         "1 point source at (50,50,11), rel. residual 1e-6",
             "table": {"g_min": gmin, "g_max": gmax, "dg": dg, "lambda": lam},
-            "solver": "FP64 refinement around complex-FP32 GMRES(20) + shifted-Laplacian multigrid V-cycle (3 levels at this size), replayed from a hipGraph",
+            "solver": "FP64 refinement around complex-FP32 GMRES(28) + shifted-Laplacian multigrid V-cycle (3 levels at this size), replayed from a hipGraph",
             "precision": "complex FP32 stencil/Krylov, FP64 residual and Givens",
         },
         "p50_ms": float(np.percentile(lat_ms, 50)),

@@ -220,7 +220,7 @@ int helm27_set_zchunk(helm27_op* op, int zchunk);
 /* ---- (c) solve ------------------------------------------------------------ */
 typedef struct {
     double tol;          /* relative residual ||b - A u|| / ||b|| per RHS (default 1e-6) */
-    int    restart;      /* GMRES(m) restart length, 1..63 (default 20) */
+    int    restart;      /* GMRES(m) restart length, 1..63 (default 28) */
     int    max_inner;    /* Arnoldi steps per refinement step (default 600) */
     int    max_outer;    /* FP64 refinement steps (default 10) */
     double inner_tol;    /* relative reduction asked of each inner solve (default 1e-4) */
@@ -230,7 +230,7 @@ typedef struct {
                             grid keeps >= 8192 points (4 levels for 400x400x200, 3 for
                             101^3, 2 for 41^3); 0 = no preconditioner */
     double mg_shift;     /* imaginary part b of the preconditioner's mass factor a + i b (default 1.0) */
-    int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level (default 2, 2) */
+    int    mg_pre, mg_post;   /* damped-Jacobi sweeps per level before / after the coarse correction (default 2, 1) */
     double mg_omega;     /* Jacobi damping (default 0.6) */
     int    mg_coarse_sweeps;  /* sweeps on the coarsest level (default 3) */
     int    use_graph;    /* replay each multigrid V-cycle from one captured hipGraph

@@ -736,7 +736,7 @@ void solver_free(helm27_op* op) {
 extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     if (!o) return;
     o->tol = 1e-6;
-    o->restart = 20;
+    o->restart = 28;
     o->max_inner = 600;
     o->max_outer = 10;
     o->inner_tol = 1e-4;
@@ -745,7 +745,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->mg_shift = 1.0;
     o->mg_shift_re = 0.4;
     o->mg_pre = 2;
-    o->mg_post = 2;
+    o->mg_post = 1;
     o->mg_omega = 0.6;
     o->mg_coarse_sweeps = 3;
     o->use_graph = 1;
