@@ -52,6 +52,18 @@ def test_table_matches_oracle_default():
     assert np.max(np.abs(w_lib - w_or)) < 1e-9
 
 
+def test_table_build_is_deterministic():
+    """The per-G block reductions run on several host threads (one per 64+
+    G values, at most 8): repeated builds of a table large enough to use them
+    are bit-identical, and it matches the oracle's dense least squares."""
+    a = _lib_table(3.0, 40.0, 0.05, 1e-3)
+    b = _lib_table(3.0, 40.0, 0.05, 1e-3)
+    assert a.shape == (741, 7)
+    assert np.array_equal(a, b)
+    w_or = T.complete_weights(T.build_table(3.0, 40.0, 0.05, 1e-3)[1])
+    assert np.max(np.abs(a - w_or)) < 1e-9
+
+
 @pytest.mark.parametrize("gmin,gmax,dg,lam,order,tol", [(2.5, 45.0, 0.1, 1e-2, 1, 1e-9),
                                                        (3.0, 8.0, 0.25, 1e-4, 2, 1e-7),
                                                        (3.0, 6.0, 0.5, 0.0, 1, 1e-10)])
