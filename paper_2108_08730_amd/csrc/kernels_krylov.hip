@@ -785,36 +785,48 @@ template <typename R>
 __global__ __launch_bounds__(64 * kXferRows) void prolong_add_kernel(const typename V2<R>::T* __restrict__ c, int cx,
                                                                     int cy, int cz, typename V2<R>::T* __restrict__ f,
                                                                     int nx, int ny, int nz, int nrhs) {
-    // one fine node per thread (trilinear interpolation of the coarse
-    // correction); x from the block's strip, y from the block's rows, (z, rhs)
-    // from the grid.  Per axis an even node takes one coarse node (weight 1),
-    // an odd node two (1/2 each); the second node's index is clamped and its
-    // weight is 0 where it is not used, so all eight loads are issued at once.
+    // trilinear interpolation of the coarse correction, added to the fine
+    // iterate.  One thread per fine (x, y) and pair of fine planes 2p, 2p + 1,
+    // which share coarse plane p: x from the block's strip, y from the block's
+    // rows, (p, rhs) from the grid.  Per axis an even node takes one coarse
+    // node (weight 1), an odd node two (1/2 each); the second node's index is
+    // clamped and its weight is 0 where it is not used, so all eight coarse
+    // loads and both fine loads are issued at once.
     using V = typename V2<R>::T;
+    const int ncp = (nz + 1) / 2;   // plane pairs
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * kXferRows + (threadIdx.x >> 6);
-    const int z = blockIdx.z % nz, rhs = blockIdx.z / nz;
+    const int zp = blockIdx.z % ncp, rhs = blockIdx.z / ncp;
     if (x >= nx || y >= ny) return;
     const V* cr = c + static_cast<int64_t>(rhs) * cx * cy * cz;
-    const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-    const int x1 = min(x0 + 1, cx - 1), y1 = min(y0 + 1, cy - 1), z1 = min(z0 + 1, cz - 1);
-    const R hx = (x & 1) && x0 + 1 < cx ? R(0.5) : R(0), hy = (y & 1) && y0 + 1 < cy ? R(0.5) : R(0),
-            hz = (z & 1) && z0 + 1 < cz ? R(0.5) : R(0);
-    const R gx = (x & 1) ? R(0.5) : R(1), gy = (y & 1) ? R(0.5) : R(1), gz = (z & 1) ? R(0.5) : R(1);
-    V* fp = f + static_cast<int64_t>(rhs) * nx * ny * nz + (static_cast<int64_t>(z) * ny + y) * nx + x;
-    const V* r00 = cr + (static_cast<int64_t>(z0) * cy + y0) * cx;
-    const V* r01 = cr + (static_cast<int64_t>(z0) * cy + y1) * cx;
+    const int x0 = x >> 1, y0 = y >> 1;
+    const int x1 = min(x0 + 1, cx - 1), y1 = min(y0 + 1, cy - 1), z1 = min(zp + 1, cz - 1);
+    const R hx = (x & 1) && x0 + 1 < cx ? R(0.5) : R(0), hy = (y & 1) && y0 + 1 < cy ? R(0.5) : R(0);
+    const R hz = zp + 1 < cz ? R(0.5) : R(0);   // the odd plane's upper coarse plane
+    const R gx = (x & 1) ? R(0.5) : R(1), gy = (y & 1) ? R(0.5) : R(1);
+    const bool odd = 2 * zp + 1 < nz;
+    V* fe = f + static_cast<int64_t>(rhs) * nx * ny * nz + (static_cast<int64_t>(2 * zp) * ny + y) * nx + x;
+    V* fo = odd ? fe + static_cast<int64_t>(nx) * ny : fe;
+    const V* r00 = cr + (static_cast<int64_t>(zp) * cy + y0) * cx;
+    const V* r01 = cr + (static_cast<int64_t>(zp) * cy + y1) * cx;
     const V* r10 = cr + (static_cast<int64_t>(z1) * cy + y0) * cx;
     const V* r11 = cr + (static_cast<int64_t>(z1) * cy + y1) * cx;
     const V a0 = r00[x0], a1 = r00[x1], b0 = r01[x0], b1 = r01[x1];
     const V c0 = r10[x0], c1 = r10[x1], d0 = r11[x0], d1 = r11[x1];
-    V o = *fp;
-    const R w00 = gz * gy, w01 = gz * hy, w10 = hz * gy, w11 = hz * hy;
-    o.x += w00 * (gx * a0.x + hx * a1.x) + w01 * (gx * b0.x + hx * b1.x) + w10 * (gx * c0.x + hx * c1.x) +
-           w11 * (gx * d0.x + hx * d1.x);
-    o.y += w00 * (gx * a0.y + hx * a1.y) + w01 * (gx * b0.y + hx * b1.y) + w10 * (gx * c0.y + hx * c1.y) +
-           w11 * (gx * d0.y + hx * d1.y);
-    *fp = o;
+    V oe = *fe, oo = *fo;
+    // interpolated in x and y on coarse planes zp (P) and zp + 1 (Q)
+    const R px = gy * (gx * a0.x + hx * a1.x) + hy * (gx * b0.x + hx * b1.x);
+    const R py = gy * (gx * a0.y + hx * a1.y) + hy * (gx * b0.y + hx * b1.y);
+    const R qx = gy * (gx * c0.x + hx * c1.x) + hy * (gx * d0.x + hx * d1.x);
+    const R qy = gy * (gx * c0.y + hx * c1.y) + hy * (gx * d0.y + hx * d1.y);
+    oe.x += px;
+    oe.y += py;
+    *fe = oe;
+    if (odd) {
+        oo.x += R(0.5) * px + hz * qx;
+        oo.y += R(0.5) * py + hz * qy;
+        *fo = oo;
+    }
 }
 
 template <typename R>
@@ -843,7 +855,8 @@ int mg_prolong_add(const void* c, int cx, int cy, int cz, void* f, int nx, int n
     const int64_t Nf = static_cast<int64_t>(nx) * ny * nz, Nc = static_cast<int64_t>(cx) * cy * cz;
     for (int r0 = 0; r0 < nrhs; r0 += per) {
         const int n = nrhs - r0 < per ? nrhs - r0 : per;
-        H27_CHECK_HIP(launch(prolong_add_kernel<R>, dim3((nx + 63) / 64, (ny + kXferRows - 1) / kXferRows, nz * n),
+        H27_CHECK_HIP(launch(prolong_add_kernel<R>,
+                             dim3((nx + 63) / 64, (ny + kXferRows - 1) / kXferRows, (nz + 1) / 2 * n),
                              dim3(64 * kXferRows), 0, s,
                              static_cast<const V*>(c) + r0 * Nc, cx, cy, cz, static_cast<V*>(f) + r0 * Nf, nx, ny,
                              nz, n));
