@@ -850,11 +850,15 @@ void h27::solver_trim(helm27_op* op) {
 size_t h27::solve_footprint(int64_t N, int nrhs, int restart, int precision, int levels) {
     const double e = precision == HELM27_C128 ? 16.0 : 8.0;   // complex element bytes, inner precision
     const double n = static_cast<double>(N) * nrhs;
-    double bytes = n * e * (restart + 1 + 5);                   // Krylov basis, w, e, rin, tmp, vin
-    double lv = 0, f = 1;
+    double bytes = n * e * (restart + 1 + 6);                   // Krylov basis, w, e, rin, tmp, vin, vy
+    double lv = 0, f = 1, pl = 0;
     if (levels < 0) levels = 8;                                 // automatic depth: bound
-    for (int l = 0; l < levels; ++l, f /= 8) lv += f * (l == 0 ? 3 : 4);
+    for (int l = 0; l < levels; ++l, f /= 8) {
+        lv += f * (l == 0 ? 3 : 4);
+        pl += f;
+    }
     bytes += n * e * lv;                                        // multigrid vectors
+    bytes += static_cast<double>(N) * e * pl;                   // omega D^-1 per level
     bytes += n * 16.0 * 2;                                      // FP64 residual and right-hand side
     bytes += static_cast<double>(N) * 7.0;                      // coarse grids (velocity + index + ...)
     bytes += static_cast<double>(nrhs) * (restart + 2) * 1024 * 16;   // reduction partials
