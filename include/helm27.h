@@ -191,8 +191,9 @@ int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int
  * the fastest and returns its rows in *best_rows (may be NULL).  Until one
  * of helm27_set_tuning, helm27_tune, helm27_set_kernel_variant or
  * helm27_set_zchunk is called, every launch chooses its own shape from its
- * work size: 2^23 or more point-RHS pairs take variant 2 with 16-plane
- * chunks and 1 row (one RHS) or 2 rows (several, FP32), smaller launches
+ * work size: 2^23 or more point-RHS pairs take variant 2 with 1 row and
+ * 32-plane chunks (one RHS) or 2 rows (FP32) and 16-plane chunks (several),
+ * smaller launches
  * variant 0 with 2 rows (FP32) / 1 row (FP64) and automatic chunks.  After
  * such a call the operator keeps its explicit settings (operators of 2^23
  * points or more start from variant 2, 1 row, 16-plane chunks; smaller ones

@@ -451,10 +451,11 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         int RY = g.plain_ry[fp64 ? 1 : 0], variant = g.kernel_variant, zc_set = g.wave_zchunk;
         if (g.auto_tile) {
             // HBM-bound launches (2^23 or more point-RHS pairs): box rows shared
-            // across the block (variant 2) in 16-plane chunks, one row per
-            // wavefront for one RHS and two for several (400x400x200: 187-198 us
-            // against 203-213 us for variant 0; 201x201x101 x 16 RHS: 390 us
-            // against 431 us); smaller launches keep the latency-friendlier
+            // across the block (variant 2), one row per wavefront in 32-plane
+            // chunks for one RHS, two rows in 16-plane chunks for several
+            // (400x400x200: 181 us against 185 us with 16-plane chunks and
+            // 203-213 us for variant 0; 201x201x101 x 16 RHS: 390 us against
+            // 431 us); smaller launches keep the latency-friendlier
             // per-wavefront tiles with automatic chunks
             const bool big = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23);
             RY = fp64 ? g.plain_ry[1] : (big && nrhs >= 2 ? 2 : (big ? 1 : 2));
@@ -463,7 +464,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
             const size_t ring = static_cast<size_t>(2 * (4 * RY + 2) * 64) * sizeof(typename V2<R>::T);
             if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= 64 * 1024) {
                 variant = 2;
-                zc_set = 16;
+                zc_set = nrhs == 1 ? 32 : 16;
             }
         }
         const int RQ = frame_rows<R>();

@@ -206,6 +206,29 @@ def test_apply_many_rhs_block_tiles_sampled(ctx, table, oracle_table):
         assert _relerr(y32[r], y1) <= 1e-5
 
 
+def test_apply_large_single_rhs_sampled(ctx, table, oracle_table):
+    """256 x 256 x 128 random field (2^23 points), 8-node PML, one
+    right-hand side: the launch takes the block-tile kernel with one row per
+    wavefront and 32-plane chunks; FP64 and FP32 sampled rows against the
+    oracle."""
+    dims, npml, f, h = (256, 256, 128), 8, 8.0, 25.0
+    c = synth.random_field_model(dims, h, seed=41)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    N = int(np.prod(dims))
+    assert N >= 2 ** 23
+    idx_o, _ = O.select_index(c, f, h, 3.0, 0.05, 341)
+    rows = np.unique(np.random.default_rng(6).integers(0, N, 1200))
+    w = O.row_weights("GA", idx_o, oracle_table[2])
+    A = O.assemble_rows(c, f, h, npml, w[rows], rows)
+    u = synth.random_vectors(N, 1, seed=14)
+    y_ref = (A @ u.T).T
+    ud = torch.from_numpy(u).cuda()
+    y64 = op.apply(ud).cpu().numpy()[:, rows]
+    y32 = op.apply(ud.to(torch.complex64)).cpu().numpy()[:, rows]
+    assert _relerr(y64[0], y_ref[0]) <= 1e-12
+    assert _relerr(y32[0], y_ref[0]) <= 1e-5
+
+
 def test_apply_large_random_field_sampled(ctx, table, oracle_table):
     """201 x 201 x 101 heterogeneous model, 8-node PML, f = 8 Hz, 4 right-hand
     sides: sampled rows against the oracle."""
