@@ -224,7 +224,7 @@ typedef struct {
     int    restart;      /* GMRES(m) restart length, 1..63 (default 28) */
     int    max_inner;    /* Arnoldi steps per refinement step (default 600) */
     int    max_outer;    /* FP64 refinement steps (default 10) */
-    double inner_tol;    /* relative reduction asked of each inner solve (default 1e-4) */
+    double inner_tol;    /* relative reduction asked of each inner solve (default 1e-3) */
     int    precision;    /* HELM27_C64: FP32 inner + FP64 refinement (default);
                             HELM27_C128: everything in FP64 */
     int    mg_levels;    /* multigrid levels, 1..8; -1 (default) = halve while the coarser

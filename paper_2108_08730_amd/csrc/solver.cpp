@@ -739,7 +739,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->restart = 28;
     o->max_inner = 600;
     o->max_outer = 10;
-    o->inner_tol = 1e-4;
+    o->inner_tol = 1e-3;
     o->precision = HELM27_C64;
     o->mg_levels = -1;
     o->mg_shift = 1.0;
