@@ -249,8 +249,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=4.0, help="serving-mix Poisson arrival rate (1/s)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded path is a design "
-              f"described in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no multi-GPU "
+              f"path (sources and frequencies would be split across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     _ensure_lib()

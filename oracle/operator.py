@@ -23,7 +23,7 @@ What is assembled (Sec. 2.1, the matrix form [M + S] p = s):
   per-point mass weights (see ``table``);
 * PML by complex coordinate stretching d/dx -> (1/xi) d/dx (Sec. 2.1).
 
-Readings (also in DESIGN.md):
+Readings:
 
 * G = c / (f h); a row takes the table entry nearest its G, ties going up:
   idx = clamp(floor((G - gmin)/dG + 1/2), 0, N_G - 1), every step in IEEE

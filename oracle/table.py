@@ -14,7 +14,7 @@ Follows Sec. 2.2 of the paper:
   "Gm" weights) and the block-diagonal, Tikhonov-regularised problem
   min ||H w - g||^2 + lambda ||D P w||^2 (adaptive table).
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
 
 * H_2 is printed without the constant term; eliminating w_s3 from v~ = 1 gives
   H_2 = (1 + 3A - 5B/3 + C/3)/2.  The rows here are *derived* from v~ (see
