@@ -183,6 +183,13 @@ class Operator:
             pass
 
 
+def _check_device_velocity(vel):
+    """A device velocity is read in place as float32 [nz][ny][nx]."""
+    torch = _torch()
+    if vel.dtype != torch.float32 or not vel.is_contiguous() or vel.dim() != 3:
+        raise TypeError("device velocity must be a contiguous float32 tensor of shape [nz, ny, nx]")
+
+
 def solve_opts(**kw):
     o = L.SolveOpts()
     L.lib.helm27_solve_opts_default(C.byref(o))
@@ -222,6 +229,7 @@ class Context:
                  weights="GA", store: Iterable[str] = ()) -> Operator:
         """vel: numpy float32 [nz, ny, nx] or a device tensor of that shape."""
         if hasattr(vel, "data_ptr"):
+            _check_device_velocity(vel)
             nz, ny, nx = vel.shape
             ptr = C.c_void_p(vel.data_ptr())
             keep = vel
@@ -275,6 +283,7 @@ class Server:
         out tensor [nrhs, N] complex128 that receives the solution)."""
         torch = _torch()
         if hasattr(vel, "data_ptr"):
+            _check_device_velocity(vel)
             nz, ny, nx = vel.shape
             vptr = C.cast(C.c_void_p(vel.data_ptr()), C.POINTER(C.c_float))
         else:
@@ -317,11 +326,13 @@ class Server:
         if st == L.EAGAIN:
             return None
         L.check(st, "serve_poll")
+        self._keep.pop(ticket, None)   # the library no longer writes the output
         return self._res(r)
 
     def wait(self, ticket, timeout=600.0):
         r = L.Result()
         L.check(L.lib.helm27_serve_wait(self._ctx.handle, ticket, C.byref(r), timeout), "serve_wait")
+        self._keep.pop(ticket, None)   # the library no longer writes the output
         return self._res(r)
 
     def stop(self):

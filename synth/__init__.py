@@ -55,7 +55,7 @@ def random_field_model(dims, h, seed, c_top=1500.0, c_bottom=4500.0, std=300.0,
     KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
     # Fourier transform of exp(-r^2/corr^2) is proportional to exp(-k^2 corr^2 / 4)
     filt = np.exp(-(KZ ** 2 + KY ** 2 + KX ** 2) * corr ** 2 / 4.0)
-    field = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(nz, ny, nx))
+    field = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(nz, ny, nx), axes=(0, 1, 2))
     sd = field.std()
     if sd > 0:
         field = field / sd * std

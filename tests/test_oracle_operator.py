@@ -179,3 +179,96 @@ def test_gam_equals_ga_where_uniform_and_averages_at_interface(w7_table):
     assert np.allclose(ga[0], gam[0]) and np.allclose(ga[5], gam[5])
     # plane 2 sees planes 1,2 (slow) and 3 (fast): 2/3 slow, 1/3 fast
     assert np.allclose(gam[2, 2, 2], (2 * ga[0, 0, 0] + ga[5, 0, 0]) / 3)
+
+
+def _pml_classes(dims, npml):
+    """Per point: along each axis 0 (interior), 1 (low face) or 2 (high face)."""
+    nx, ny, nz = dims
+    ii, jj, kk = _grid(nx, ny, nz)
+    out = []
+    for q, n, p in ((ii, nx, npml[0]), (jj, ny, npml[1]), (kk, nz, npml[2])):
+        out.append(np.where(q < p, 1, np.where(q >= n - p, 2, 0)))
+    return np.stack(out, axis=1)
+
+
+def test_assemble_rows_equals_assemble(w7_table):
+    """The row-by-row assembly used on large grids reproduces the whole-matrix
+    assembly on a heterogeneous grid whose rows cover the interior, every PML
+    face, edge and corner class and the grid boundary (Sec. 2.1 operator,
+    built two different ways: Kronecker products of whole 1D matrices versus
+    of single rows)."""
+    Gs, W7 = w7_table
+    dims, npml, f, h = (11, 10, 9), (3, 2, 3), 7.0, 25.0
+    c = synth.random_field_model(dims, h, seed=21)
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, len(Gs))
+    w = O.row_weights("GA", idx, W7)
+    classes = _pml_classes(dims, npml)
+    # every combination of (interior, low, high) per axis occurs
+    assert len({tuple(r) for r in classes}) == 27
+    rows = np.arange(int(np.prod(dims)))
+    for shift in (0.0, 0.7):
+        A = O.assemble(c, f, h, npml, w, shift=shift)
+        Ar = O.assemble_rows(c, f, h, npml, w[rows], rows, shift=shift)
+        diff = abs(A - Ar).max()
+        assert diff <= 1e-14 * abs(A).max(), (shift, diff)
+        # the same explicit sparsity (no entry missing on either side)
+        assert (A != 0).nnz == (Ar != 0).nnz
+
+
+def _mass_entry_by_entry(c, f, h, npml, w, form):
+    """Consistent mass of Sec. 2.1, equation (8), written out entry by entry:
+    row i, neighbour j = i + d, class n = number of nonzero components of d,
+    entry omega^2 / kappa_m * w_m[n](i) * prod_a s_a, where kappa_m is the bulk
+    modulus (c^2, unit density) of the neighbour j in the first form and of
+    the collocation point i in the second, and s_a is the coordinate stretch
+    at the node (d_a = 0) or at the half node between i and j (d_a = +-1)."""
+    nz, ny, nx = c.shape
+    omega = 2.0 * math.pi * f
+    cr = float(c.astype(np.float64).max())
+    prof = [O.pml_profile(n, p, h, omega, cr) for n, p in zip((nx, ny, nz), npml)]
+    c64 = c.astype(np.float64).ravel()
+    N = nx * ny * nz
+    M = np.zeros((N, N), complex)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = i + nx * (j + ny * k)
+                for dz in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            q = (i + dx, j + dy, k + dz)
+                            if not (0 <= q[0] < nx and 0 <= q[1] < ny and 0 <= q[2] < nz):
+                                continue
+                            col = q[0] + nx * (q[1] + ny * q[2])
+                            s = 1.0 + 0j
+                            for a, (node, d) in enumerate(((i, dx), (j, dy), (k, dz))):
+                                xn, xh = prof[a]
+                                # half node between node and node + d is xh[node + 1] (d = +1) or xh[node] (d = -1)
+                                s *= xn[node] if d == 0 else xh[node + (1 if d > 0 else 0)]
+                            n = abs(dx) + abs(dy) + abs(dz)
+                            kap = c64[col] ** 2 if form == "a" else c64[r] ** 2
+                            M[r, col] += omega ** 2 / kap * w[r, 3 + n] * s
+    return M
+
+
+@pytest.mark.parametrize("form", ["a", "b"])
+def test_mass_forms_entry_by_entry_heterogeneous(w7_table, form):
+    """Both consistent-mass forms of Sec. 2.1 on a heterogeneous model with
+    PML: the assembled matrix minus its stiffness (the same matrix assembled
+    with zero mass weights) equals the mass written out entry by entry.  In a
+    heterogeneous medium the two forms differ, and a row/column mix-up of the
+    bulk modulus fails one of the two cases."""
+    Gs, W7 = w7_table
+    dims, npml, f, h = (6, 5, 7), (2, 1, 2), 9.0, 25.0
+    c = synth.random_field_model(dims, h, seed=5)
+    c[3:] *= np.float32(1.35)   # a sharp jump, so neighbouring k^2 differ
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, len(Gs))
+    w = O.row_weights("GA", idx, W7)
+    w_stiff = w.copy()
+    w_stiff[:, 3:] = 0.0
+    A = O.assemble(c, f, h, npml, w, mass_form=form).toarray()
+    S = O.assemble(c, f, h, npml, w_stiff, mass_form=form).toarray()
+    M = _mass_entry_by_entry(c, f, h, npml, w, form)
+    assert np.abs((A - S) - M).max() <= 1e-13 * np.abs(M).max()
+    other = _mass_entry_by_entry(c, f, h, npml, w, "b" if form == "a" else "a")
+    assert np.abs(other - M).max() > 1e-3 * np.abs(M).max()
