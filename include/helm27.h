@@ -211,6 +211,23 @@ int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows
  * All compute the same operator.  Switches off the per-launch choice (see
  * helm27_tune).  Errors: EINVAL. */
 int helm27_set_kernel_variant(helm27_op* op, int variant);
+/* Right-hand sides per box wavefront of the FP32 recompute kernels: with
+ * nb = 2 or 4 a wavefront computes one output row (62 columns) of nb
+ * consecutive right-hand sides at once (block tiles of four wavefronts that
+ * share plane rows through LDS), so a point's table index, velocity and
+ * coefficients are read and formed once per nb right-hand sides; nb = 1 or
+ * 0 (default) keep one right-hand side per wavefront.  Used by every mode
+ * (apply, residual, Jacobi sweeps) of FP32 launches with several right-hand
+ * sides; helm27_tune sweeps it for nrhs >= 2.  Results agree to rounding
+ * across choices.  Errors: EINVAL (nb not 0, 1, 2 or 4). */
+int helm27_set_rhs_block(helm27_op* op, int nb);
+/* Work-item order of launches with several right-hand sides: 2 = right-hand
+ * side slowest (each right-hand side's tiles run together, so the rows and
+ * planes neighbouring tiles share are re-read from cache), 1 = right-hand
+ * side fastest (a tile's right-hand sides run together and share its
+ * per-point data), 0 (default) = 2.  helm27_tune sweeps it for nrhs >= 2.
+ * Results are bit-identical across orders.  Errors: EINVAL. */
+int helm27_set_rhs_order(helm27_op* op, int order);
 /* z planes per work item of the wavefront kernel (each item marches its
  * chunk of planes; two extra planes are read per chunk): 0 = automatic
  * (about 4096 work items, 2..16 planes each), else 2..4096.  Results agree

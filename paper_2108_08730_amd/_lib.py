@@ -93,6 +93,8 @@ def _load():
         "helm27_set_tuning": (C.c_int, [P, C.c_int, C.c_int]),
         "helm27_set_kernel_variant": (C.c_int, [P, C.c_int]),
         "helm27_set_zchunk": (C.c_int, [P, C.c_int]),
+        "helm27_set_rhs_block": (C.c_int, [P, C.c_int]),
+        "helm27_set_rhs_order": (C.c_int, [P, C.c_int]),
         "helm27_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
         "helm27_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
         "helm27_solve": (C.c_int, [P, C.POINTER(C.c_double), C.c_void_p, C.c_int, C.POINTER(SolveOpts),

@@ -125,6 +125,14 @@ class Operator:
         """z planes per work item of the wavefront kernel (0 = automatic)."""
         L.check(L.lib.helm27_set_zchunk(self._h, zchunk), "set_zchunk")
 
+    def set_rhs_block(self, nb):
+        """Right-hand sides per box wavefront of FP32 launches: 1, 2, 4, or 0 (automatic)."""
+        L.check(L.lib.helm27_set_rhs_block(self._h, nb), "set_rhs_block")
+
+    def set_rhs_order(self, order):
+        """Multi-RHS work-item order: 2 right-hand side slowest, 1 fastest, 0 automatic."""
+        L.check(L.lib.helm27_set_rhs_order(self._h, order), "set_rhs_order")
+
     def tune(self, nrhs=1, dtype="c64", stream=None):
         dt = L.C64 if dtype in ("c64", L.C64) else L.C128
         best = C.c_int()

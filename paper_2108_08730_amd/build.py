@@ -35,7 +35,8 @@ EXTRA = {
 }
 SOURCES = [
     "table.cpp", "op.cpp", "solver.cpp", "serve.cpp",
-    "kernels_assemble.hip", "kernels_stencil.hip", "kernels_wave.hip", "kernels_krylov.hip",
+    "kernels_assemble.hip", "kernels_stencil.hip", "kernels_wave.hip", "kernels_wave_apply.hip",
+    "kernels_wave_resid.hip", "kernels_wave_jacobi.hip", "kernels_wave_jacobi0.hip", "kernels_krylov.hip",
 ]
 
 
@@ -55,7 +56,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]

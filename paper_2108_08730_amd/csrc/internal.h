@@ -150,6 +150,10 @@ struct GridOp {
     int plain_ry[2] = {2, 1};                  // box rows per wavefront: [fp32, fp64] (1..4)
     int kernel_variant = 0;                    // 0: wavefront-per-tile kernel, 1: LDS-tiled kernel
     int wave_zchunk = 0;                       // z planes per wavefront work item (0: automatic)
+    int rhs_block = 0;                         // right-hand sides per box wavefront (FP32 block tiles):
+                                               // 0 = automatic (1), 1, 2 or 4
+    int rhs_order = 0;                         // work-item order of a multi-RHS launch: 0 = automatic
+                                               // (right-hand side slowest), 1 = fastest, 2 = slowest
     bool auto_tile = true;                     // kernel variant, rows and z chunk chosen per launch from
                                                // the work size; an explicit setting or the tuner clears it
     size_t bytes = 0;

@@ -400,6 +400,23 @@ static int launch_mode(const StencilArgs<R>& args, dim3 grid, hipStream_t s) {
     return HELM27_OK;
 }
 
+// LDS bytes one block may use on the current device (queried once per device)
+static size_t lds_limit() {
+    static std::mutex mu;
+    static std::vector<size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 64 * 1024;
+    std::lock_guard<std::mutex> lk(mu);
+    if (static_cast<size_t>(dev) >= cache.size()) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int v = 0;
+        cache[dev] = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0
+                         ? static_cast<size_t>(v)
+                         : 64 * 1024;
+    }
+    return cache[dev];
+}
+
 // whether the wavefront kernel serves this grid (else the LDS-tiled kernel)
 bool stencil_wave_path(const GridOp& g, bool fp64) {
     const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
@@ -409,7 +426,7 @@ bool stencil_wave_path(const GridOp& g, bool fp64) {
     const size_t ring = g.kernel_variant == 2 ? static_cast<size_t>(2 * (4 * ry + 2) * 64) * (fp64 ? 16 : 8) : 0;
     return (g.kernel_variant == 0 || g.kernel_variant == 2) && n_tab > 0 &&
            static_cast<int64_t>(g.N) * (fp64 ? 16 : 8) < (int64_t(1) << 31) &&
-           wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= 64 * 1024;
+           wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit();
 }
 
 template <typename R>
@@ -462,12 +479,41 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
             variant = 0;
             zc_set = 0;
             const size_t ring = static_cast<size_t>(2 * (4 * RY + 2) * 64) * sizeof(typename V2<R>::T);
-            if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= 64 * 1024) {
+            if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit()) {
                 variant = 2;
                 zc_set = nrhs == 1 ? 32 : 16;
             }
         }
         const int RQ = frame_rows<R>();
+        // several right-hand sides per box wavefront (FP32 block tiles, one
+        // row per wavefront) when asked for (helm27_set_rhs_block or the
+        // tuner), the group's vectors are addressable with 32-bit buffer
+        // offsets and its row ring fits in LDS.  Automatic: one (measured on
+        // 400x400x200 x 16 and 201x201x101 x 64: groups of 2 or 4 change the
+        // time by -4 % to +4 %; the per-RHS cost is the row traffic of u
+        // and y, not the per-point data the groups share)
+        int NB = 1;
+        if (!fp64 && nrhs >= 2 && g.rhs_block > 1) {
+            NB = g.rhs_block;
+            const bool fits = static_cast<int64_t>(g.N) * 8 * NB < (int64_t(1) << 31) &&
+                              wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + wave_ring_bytes(1, NB, fp64) <=
+                                  lds_limit();
+            if (!fits) NB = 1;
+        }
+        if (NB > 1) {
+            variant = 2;
+            RY = 1;
+            if (g.auto_tile) zc_set = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23) ? 32 : 0;
+        }
+        w.nb = NB;
+        w.ngrp = (nrhs + NB - 1) / NB;
+        // multi-RHS item order: right-hand side slowest by default (each
+        // right-hand side's pass keeps its tiles' shared halo rows and planes
+        // close in time, as a single-RHS launch does; 201x201x101 x 64:
+        // 1.81 -> 1.52 ms), or fastest (the per-point data of a tile are
+        // shared by its right-hand sides in L2)
+        w.rhs_outer = g.rhs_order == 1 ? 0 : 1;
+        const int TC = kWaveCols;
         w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
         Rect fr[4] = {t.frame[0], t.frame[1], t.frame[2], t.frame[3]};
         // The box is cut into 62-column tiles; a last partial tile costs as
@@ -476,8 +522,8 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         // already use, they take them (the general formula holds for
         // unstretched columns too) and the box becomes whole tiles
         // (400 wide with an 8-node PML: 6 tiles instead of 6 + 12 columns).
-        if (w.pw > kWaveCols && fr[2].w > 0 && fr[3].w > 0) {
-            const int left = w.pw % kWaveCols;
+        if (w.pw > TC && fr[2].w > 0 && fr[3].w > 0) {
+            const int left = w.pw % TC;
             const int capl = 14 * ((fr[2].w + 13) / 14) - fr[2].w, capr = 14 * ((fr[3].w + 13) / 14) - fr[3].w;
             if (left > 0 && left <= capl + capr) {
                 const int a = std::min(left, capl);
@@ -491,7 +537,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
         w.blk = variant == 2 ? 1 : 0;
         const int rows_per_tile = w.blk ? 4 * RY : RY;
-        w.ntx = w.pw > 0 ? (w.pw + kWaveCols - 1) / kWaveCols : 0;
+        w.ntx = w.pw > 0 ? (w.pw + TC - 1) / TC : 0;
         w.nty = w.ph > 0 ? (w.ph + rows_per_tile - 1) / rows_per_tile : 0;
         w.n_plain = w.ntx * w.nty;
         int accf = 0;
@@ -514,7 +560,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         w.n_frame = accf;
         // work items: wavefront items (variant 0) or block items of 4 wavefronts (variant 2)
         const int64_t tiles = static_cast<int64_t>(w.blk ? (w.n_frame + 3) / 4 + w.n_plain : w.n_plain + w.n_frame) *
-                              nrhs;
+                              w.ngrp;
         if (tiles <= 0) return HELM27_OK;
         const int64_t target = w.blk ? 1024 : 4096;
         int64_t nzc = (target + tiles - 1) / tiles;

@@ -1,804 +1,20 @@
-// Wavefront-per-tile 27-point stencil (apply, residual, damped Jacobi).
-//
-// Operator (paper Sec. 2.1 with per-row weights, Sec. 3.1): for an output row
-// with table entry E and kappa = k^2 (a + i b) ((a, b) = (1, 0) for the
-// physical operator),
-//   A u = (1/h^2) [ sum_a T_a + beta2 sum_{a<b} T_a T_b + beta3 T_x T_y T_z ] u
-//       + kappa   [ m0 XXX + 2 m1 sum UXX + 4 m2 sum UUX + 8 m3 UUU ] u
-// with T, U, X the (stretched) 1D second difference, neighbour half-sum and
-// node stretch; an axis absent from a product contributes X.
-//
-// One wavefront per work item: 62 output columns along its lane axis (lanes
-// 0 and 63 are halo), R rows along the other in-plane axis, a chunk of z
-// planes marched in registers, one right-hand side.
-//   * All control flow is wave-uniform (scalar registers): the work item, the
-//     z loop, the plane kind, the row count and the grid-edge case.
-//   * In-plane neighbours along the lane axis come from cross-lane DPP shifts
-//     of the values the wave loaded, along the row axis from the R + 2 rows it
-//     loads per plane, along z from the previous planes kept in registers.
-//   * Software pipeline: the loads of plane q + 2 and the per-point data of
-//     output plane q are issued before plane q is combined; loads go to
-//     clamped (always valid) addresses and the zero outside the grid is
-//     applied when the plane is used.  The z loop is unrolled three times so
-//     the three load buffers, plane slots and per-point slots rotate by
-//     renaming, not copying.
-//   * The slice of the weight table the grid uses is staged in LDS per block
-//     (stiffness weights pre-scaled by 1/h^2).
-//   * Blocks are renumbered so that each XCD (blocks dispatched round-robin
-//     over the 8 XCDs) runs a contiguous range of work items, and rows shared
-//     by neighbouring tiles are re-read from its own L2.
-// Two kinds of work items share a launch:
-//   * box tiles (x and y unstretched, lanes along x): per plane the centre c,
-//     4-face sum f and 4-diagonal sum e; the output is a 9-term combination
-//     with real coefficients, complex in z-PML planes (uniform per plane);
-//   * PML-frame tiles (lanes along x in groups of 64 or 16): the separable
-//     contractions a = XX u, b = (TX + XT) u, c = TT u, d = (UX + XU) u,
-//     e = UU u with the complex 1D factors of the lane node and of the row
-//     node, then the same z combination.
-#include "stencil.h"
+// Mode dispatch of the wavefront-per-tile stencil kernels (the kernels and
+// their launchers are in wave_impl.h; each mode is compiled in its own
+// translation unit, kernels_wave_<mode>.hip).
+#include "wave_impl.h"
 
 namespace h27 {
-
-// LDS copy of one table entry: s = stiffness class weights times 1/h^2,
-// m = mass class weights, b2 / b3 = unscaled beta2 / beta3 (frame formula).
-template <typename R>
-struct alignas(16) TabEntry {
-    R s[4];
-    R m[4];
-    R b2, b3, pad0, pad1;
-};
-
-// lane i <- lane i + 1 (wshl) and lane i <- lane i - 1 (wshr), whole wavefront
-__device__ __forceinline__ float wshl(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float wshr(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
-}
-__device__ __forceinline__ double wshl(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffLL), 0x130, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x130, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-__device__ __forceinline__ double wshr(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffLL), 0x138, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x138, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-// the same within each row of 16 lanes
-__device__ __forceinline__ float rshl(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float rshr(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
-}
-__device__ __forceinline__ double rshl(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffLL), 0x101, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x101, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-__device__ __forceinline__ double rshr(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffLL), 0x111, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x111, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-// neighbours along the lane axis for a lane-group width of 64 (whole wave) or 16 (DPP rows)
-template <int LW, typename R>
-__device__ __forceinline__ Cx<R> nxt_g(Cx<R> v) {
-    if (LW == 64) return Cx<R>{wshl(v.re), wshl(v.im)};
-    return Cx<R>{rshl(v.re), rshl(v.im)};
-}
-template <int LW, typename R>
-__device__ __forceinline__ Cx<R> prv_g(Cx<R> v) {
-    if (LW == 64) return Cx<R>{wshr(v.re), wshr(v.im)};
-    return Cx<R>{rshr(v.re), rshr(v.im)};
-}
-
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// reciprocal: v_rcp_f32 (1 ulp) in the FP32 kernels, a correctly rounded
-// division in the FP64 kernels
-__device__ __forceinline__ float rcp_of(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_of(double x) { return 1.0 / x; }
-
-template <typename R>
-__device__ __forceinline__ Cx<R> inv_of(Cx<R> a) {
-    const R d = rcp_of(a.re * a.re + a.im * a.im);
-    return Cx<R>{a.re * d, -a.im * d};
-}
-
-// the value a mode stores for the operator row acc = (A u)_i
-template <typename R, int MODE>
-__device__ __forceinline__ Cx<R> finish(R omega_j, Cx<R> acc, Cx<R> diag, Cx<R> xcen,
-                                        typename V2<R>::T bb) {
-    if (MODE == MODE_APPLY) return acc;
-    if (MODE == MODE_JACOBI0) return omega_j * (Cx<R>{bb.x, bb.y} * inv_of(diag));
-    const Cx<R> rr{bb.x - acc.re, bb.y - acc.im};
-    if (MODE == MODE_RESID) return rr;
-    return xcen + omega_j * (rr * inv_of(diag));
-}
-
-// ---------------------------------------------------------------------------
-// Buffer loads and stores.  Every vector access goes through a buffer resource
-// with the byte size of its array, so the hardware range check does the grid
-// boundary: a lane offset of kOff (or a plane outside the grid, whose
-// resource has size 0) reads 0 and drops the store; no lane masks, no
-// address arithmetic in the vector unit.
-using Rsrc = __amdgpu_buffer_rsrc_t;
-using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
-using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
-constexpr int kRsrcWord3 = 0x00020000;          // untyped 32-bit data, range checked
-constexpr unsigned kOff = 0x80000000u;          // beyond every buffer (sizes < 2^31 bytes)
-
-__device__ __forceinline__ Rsrc rsrc(const void* p, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRsrcWord3);
-}
-__device__ __forceinline__ void bld(float2& v, Rsrc r, unsigned vo, unsigned so) {
-    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(vo), static_cast<int>(so), 0);
-    v.x = __uint_as_float(w.x);
-    v.y = __uint_as_float(w.y);
-}
-__device__ __forceinline__ void bld(double2& v, Rsrc r, unsigned vo, unsigned so) {
-    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(vo), static_cast<int>(so), 0);
-    v.x = __hiloint2double(static_cast<int>(w.y), static_cast<int>(w.x));
-    v.y = __hiloint2double(static_cast<int>(w.w), static_cast<int>(w.z));
-}
-__device__ __forceinline__ void bst(Cx<float> v, Rsrc r, unsigned vo, unsigned so) {
-    u32x2 w;
-    w.x = __float_as_uint(v.re);
-    w.y = __float_as_uint(v.im);
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(vo), static_cast<int>(so), 0);
-}
-__device__ __forceinline__ void bst(Cx<double> v, Rsrc r, unsigned vo, unsigned so) {
-    u32x4 w;
-    w.x = static_cast<unsigned>(__double2loint(v.re));
-    w.y = static_cast<unsigned>(__double2hiint(v.re));
-    w.z = static_cast<unsigned>(__double2loint(v.im));
-    w.w = static_cast<unsigned>(__double2hiint(v.im));
-    __builtin_amdgcn_raw_buffer_store_b128(w, r, static_cast<int>(vo), static_cast<int>(so), 0);
-}
-__device__ __forceinline__ int bld_u16(Rsrc r, unsigned vo, unsigned so) {
-    return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), 0));
-}
-__device__ __forceinline__ float bld_f32(Rsrc r, unsigned vo, unsigned so) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo), static_cast<int>(so), 0));
-}
-
-// table entry reads from LDS as 16-byte loads
-__device__ __forceinline__ void tab_sm(const TabEntry<float>* t, int e, float (&s)[4], float (&m)[4]) {
-    const float4* p = reinterpret_cast<const float4*>(t + e);
-    const float4 a = p[0], b = p[1];
-    s[0] = a.x; s[1] = a.y; s[2] = a.z; s[3] = a.w;
-    m[0] = b.x; m[1] = b.y; m[2] = b.z; m[3] = b.w;
-}
-__device__ __forceinline__ void tab_sm(const TabEntry<double>* t, int e, double (&s)[4], double (&m)[4]) {
-    const double2* p = reinterpret_cast<const double2*>(t + e);
-    const double2 a = p[0], b = p[1], c = p[2], d = p[3];
-    s[0] = a.x; s[1] = a.y; s[2] = b.x; s[3] = b.y;
-    m[0] = c.x; m[1] = c.y; m[2] = d.x; m[3] = d.y;
-}
-__device__ __forceinline__ void tab_bm(const TabEntry<float>* t, int e, float& b2, float& b3, float (&m)[4]) {
-    const float4* p = reinterpret_cast<const float4*>(t + e);
-    const float4 b = p[1], c = p[2];
-    m[0] = b.x; m[1] = b.y; m[2] = b.z; m[3] = b.w;
-    b2 = c.x; b3 = c.y;
-}
-__device__ __forceinline__ void tab_bm(const TabEntry<double>* t, int e, double& b2, double& b3, double (&m)[4]) {
-    const double2* p = reinterpret_cast<const double2*>(t + e);
-    const double2 c = p[2], d = p[3], x = p[4];
-    m[0] = c.x; m[1] = c.y; m[2] = d.x; m[3] = d.y;
-    b2 = x.x; b3 = x.y;
-}
-
-// per-point data of one output plane: table index, velocity and (residual /
-// Jacobi modes) the right-hand side
-template <typename R, int NR>
-struct Meta {
-    int idx[NR];
-    float c[NR];
-    typename V2<R>::T b[NR];
-};
-
-template <typename R, int NR>
-struct BoxPlane {
-    Cx<R> c[NR], f[NR], e[NR];
-};
-
-// the arrays of one work item (one right-hand side) as buffer resources
-template <typename R, int MODE>
-struct ItemBuf {
-    const typename V2<R>::T* u;
-    unsigned vbytes;          // N * sizeof(complex)
-    unsigned plane_b;         // plane * sizeof(complex)
-    unsigned plane;
-    Rsrc ry, rb, ri, rc;
-    __device__ __forceinline__ ItemBuf(const WaveArgs<R>& a, int rhs) {
-        const GridData<R>& g = a.g;
-        using V = typename V2<R>::T;
-        const int64_t ro = static_cast<int64_t>(rhs) * g.N;
-        vbytes = static_cast<unsigned>(g.N) * static_cast<unsigned>(sizeof(V));
-        plane = static_cast<unsigned>(g.plane);
-        plane_b = plane * static_cast<unsigned>(sizeof(V));
-        u = a.u + ro;
-        ry = rsrc(a.y + ro, vbytes);
-        rb = rsrc(MODE == MODE_APPLY ? a.y + ro : a.b + ro, vbytes);
-        ri = rsrc(g.idx, static_cast<unsigned>(g.N) * 2u);
-        rc = rsrc(g.c, static_cast<unsigned>(g.N) * 4u);
-    }
-    // plane q of u: offsets of the lanes' rows in ofs; zero outside the grid
-    template <int NK>
-    __device__ __forceinline__ void load_plane(int q, int nz, const unsigned (&ofs)[NK],
-                                               typename V2<R>::T (&L)[NK]) const {
-        if (MODE == MODE_JACOBI0) {   // the iterate is zero: nothing to read
-#pragma unroll
-            for (int k = 0; k < NK; ++k) L[k] = typename V2<R>::T{};
-            return;
-        }
-        const bool in = q >= 0 && q < nz;
-        const Rsrc r = rsrc(u, in ? vbytes : 0u);
-        const unsigned so = in ? static_cast<unsigned>(q) * plane_b : 0u;
-#pragma unroll
-        for (int k = 0; k < NK; ++k) bld(L[k], r, ofs[k], so);
-    }
-    // per-point data of plane q (0 <= q < nz); mo = element offsets of the rows
-    template <int NR, bool ROWC>
-    __device__ __forceinline__ void load_meta(int q, const unsigned (&mo)[NR], Meta<R, NR>& M) const {
-        const unsigned pe = static_cast<unsigned>(q) * plane;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (!ROWC) M.idx[r] = bld_u16(ri, mo[r] * 2u, pe * 2u);
-            M.c[r] = bld_f32(rc, mo[r] * 4u, pe * 4u);
-            if (MODE != MODE_APPLY)
-                bld(M.b[r], rb, mo[r] * static_cast<unsigned>(sizeof(typename V2<R>::T)), q * plane_b);
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// unstretched-box tile.  BLK = false: one wavefront per tile of RY rows, which
-// loads its RY + 2 rows per plane.  BLK = true: the block's 4 wavefronts take
-// 4 stacked tiles of RY rows; each loads its own RY rows (wavefront 0 also the
-// row below the block, wavefront 3 the row above) and passes them to the
-// others through a two-plane LDS ring, so each row is read from memory once
-// per block instead of once per tile that needs it (1 + 2/(4 RY) instead of
-// 1 + 2/RY loads per output row), at one barrier per plane.
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK>
-__device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
-                                         typename V2<R>::T* ring, int tile, int zc, int rhs, int wave, int lane) {
-    using V = typename V2<R>::T;
-    constexpr unsigned SV = sizeof(V);
-    constexpr int NL = BLK ? RY + 1 : RY + 2;   // rows this wavefront loads per plane
-    constexpr int KB = 4 * RY + 2;              // rows of a block plane in the ring
-    const GridData<R>& g = a.g;
-    const int tx = tile % a.ntx, ty = tile / a.ntx;
-    const int gx = a.px0 + tx * kWaveCols - 1 + lane;
-    const bool inx = gx >= 0 && gx < g.nx;
-    const bool outx = lane >= 1 && lane <= kWaveCols && gx < a.px0 + a.pw;
-    const int gxc = min(max(gx, 0), g.nx - 1);
-    const int yb = a.py0 + ty * (BLK ? 4 * RY : RY);   // first output row of the tile (block)
-    const int y0 = yb + (BLK ? wave * RY : 0);          // first output row of this wavefront
-    const int z0 = zc * a.zchunk;
-    const int z1 = min(z0 + a.zchunk, g.nz);
-    const int yend = a.py0 + a.ph;
-    unsigned lo[NL];          // byte offsets of the loaded rows (kOff outside the grid)
-    unsigned so[RY];          // byte offsets of the stored rows (kOff: no output)
-    unsigned mo[RY];          // element offsets of the output rows (clamped, always valid)
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        int yy;
-        bool use = true;
-        if (BLK) {   // own rows, then the block's halo row (wavefronts 0 and 3)
-            yy = k < RY ? y0 + k : (wave == 0 ? yb - 1 : yb + 4 * RY);
-            use = k < RY || wave == 0 || wave == 3;
-        } else {
-            yy = y0 - 1 + k;
-        }
-        lo[k] = (use && inx && yy >= 0 && yy < g.ny) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
-    }
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        const int yy = y0 + r;
-        so[r] = (outx && yy < yend) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
-        mo[r] = static_cast<unsigned>(min(yy, g.ny - 1) * g.nx + gxc);
-    }
-    const ItemBuf<R, MODE> B_(a, rhs);
-    const R sig = g.inv_h2;
-
-    auto output = [&](int zo, const Meta<R, RY>& M, const BoxPlane<R, RY>& A, const BoxPlane<R, RY>& B,
-                      const BoxPlane<R, RY>& C) __attribute__((always_inline)) {
-        const AxisNode<R> Z = zn[zo];
-        const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            R s[4], m[4];
-            if (ROWC) {
-                const EntryCoef<R> F = g.rowcoef[static_cast<int64_t>(zo) * g.plane + mo[r]];
-                s[0] = sig * F.s0; s[1] = sig * F.s1; s[2] = sig * F.s2; s[3] = sig * F.s3;
-                m[0] = F.m0; m[1] = F.m1; m[2] = F.m2; m[3] = F.m3;
-            } else {
-                tab_sm(tab, M.idx[r] - a.tab_lo, s, m);
-            }
-            const R cvr = static_cast<R>(M.c[r]);
-            const R kap = g.omega2 * rcp_of(cvr * cvr);
-            Cx<R> acc, diag;
-            if (Z.plain) {
-                const Cx<R> Fc = B.f[r] + A.c[r] + C.c[r];
-                const Cx<R> Ec = B.e[r] + A.f[r] + C.f[r];
-                const Cx<R> Co = A.e[r] + C.e[r];
-                if (SHIFTED) {
-                    const R kr = kap * g.shift_re, ks = kap * g.shift_im;
-                    const Cx<R> K0{s[0] + kr * m[0], ks * m[0]}, K1{s[1] + kr * m[1], ks * m[1]};
-                    const Cx<R> K2{s[2] + kr * m[2], ks * m[2]}, K3{s[3] + kr * m[3], ks * m[3]};
-                    acc = K0 * B.c[r];
-                    cmac(acc, K1, Fc);
-                    cmac(acc, K2, Ec);
-                    cmac(acc, K3, Co);
-                    diag = K0;
-                } else {
-                    const R A0 = s[0] + kap * m[0], A1 = s[1] + kap * m[1];
-                    const R A2 = s[2] + kap * m[2], A3 = s[3] + kap * m[3];
-                    acc = A0 * B.c[r];
-                    rmac(acc, A1, Fc);
-                    rmac(acc, A2, Ec);
-                    rmac(acc, A3, Co);
-                    diag = Cx<R>{A0, R(0)};
-                }
-            } else {
-                // z-stretched plane: the in-plane class sums of planes zo - 1,
-                // zo, zo + 1 with real weights, then the complex z factors
-                const R b2 = s[2] + R(2) * s[3];   // beta2 / h^2
-                const R x0 = R(4) * b2 - R(4) * sig, x1 = sig - R(2) * b2;
-                Cx<R> Sm = s[1] * A.c[r], Sp = s[1] * C.c[r], S0 = s[1] * B.c[r], SX = x0 * B.c[r];
-                rmac(Sm, s[2], A.f[r]); rmac(Sm, s[3], A.e[r]);
-                rmac(Sp, s[2], C.f[r]); rmac(Sp, s[3], C.e[r]);
-                rmac(S0, s[2], B.f[r]); rmac(S0, s[3], B.e[r]);
-                rmac(SX, x1, B.f[r]); rmac(SX, b2, B.e[r]);
-                Cx<R> Mm = m[1] * A.c[r], Mp = m[1] * C.c[r], MX = m[0] * B.c[r];
-                rmac(Mm, m[2], A.f[r]); rmac(Mm, m[3], A.e[r]);
-                rmac(Mp, m[2], C.f[r]); rmac(Mp, m[3], C.e[r]);
-                rmac(MX, m[1], B.f[r]); rmac(MX, m[2], B.e[r]);
-                const Cx<R> tm{Z.tm_re, Z.tm_im}, tp{Z.tp_re, Z.tp_im};
-                const Cx<R> t0 = -(tm + tp);
-                const Cx<R> xz{Z.xi_re, Z.xi_im};
-                const Cx<R> um2{R(2) * Z.um_re, R(2) * Z.um_im}, up2{R(2) * Z.up_re, R(2) * Z.up_im};
-                Cx<R> st = tm * Sm;
-                cmac(st, tp, Sp);
-                cmac(st, t0, S0);
-                cmac(st, xz, SX);
-                Cx<R> ms = um2 * Mm;
-                cmac(ms, up2, Mp);
-                cmac(ms, xz, MX);
-                if (SHIFTED) {
-                    const Cx<R> kc{kap * g.shift_re, kap * g.shift_im};
-                    acc = st;
-                    cmac(acc, kc, ms);
-                } else {
-                    acc = st;
-                    rmac(acc, kap, ms);
-                }
-                if (MODE == MODE_JACOBI || MODE == MODE_JACOBI0) {
-                    const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
-                    diag = s[1] * t0 + x0 * xz + m[0] * (kc * xz);
-                } else {
-                    diag = zero<R>();
-                }
-            }
-            V bb{};
-            if (MODE != MODE_APPLY) bb = M.b[r];
-            bst(finish<R, MODE>(a.omega_j, acc, diag, B.c[r], bb), B_.ry, so[r], pso);
-        }
-    };
-    // one z step: plane q enters, output plane q - 1 leaves.  Plane q + 2 and
-    // the per-point data of plane q + 1 are loaded two steps ahead of their
-    // use; past the chunk the last plane is loaded again, so every step issues
-    // the same loads and the waits stay exact.
-    auto step = [&](int q, bool out, const V (&Lc)[NL], V (&Ln)[NL], const BoxPlane<R, RY>& A,
-                    const BoxPlane<R, RY>& B, BoxPlane<R, RY>& C, const Meta<R, RY>& Mc, Meta<R, RY>& Mn)
-                    __attribute__((always_inline)) {
-        B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
-        B_.template load_meta<RY, ROWC>(min(q + 1, z1 - 1), mo, Mn);
-        Cx<R> U[RY + 2];
-        if constexpr (BLK) {
-            // ring[slot][row of the block plane][lane]; slot alternates with q
-            V* pl = ring + ((q & 1) * KB) * 64;
-#pragma unroll
-            for (int k = 0; k < RY; ++k) pl[(1 + wave * RY + k) * 64 + lane] = Lc[k];
-            if (wave == 0) pl[lane] = Lc[RY];
-            if (wave == 3) pl[(KB - 1) * 64 + lane] = Lc[RY];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) {
-                const V v = pl[(wave * RY + k) * 64 + lane];
-                U[k] = Cx<R>{v.x, v.y};
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
-        }
-        Cx<R> sx[RY + 2];
-#pragma unroll
-        for (int k = 0; k < RY + 2; ++k) sx[k] = nxt_g<64>(U[k]) + prv_g<64>(U[k]);
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            C.c[r] = U[r + 1];
-            C.f[r] = sx[r + 1] + U[r] + U[r + 2];
-            C.e[r] = sx[r] + sx[r + 2];
-        }
-        if (out) output(q - 1, Mc, A, B, C);
-    };
-
-    // slot k % 3 (k = q - z0 + 1) holds the loads, the plane sums and the
-    // per-point data of plane q
-    V L0[NL], L1[NL], L2[NL];
-    BoxPlane<R, RY> P0, P1, P2;
-    Meta<R, RY> M0, M1, M2;
-    if (BLK) __syncthreads();   // the previous item's last ring reads are done
-    B_.load_plane(z0 - 1, g.nz, lo, L0);
-    B_.load_plane(z0, g.nz, lo, L1);
-    // planes z0 - 1 and z0 enter without an output; then one output per step
-    step(z0 - 1, false, L0, L2, P1, P2, P0, M2, M1);
-    step(z0, false, L1, L0, P2, P0, P1, M0, M2);
-    int q = z0 + 1;
-    for (;;) {
-        step(q, true, L2, L1, P0, P1, P2, M1, M0);
-        if (++q > z1) break;
-        step(q, true, L0, L2, P1, P2, P0, M2, M1);
-        if (++q > z1) break;
-        step(q, true, L1, L0, P2, P0, P1, M0, M2);
-        if (++q > z1) break;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// PML-frame tile: lanes along x in groups of LW (LW - 2 output columns each,
-// halo at both ends), 64 / LW groups stacked along y, RQ rows per lane.  The
-// 16-lane groups serve the left / right strips, whose rows are unstretched.
-template <typename R>
-struct Factors {
-    Cx<R> tm, tp, t0, xi, um, up;
-};
-template <typename R>
-__device__ __forceinline__ Factors<R> factors(const AxisNode<R>& n) {
-    Factors<R> f;
-    f.tm = Cx<R>{n.tm_re, n.tm_im};
-    f.tp = Cx<R>{n.tp_re, n.tp_im};
-    f.t0 = -(f.tm + f.tp);
-    f.xi = Cx<R>{n.xi_re, n.xi_im};
-    f.um = Cx<R>{n.um_re, n.um_im};
-    f.up = Cx<R>{n.up_re, n.up_im};
-    return f;
-}
-
-template <typename R, int NR>
-struct FramePlane {
-    Cx<R> a[NR], b[NR], c[NR], d[NR], e[NR], u[NR];
-};
-
-template <typename R, int MODE, bool SHIFTED, int RQ, int LW, bool ROWC>
-__device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
-                                           int fr, int ft, int zc, int rhs, int lane) {
-    using V = typename V2<R>::T;
-    constexpr unsigned SV = sizeof(V);
-    constexpr bool QPLAIN = LW == 16;   // left / right strips: rows unstretched
-    const GridData<R>& g = a.g;
-    constexpr int NG = 64 / LW;
-    const int lx = lane % LW, ly = lane / LW;
-    const int tl = ft % a.fnl[fr], tq = ft / a.fnl[fr];
-    const int x_org = a.fx0[fr], x_ext = a.fw[fr];
-    const int y_org = a.fy0[fr], y_ext = a.fh[fr];
-    const int lc = x_org + tl * (LW - 2) - 1 + lx;
-    const bool outl = lx >= 1 && lx <= LW - 2 && lc < x_org + x_ext;
-    const bool inl = lc >= 0 && lc < g.nx;
-    const int lcc = min(max(lc, 0), g.nx - 1);
-    const int q0 = y_org + (tq * NG + ly) * RQ;
-    const int z0 = zc * a.zchunk;
-    const int z1 = min(z0 + a.zchunk, g.nz);
-    const Factors<R> FL = factors<R>(g.ax[lcc]);
-    Factors<R> FQ[RQ];
-    Cx<R> xLQ[RQ];
-    unsigned lo[RQ + 2], so[RQ], mo[RQ];
-#pragma unroll
-    for (int k = 0; k < RQ + 2; ++k) {
-        const int qq = q0 - 1 + k;
-        lo[k] = (inl && qq >= 0 && qq < g.ny) ? static_cast<unsigned>(qq * g.nx + lc) * SV : kOff;
-    }
-#pragma unroll
-    for (int r = 0; r < RQ; ++r) {
-        const int qq = q0 + r;
-        FQ[r] = factors<R>(g.ay[min(qq, g.ny - 1)]);
-        xLQ[r] = QPLAIN ? FL.xi : FL.xi * FQ[r].xi;
-        so[r] = (outl && qq < y_org + y_ext) ? static_cast<unsigned>(qq * g.nx + lc) * SV : kOff;
-        mo[r] = static_cast<unsigned>(min(qq, g.ny - 1) * g.nx + lcc);
-    }
-    const ItemBuf<R, MODE> B_(a, rhs);
-    const R sig = g.inv_h2;
-
-    auto output = [&](int zo, const Meta<R, RQ>& M, const FramePlane<R, RQ>& A, const FramePlane<R, RQ>& B,
-                      const FramePlane<R, RQ>& C) __attribute__((always_inline)) {
-        const AxisNode<R> Z = zn[zo];
-        const bool plainz = Z.plain != 0;
-        const Factors<R> FZ = factors<R>(Z);
-        const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) {
-            R b2, b3, m[4];
-            if (ROWC) {
-                const EntryCoef<R> E = g.rowcoef[static_cast<int64_t>(zo) * g.plane + mo[r]];
-                b2 = E.beta2; b3 = E.beta3; m[0] = E.m0; m[1] = E.m1; m[2] = E.m2; m[3] = E.m3;
-            } else {
-                tab_bm(tab, M.idx[r] - a.tab_lo, b2, b3, m);
-            }
-            const R cvr = static_cast<R>(M.c[r]);
-            const R kap = g.omega2 * rcp_of(cvr * cvr);
-            Cx<R> PTA = A.a[r], PTB = B.a[r], PTC = C.a[r];
-            rmac(PTA, b2, A.b[r]); rmac(PTA, b3, A.c[r]);
-            rmac(PTB, b2, B.b[r]); rmac(PTB, b3, B.c[r]);
-            rmac(PTC, b2, C.b[r]); rmac(PTC, b3, C.c[r]);
-            const R w1 = R(2) * m[1], w2 = R(4) * m[2], w3 = R(8) * m[3];
-            Cx<R> PUA = w1 * A.a[r], PUC = w1 * C.a[r];
-            rmac(PUA, w2, A.d[r]); rmac(PUA, w3, A.e[r]);
-            rmac(PUC, w2, C.d[r]); rmac(PUC, w3, C.e[r]);
-            Cx<R> PXs = B.b[r];
-            rmac(PXs, b2, B.c[r]);
-            Cx<R> PXm = m[0] * B.a[r];
-            rmac(PXm, w1, B.d[r]); rmac(PXm, w2, B.e[r]);
-            Cx<R> stiff, mass;
-            if (plainz) {   // T_z = (1, -2, 1), X_z = 1, U_z = (1/2, 0, 1/2)
-                stiff = PTA + PTC + PXs - R(2) * PTB;
-                mass = PXm + R(0.5) * (PUA + PUC);
-            } else {
-                stiff = FZ.tm * PTA;
-                cmac(stiff, FZ.t0, PTB);
-                cmac(stiff, FZ.tp, PTC);
-                cmac(stiff, FZ.xi, PXs);
-                mass = FZ.um * PUA;
-                cmac(mass, FZ.up, PUC);
-                cmac(mass, FZ.xi, PXm);
-            }
-            Cx<R> acc = sig * stiff;
-            if (SHIFTED) {
-                cmac(acc, Cx<R>{kap * g.shift_re, kap * g.shift_im}, mass);
-            } else {
-                rmac(acc, kap, mass);
-            }
-            Cx<R> diag = zero<R>();
-            if (MODE == MODE_JACOBI || MODE == MODE_JACOBI0) {
-                const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
-                const Factors<R>& Q = FQ[r];
-                const Cx<R> ac = xLQ[r];
-                const Cx<R> bc = QPLAIN ? FL.t0 + R(-2) * FL.xi : FL.t0 * Q.xi + FL.xi * Q.t0;
-                const Cx<R> cc = QPLAIN ? R(-2) * FL.t0 : FL.t0 * Q.t0;
-                Cx<R> pc = ac;
-                rmac(pc, b2, bc);
-                rmac(pc, b3, cc);
-                Cx<R> pxs = bc;
-                rmac(pxs, b2, cc);
-                diag = sig * (FZ.t0 * pc + FZ.xi * pxs) + (m[0] * kc) * (FZ.xi * ac);
-            }
-            V bb{};
-            if (MODE != MODE_APPLY) bb = M.b[r];
-            bst(finish<R, MODE>(a.omega_j, acc, diag, B.u[r], bb), B_.ry, so[r], pso);
-        }
-    };
-    auto step = [&](int q, bool out, const V (&Lc)[RQ + 2], V (&Ln)[RQ + 2], const FramePlane<R, RQ>& A,
-                    const FramePlane<R, RQ>& B, FramePlane<R, RQ>& C, const Meta<R, RQ>& Mc, Meta<R, RQ>& Mn)
-                    __attribute__((always_inline)) {
-        B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
-        B_.template load_meta<RQ, ROWC>(min(q + 1, z1 - 1), mo, Mn);
-        Cx<R> U[RQ + 2];
-#pragma unroll
-        for (int k = 0; k < RQ + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
-        Cx<R> RT[RQ + 2], RU[RQ + 2];
-#pragma unroll
-        for (int k = 0; k < RQ + 2; ++k) {
-            const Cx<R> vm = prv_g<LW>(U[k]), vp = nxt_g<LW>(U[k]);
-            RT[k] = FL.tm * vm + FL.t0 * U[k] + FL.tp * vp;
-            RU[k] = FL.um * vm + FL.up * vp;
-        }
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) {
-            C.u[r] = U[r + 1];
-            C.a[r] = xLQ[r] * U[r + 1];
-            if (QPLAIN) {   // row factors T = (1, -2, 1), X = 1, U = (1/2, 0, 1/2)
-                const Cx<R> ys = U[r] + U[r + 2];
-                C.b[r] = RT[r + 1] + FL.xi * (ys - R(2) * U[r + 1]);
-                C.c[r] = RT[r] + RT[r + 2] - R(2) * RT[r + 1];
-                C.d[r] = RU[r + 1] + R(0.5) * (FL.xi * ys);
-                C.e[r] = R(0.5) * (RU[r] + RU[r + 2]);
-            } else {
-                const Factors<R>& Q = FQ[r];
-                C.b[r] = Q.xi * RT[r + 1] + FL.xi * (Q.tm * U[r] + Q.t0 * U[r + 1] + Q.tp * U[r + 2]);
-                C.c[r] = Q.tm * RT[r] + Q.t0 * RT[r + 1] + Q.tp * RT[r + 2];
-                C.d[r] = Q.xi * RU[r + 1] + FL.xi * (Q.um * U[r] + Q.up * U[r + 2]);
-                C.e[r] = Q.um * RU[r] + Q.up * RU[r + 2];
-            }
-        }
-        if (out) output(q - 1, Mc, A, B, C);
-    };
-
-    // slot k % 3 (k = q - z0 + 1) holds the loads, the plane sums and the
-    // per-point data of plane q
-    V L0[RQ + 2], L1[RQ + 2], L2[RQ + 2];
-    FramePlane<R, RQ> P0, P1, P2;
-    Meta<R, RQ> M0, M1, M2;
-    B_.load_plane(z0 - 1, g.nz, lo, L0);
-    B_.load_plane(z0, g.nz, lo, L1);
-    step(z0 - 1, false, L0, L2, P1, P2, P0, M2, M1);
-    step(z0, false, L1, L0, P2, P0, P1, M0, M2);
-    int q = z0 + 1;
-    for (;;) {
-        step(q, true, L2, L1, P0, P1, P2, M1, M0);
-        if (++q > z1) break;
-        step(q, true, L0, L2, P1, P2, P0, M2, M1);
-        if (++q > z1) break;
-        step(q, true, L1, L0, P2, P0, P1, M0, M2);
-        if (++q > z1) break;
-    }
-}
-
-// register budget: 4 waves per SIMD (128 VGPRs) for FP32, 2 for FP64
-template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
-void wave27_kernel(WaveArgs<R> a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const GridData<R>& g = a.g;
-    const int n_tab = ROWC ? 0 : a.n_tab;
-    TabEntry<R>* tab = reinterpret_cast<TabEntry<R>*>(smem_raw);
-    AxisNode<R>* zn = reinterpret_cast<AxisNode<R>*>(smem_raw + static_cast<size_t>(n_tab) * sizeof(TabEntry<R>));
-    const R sig = g.inv_h2;
-    for (int t = threadIdx.x; t < n_tab; t += kBlock) {
-        const EntryCoef<R> E = g.entry[g.fixed ? 0 : a.tab_lo + t];   // fixed weights: one entry everywhere
-        TabEntry<R> e;
-        e.s[0] = sig * E.s0; e.s[1] = sig * E.s1; e.s[2] = sig * E.s2; e.s[3] = sig * E.s3;
-        e.m[0] = E.m0; e.m[1] = E.m1; e.m[2] = E.m2; e.m[3] = E.m3;
-        e.b2 = E.s2 + R(2) * E.s3;
-        e.b3 = E.s3;
-        e.pad0 = e.pad1 = R(0);
-        tab[t] = e;
-    }
-    for (int t = threadIdx.x; t < g.nz; t += kBlock) zn[t] = g.az[t];
-    // row ring after the table slice and the z nodes, 16-byte aligned (as wave_ring_offset)
-    const size_t ring_off = (static_cast<size_t>(n_tab) * sizeof(TabEntry<R>) +
-                             static_cast<size_t>(g.nz) * sizeof(AxisNode<R>) + 15) & ~static_cast<size_t>(15);
-    typename V2<R>::T* ring = reinterpret_cast<typename V2<R>::T*>(smem_raw + ring_off);
-    __syncthreads();
-    // XCD-contiguous block order: block b runs on XCD b % 8; the grid is at
-    // most one resident wave per slot and each wave strides over the items
-    const int nb = static_cast<int>(gridDim.x);
-    const int bx = static_cast<int>(blockIdx.x);
-    const int xcd = bx & 7, q8 = nb >> 3, r8 = nb & 7;
-    const int lb = xcd * q8 + min(xcd, r8) + (bx >> 3);
-    const int wave = uni(static_cast<int>(threadIdx.x) >> 6);
-    const int lane = static_cast<int>(threadIdx.x) & 63;
-    if (!BLK) {
-        const int ntile = a.n_frame + a.n_plain;
-        for (int item = lb * (kBlock / 64) + wave; item < a.n_items; item += nb * (kBlock / 64)) {
-            // item order: right-hand side fastest, then tile, then z chunk
-            const int rhs = item % a.nrhs;
-            const int t = item / a.nrhs;
-            const int tile = t % ntile;
-            const int zc = t / ntile;
-            if (tile < a.n_frame) {
-                int k = 0;
-                while (k < 3 && tile >= a.fstart[k + 1]) ++k;
-                if (a.flx[k])
-                    frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
-                else
-                    frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
-            } else {
-                box_item<R, MODE, SHIFTED, RY, ROWC, false>(a, tab, zn, ring, tile - a.n_frame, zc, rhs, wave,
-                                                            lane);
-            }
-        }
-    } else {
-        // block items: 4 frame tiles (one per wavefront) or one box block
-        // tile (4 stacked tiles sharing rows through the LDS ring)
-        const int nfb = (a.n_frame + 3) / 4;
-        const int nbt = nfb + a.n_plain;   // n_plain counts box block tiles here
-        for (int bi = lb; bi < a.n_items; bi += nb) {
-            const int rhs = bi % a.nrhs;
-            const int t = bi / a.nrhs;
-            const int bt = t % nbt;
-            const int zc = t / nbt;
-            if (bt < nfb) {
-                const int tile = bt * 4 + wave;
-                if (tile < a.n_frame) {
-                    int k = 0;
-                    while (k < 3 && tile >= a.fstart[k + 1]) ++k;
-                    if (a.flx[k])
-                        frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
-                    else
-                        frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
-                }
-            } else {
-                box_item<R, MODE, SHIFTED, RY, ROWC, true>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
-            }
-        }
-    }
-}
-
-template <typename R> struct FrameRows;
-template <> struct FrameRows<float> { static constexpr int value = 1; };
-template <> struct FrameRows<double> { static constexpr int value = 1; };
-
-// blocks of one kernel that fit on the device at once (cached per kernel and
-// LDS size; queried on the current device)
-static int resident_blocks(const void* fn, size_t lds) {
-    struct Entry { const void* fn; size_t lds; int dev; int blocks; };
-    static thread_local Entry cache[64] = {};
-    static thread_local int next = 0;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    for (const Entry& e : cache)
-        if (e.fn == fn && e.lds == lds && e.dev == dev) return e.blocks;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    const int blocks = per_cu * cus;
-    cache[next] = Entry{fn, lds, dev, blocks};
-    next = (next + 1) % 64;
-    return blocks;
-}
-
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK>
-static int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
-    constexpr int RQ = FrameRows<R>::value;
-    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK>);
-    const int n_tab = ROWC ? 0 : a.n_tab;
-    const size_t lds = wave_ring_offset(n_tab, a.g.nz, sizeof(R) == 8) +
-                       (BLK ? static_cast<size_t>(2 * (4 * RY + 2) * 64) * sizeof(typename V2<R>::T) : 0);
-    int blocks = BLK ? a.n_items : (a.n_items + (kBlock / 64) - 1) / (kBlock / 64);
-    const int cap = resident_blocks(fn, lds);
-    if (cap <= 0) return HELM27_EDEVICE;
-    if (blocks > cap) blocks = cap;
-    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK>, dim3(blocks), dim3(kBlock), lds, s, a));
-    return HELM27_OK;
-}
-
-template <typename R, int MODE, bool SHIFTED, int RY>
-static int launch_wave_ry(const WaveArgs<R>& a, hipStream_t s) {
-    if (a.blk)
-        return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true, true>(a, s)
-                           : launch_wave_k<R, MODE, SHIFTED, RY, false, true>(a, s);
-    return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true, false>(a, s)
-                       : launch_wave_k<R, MODE, SHIFTED, RY, false, false>(a, s);
-}
-
-template <typename R, int MODE, bool SHIFTED>
-static int launch_wave_mode(const WaveArgs<R>& a, int ry, hipStream_t s) {
-    switch (ry) {
-        case 1: return launch_wave_ry<R, MODE, SHIFTED, 1>(a, s);
-        case 2: return launch_wave_ry<R, MODE, SHIFTED, 2>(a, s);
-        case 3: return launch_wave_ry<R, MODE, SHIFTED, 3>(a, s);
-        case 4: return launch_wave_ry<R, MODE, SHIFTED, 4>(a, s);
-        default: return HELM27_EINVAL;
-    }
-}
 
 template <typename R>
 int launch_wave(const WaveArgs<R>& a, int mode, bool shifted, int ry, int rq, hipStream_t s) {
     (void)rq;
     if (a.n_items <= 0) return HELM27_OK;
     switch (mode) {
-        case MODE_APPLY:
-            return shifted ? launch_wave_mode<R, MODE_APPLY, true>(a, ry, s)
-                           : launch_wave_mode<R, MODE_APPLY, false>(a, ry, s);
-        case MODE_RESID:
-            return shifted ? launch_wave_mode<R, MODE_RESID, true>(a, ry, s)
-                           : launch_wave_mode<R, MODE_RESID, false>(a, ry, s);
-        case MODE_JACOBI:
-            return shifted ? launch_wave_mode<R, MODE_JACOBI, true>(a, ry, s)
-                           : launch_wave_mode<R, MODE_JACOBI, false>(a, ry, s);
-        case MODE_JACOBI0:
-            return shifted ? launch_wave_mode<R, MODE_JACOBI0, true>(a, ry, s)
-                           : launch_wave_mode<R, MODE_JACOBI0, false>(a, ry, s);
-        default:
-            return HELM27_EINVAL;
+        case MODE_APPLY: return launch_wave_m<R, MODE_APPLY>(a, shifted, ry, s);
+        case MODE_RESID: return launch_wave_m<R, MODE_RESID>(a, shifted, ry, s);
+        case MODE_JACOBI: return launch_wave_m<R, MODE_JACOBI>(a, shifted, ry, s);
+        case MODE_JACOBI0: return launch_wave_m<R, MODE_JACOBI0>(a, shifted, ry, s);
+        default: return HELM27_EINVAL;
     }
 }
 template int launch_wave<float>(const WaveArgs<float>&, int, bool, int, int, hipStream_t);
@@ -812,6 +28,11 @@ template int frame_rows<double>();
 // byte offset of the LDS row ring (after the table slice and the z nodes, 16-byte aligned)
 size_t wave_ring_offset(int n_tab, int nz, bool fp64) {
     return (wave_lds_bytes(n_tab, nz, fp64) + 15) & ~static_cast<size_t>(15);
+}
+
+size_t wave_ring_bytes(int ry, int nb, bool fp64) {
+    const size_t rows = nb > 1 ? static_cast<size_t>(nb) * 6 : static_cast<size_t>(4 * ry + 2);
+    return 2 * rows * 64 * (fp64 ? 16 : 8);
 }
 
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64) {

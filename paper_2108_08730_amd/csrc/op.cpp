@@ -492,13 +492,24 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
     const int slot = dtype == HELM27_C64 ? 0 : 1;
     float best = 1e30f;
     int best_ry = op->g.plain_ry[slot], best_zc = op->g.wave_zchunk, best_var = op->g.kernel_variant;
+    int best_nb = op->g.rhs_block, best_order = op->g.rhs_order;
     op->g.auto_tile = false;   // the tuner measures explicit shapes and keeps the fastest
     const int zchunks[5] = {0, 8, 16, 32, 64};   // 0 = automatic
     const int variants[2] = {0, 2};
+    // right-hand sides per box wavefront: 1, and for several FP32 right-hand
+    // sides 2 and 4 (block tiles, one row per wavefront)
+    const int nbs[3] = {1, 2, 4};
+    const int n_nb = (dtype == HELM27_C64 && nrhs >= 2) ? (nrhs >= 4 ? 3 : 2) : 1;
+    const int n_order = nrhs >= 2 ? 2 : 1;   // right-hand side slowest, then fastest
+    for (int oi = 0; oi < n_order && st == HELM27_OK; ++oi)
+    for (int ni = 0; ni < n_nb && st == HELM27_OK; ++ni)
     for (int vi = 0; vi < 2 && st == HELM27_OK; ++vi)
     for (int ry = 1; ry <= 4 && st == HELM27_OK; ++ry) {
+        if (ni > 0 && (vi == 0 || ry > 1)) continue;   // grouped right-hand sides: variant 2, one row
         for (int zi = 0; zi < 5 && st == HELM27_OK; ++zi) {
             if (zchunks[zi] > op->g.nz) continue;
+            op->g.rhs_block = nbs[ni];
+            op->g.rhs_order = oi == 0 ? 2 : 1;
             op->g.kernel_variant = variants[vi];
             op->g.plain_ry[slot] = ry;
             op->g.wave_zchunk = zchunks[zi];
@@ -518,12 +529,16 @@ extern "C" int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int
                 best_ry = ry;
                 best_zc = zchunks[zi];
                 best_var = variants[vi];
+                best_nb = nbs[ni];
+                best_order = oi == 0 ? 2 : 1;
             }
         }
     }
     op->g.plain_ry[slot] = best_ry;
     op->g.wave_zchunk = best_zc;
     op->g.kernel_variant = best_var;
+    op->g.rhs_block = n_nb > 1 ? best_nb : op->g.rhs_block;
+    op->g.rhs_order = n_order > 1 ? best_order : op->g.rhs_order;
     if (best_rows) *best_rows = best_ry;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -536,6 +551,18 @@ extern "C" int helm27_set_kernel_variant(helm27_op* op, int variant) {
     if (!op || variant < 0 || variant > 2) return HELM27_EINVAL;
     op->g.kernel_variant = variant;
     op->g.auto_tile = false;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_set_rhs_block(helm27_op* op, int nb) {
+    if (!op || !(nb == 0 || nb == 1 || nb == 2 || nb == 4)) return HELM27_EINVAL;
+    op->g.rhs_block = nb;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_set_rhs_order(helm27_op* op, int order) {
+    if (!op || order < 0 || order > 2) return HELM27_EINVAL;
+    op->g.rhs_order = order;
     return HELM27_OK;
 }
 

@@ -66,6 +66,9 @@ struct WaveArgs {
     int fstart[5], n_frame;        // prefix sums of frame tiles
     int nzc, zchunk, nrhs, n_items;
     int blk;                       // 1: box tiles in block items of 4 stacked tiles (LDS row ring)
+    int nb;                        // right-hand sides per box wavefront (1; 2 or 4 with block tiles, one row)
+    int ngrp;                      // right-hand-side groups per tile in the item order (nrhs / nb rounded up)
+    int rhs_outer;                 // 1: items ordered tile, z chunk, then right-hand-side group
     int tab_lo, n_tab;             // table slice [tab_lo, tab_lo + n_tab)
     const typename V2<R>::T* u;
     typename V2<R>::T* y;
@@ -86,5 +89,8 @@ int frame_rows();
 // entries; 0 with per-row coefficients) and the z-axis PML nodes
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64);
 size_t wave_ring_offset(int n_tab, int nz, bool fp64);
+// LDS bytes of the block kernel's row ring: two planes of 4 ry + 2 rows per
+// right-hand side of a wavefront (nb: 2 or 4 take one row, 6 rows each)
+size_t wave_ring_bytes(int ry, int nb, bool fp64);
 
 }  // namespace h27
