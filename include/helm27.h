@@ -161,6 +161,33 @@ int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const float* vel,
 int helm27_op_info(const helm27_op* op, helm27_op_desc* out);
 void helm27_op_destroy(helm27_op* op);
 
+/* Table index of every point with no allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It computes what helm27_assemble stores
+ * per point -- idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, N_G - 1),
+ * binary64, no contraction, bit-identical to helm27_assemble's index -- for
+ * `n` velocities `vel` (device pointer on ctx's device, float32) into `idx`
+ * (device pointer on ctx's device, uint16 [n], caller-owned), enqueued on
+ * `stream` (NULL = null stream).  Its kernels keep their partial counts in a
+ * file-scope device array of the library (131 KB per device, 4096 records of
+ * 65536 points), so n is limited to 268,435,456 points (EINVAL beyond).
+ * Calls that overlap on one device (any streams, any threads) share that
+ * array and race: serialise them.  With `stats` non-NULL the call waits for
+ * the stream and fills it (clamped points, invalid velocities -- zero,
+ * negative, infinite or NaN -- and the model's G range) and returns EINVAL if
+ * any velocity is invalid; with stats NULL it returns right after enqueueing
+ * and does not validate.  Errors: EINVAL (null or non-device pointer, n out
+ * of range, h or freq not positive, invalid velocities), EDEVICE. */
+typedef struct {
+    int64_t n_clamped;      /* points whose G fell outside the table (clamped) */
+    int64_t n_invalid;      /* velocities that are not finite and positive */
+    double  g_min_model;    /* smallest / largest G = c/(f h) of the valid velocities */
+    double  g_max_model;
+} helm27_index_stats;
+int helm27_select_index_noalloc(helm27_ctx* ctx, const helm27_table* t, const float* vel, int64_t n,
+                                double h, double freq, uint16_t* idx, helm27_index_stats* stats,
+                                void* stream);
+
 /* Test hooks.  helm27_export_index copies the table index of every point to
  * host memory `idx` [N] (uint16).  helm27_export_csr writes the matrix in
  * CSR form to host memory: indptr [N+1], indices [nnz] (ascending columns,

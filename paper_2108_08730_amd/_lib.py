@@ -43,6 +43,11 @@ class SolveOpts(C.Structure):
                 ("reorth_always", C.c_int)]
 
 
+class IndexStats(C.Structure):
+    _fields_ = [("n_clamped", C.c_int64), ("n_invalid", C.c_int64), ("g_min_model", C.c_double),
+                ("g_max_model", C.c_double)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int), ("converged", C.c_int),
                 ("max_relres", C.c_double), ("seconds", C.c_double)]
@@ -88,6 +93,8 @@ def _load():
         "helm27_op_info": (C.c_int, [P, C.POINTER(OpDesc)]),
         "helm27_op_destroy": (None, [P]),
         "helm27_export_index": (C.c_int, [P, C.c_void_p]),
+        "helm27_select_index_noalloc": (C.c_int, [P, P, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                                  C.c_void_p, C.POINTER(IndexStats), C.c_void_p]),
         "helm27_export_csr": (C.c_int, [P, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p]),
         "helm27_apply": (C.c_int, [P, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
         "helm27_set_tuning": (C.c_int, [P, C.c_int, C.c_int]),

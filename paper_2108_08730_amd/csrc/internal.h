@@ -204,6 +204,9 @@ int host_index(float c, double fh, double gmin, double dg, int n_g);
 // kernels (kernels_*.hip): host-side launchers
 // d_counts: 4 entries, initialised by the caller to {0, 0, bits of +inf, 0}:
 // clamped points, invalid velocities, min / max bit pattern of the valid ones
+// look up this device's scratch array of the no-allocation index selection
+// (the device must be current)
+int noalloc_init(int device);
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
                         int n_g, unsigned long long* d_counts, hipStream_t s);
 // y = A u (MODE_APPLY), y = b - A u (MODE_RESID), y = u + omega_j D^-1 (b - A u)

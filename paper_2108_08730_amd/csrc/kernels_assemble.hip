@@ -5,6 +5,9 @@
 // same binary64 result as the same formula evaluated anywhere else.
 #include "stencil.h"
 
+#include <cmath>
+#include <cstring>
+
 namespace h27 {
 
 // idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, n_g - 1)   (paper Sec. 3.1:
@@ -13,6 +16,34 @@ namespace h27 {
 // counts[2] / counts[3] = min / max bit pattern of the valid velocities (the
 // bits of positive floats order like the values; the caller initialises them
 // to +inf and 0).
+// One point: its table index, and the running clamp / invalid counts and
+// velocity range of the calling thread.
+__device__ __forceinline__ uint16_t index_point(float cv, double fh, double gmin, double dg, int n_g,
+                                                unsigned long long& ncl, unsigned long long& nbad, float& vmin,
+                                                float& vmax) {
+    const double top = static_cast<double>(n_g - 1);
+    if (!(cv > 0.0f) || !isfinite(cv)) {
+        ++nbad;
+    } else {
+        vmin = fminf(vmin, cv);
+        vmax = fmaxf(vmax, cv);
+    }
+    const double G = static_cast<double>(cv) / fh;
+    const double t = (G - gmin) / dg;
+    const double raw = floor(t + 0.5);
+    int k;
+    if (!(raw >= 0.0)) {
+        k = 0;
+        ++ncl;
+    } else if (raw > top) {
+        k = n_g - 1;
+        ++ncl;
+    } else {
+        k = static_cast<int>(raw);
+    }
+    return static_cast<uint16_t>(k);
+}
+
 __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __restrict__ idx, int64_t N,
                                     double fh, double gmin, double dg, int n_g,
                                     unsigned long long* __restrict__ counts) {
@@ -20,31 +51,9 @@ __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __res
     __shared__ float rmm[2][kBlock / 64];
     unsigned long long ncl = 0, nbad = 0;
     float vmin = __builtin_inff(), vmax = 0.0f;
-    const double top = static_cast<double>(n_g - 1);
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const float cv = c[i];
-        if (!(cv > 0.0f) || !isfinite(cv)) {
-            ++nbad;
-        } else {
-            vmin = fminf(vmin, cv);
-            vmax = fmaxf(vmax, cv);
-        }
-        const double G = static_cast<double>(cv) / fh;
-        const double t = (G - gmin) / dg;
-        const double raw = floor(t + 0.5);
-        int k;
-        if (!(raw >= 0.0)) {
-            k = 0;
-            ++ncl;
-        } else if (raw > top) {
-            k = n_g - 1;
-            ++ncl;
-        } else {
-            k = static_cast<int>(raw);
-        }
-        idx[i] = static_cast<uint16_t>(k);
-    }
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        idx[i] = index_point(c[i], fh, gmin, dg, n_g, ncl, nbad, vmin, vmax);
     // wavefront reduction, then one atomic per block
     for (int off = 32; off > 0; off >>= 1) {
         ncl += __shfl_down(ncl, off, 64);
@@ -78,6 +87,109 @@ __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __res
         if (lo < __hip_atomic_load(counts + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(counts + 2, lo);
         if (hi > __hip_atomic_load(counts + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(counts + 3, hi);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Index selection that allocates nothing (helm27_select_index_noalloc): each
+// block of the first kernel handles a fixed range of kNaPerBlock points and
+// writes its counts and velocity range to its own record of a file-scope
+// device array; the second kernel reduces the records in a fixed order into
+// the last record.  Every record a launch reads was written by that launch,
+// so nothing needs clearing between calls.
+struct NaRecord {
+    unsigned long long ncl, nbad, minbits, maxbits;
+};
+constexpr int kNaBlocks = 4096;                  // partial records (blocks) at most
+constexpr int64_t kNaPerBlock = 65536;           // points per block
+constexpr int64_t kNaMaxPoints = kNaBlocks * kNaPerBlock;   // 268,435,456 points
+// kNaBlocks partial records + the reduced record: 131 KB per device
+static __device__ __align__(256) NaRecord scratch[kNaBlocks + 1];
+
+__device__ __forceinline__ void block_reduce_record(unsigned long long ncl, unsigned long long nbad, float vmin,
+                                                    float vmax, NaRecord* out) {
+    __shared__ unsigned long long red[2][kBlock / 64];
+    __shared__ float rmm[2][kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        ncl += __shfl_down(ncl, off, 64);
+        nbad += __shfl_down(nbad, off, 64);
+        vmin = fminf(vmin, __shfl_down(vmin, off, 64));
+        vmax = fmaxf(vmax, __shfl_down(vmax, off, 64));
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        red[0][w] = ncl;
+        red[1][w] = nbad;
+        rmm[0][w] = vmin;
+        rmm[1][w] = vmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        NaRecord r{0, 0, 0, 0};
+        float mn = __builtin_inff(), mx = 0.0f;
+        for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) {
+            r.ncl += red[0][k];
+            r.nbad += red[1][k];
+            mn = fminf(mn, rmm[0][k]);
+            mx = fmaxf(mx, rmm[1][k]);
+        }
+        r.minbits = __float_as_uint(mn);
+        r.maxbits = __float_as_uint(mx);
+        *out = r;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void select_index_blocks_kernel(const float* __restrict__ c,
+                                                                     uint16_t* __restrict__ idx, int64_t N, double fh,
+                                                                     double gmin, double dg, int n_g,
+                                                                     NaRecord* __restrict__ rec) {
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kNaPerBlock;
+    const int64_t i1 = i0 + kNaPerBlock < N ? i0 + kNaPerBlock : N;
+    unsigned long long ncl = 0, nbad = 0;
+    float vmin = __builtin_inff(), vmax = 0.0f;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock)
+        idx[i] = index_point(c[i], fh, gmin, dg, n_g, ncl, nbad, vmin, vmax);
+    block_reduce_record(ncl, nbad, vmin, vmax, rec + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void reduce_records_kernel(const NaRecord* __restrict__ rec, int nrec,
+                                                                NaRecord* __restrict__ out) {
+    unsigned long long ncl = 0, nbad = 0;
+    float vmin = __builtin_inff(), vmax = 0.0f;
+    for (int k = threadIdx.x; k < nrec; k += kBlock) {
+        const NaRecord r = rec[k];
+        ncl += r.ncl;
+        nbad += r.nbad;
+        vmin = fminf(vmin, __uint_as_float(static_cast<unsigned>(r.minbits)));
+        vmax = fmaxf(vmax, __uint_as_float(static_cast<unsigned>(r.maxbits)));
+    }
+    block_reduce_record(ncl, nbad, vmin, vmax, out);
+}
+
+// device address of this device's scratch array (looked up once per device,
+// with that device current)
+static int scratch_address(int device, NaRecord** out) {
+    static std::mutex mu;
+    static std::vector<NaRecord*> ptrs;
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0) return HELM27_EINVAL;
+    if (static_cast<size_t>(device) >= ptrs.size()) ptrs.resize(device + 1, nullptr);
+    if (!ptrs[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            std::fprintf(stderr, "helm27: hipGetSymbolAddress(scratch) failed on device %d: %s\n", device,
+                         hipGetErrorString(e));
+            return HELM27_EDEVICE;
+        }
+        ptrs[device] = static_cast<NaRecord*>(p);
+    }
+    *out = ptrs[device];
+    return HELM27_OK;
+}
+
+int noalloc_init(int device) {
+    NaRecord* p = nullptr;
+    return scratch_address(device, &p);
 }
 
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
@@ -294,3 +406,60 @@ template int launch_gam_average<float>(const GridOp&, EntryCoef<float>*, hipStre
 template int launch_gam_average<double>(const GridOp&, EntryCoef<double>*, hipStream_t);
 
 }  // namespace h27
+
+// a device pointer on `device` (host, managed-elsewhere or foreign pointers are refused)
+static bool device_pointer_on(const void* p, int device) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice && at.device == device;
+}
+
+extern "C" int helm27_select_index_noalloc(helm27_ctx* ctx, const helm27_table* t, const float* vel, int64_t n,
+                                           double h, double freq, uint16_t* idx, helm27_index_stats* stats,
+                                           void* stream) {
+    using namespace h27;
+    if (!ctx || !t || !vel || !idx || t->n_g < 1 || !(h > 0.0) || !(freq > 0.0) || !std::isfinite(h) ||
+        !std::isfinite(freq))
+        return HELM27_EINVAL;
+    if (n <= 0 || n > kNaMaxPoints) {
+        std::fprintf(stderr, "helm27_select_index_noalloc: %lld points; its scratch holds at most %lld\n",
+                     static_cast<long long>(n), static_cast<long long>(kNaMaxPoints));
+        return HELM27_EINVAL;
+    }
+    int prev = 0;
+    H27_CHECK_HIP(hipGetDevice(&prev));
+    if (prev != ctx->device) H27_CHECK_HIP(hipSetDevice(ctx->device));
+    auto done = [&](int st) {
+        if (prev != ctx->device) (void)hipSetDevice(prev);
+        return st;
+    };
+    if (!device_pointer_on(vel, ctx->device) || !device_pointer_on(idx, ctx->device)) return done(HELM27_EINVAL);
+    NaRecord* rec = nullptr;
+    int st = scratch_address(ctx->device, &rec);
+    if (st) return done(st);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nblocks = static_cast<int>((n + kNaPerBlock - 1) / kNaPerBlock);
+    const double fh = freq * h;
+    hipLaunchKernelGGL(select_index_blocks_kernel, dim3(nblocks), dim3(kBlock), 0, s, vel, idx, n, fh, t->g_min,
+                       t->dg, t->n_g, rec);
+    if (hipGetLastError() != hipSuccess) return done(HELM27_EDEVICE);
+    hipLaunchKernelGGL(reduce_records_kernel, dim3(1), dim3(kBlock), 0, s, rec, nblocks, rec + kNaBlocks);
+    if (hipGetLastError() != hipSuccess) return done(HELM27_EDEVICE);
+    if (!stats) return done(HELM27_OK);
+    NaRecord r{};
+    if (hipMemcpyAsync(&r, rec + kNaBlocks, sizeof(r), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return done(HELM27_EDEVICE);
+    float cmin = __builtin_inff(), cmax = 0.0f;
+    const unsigned lo = static_cast<unsigned>(r.minbits), hi = static_cast<unsigned>(r.maxbits);
+    std::memcpy(&cmin, &lo, sizeof(float));
+    std::memcpy(&cmax, &hi, sizeof(float));
+    stats->n_clamped = static_cast<int64_t>(r.ncl);
+    stats->n_invalid = static_cast<int64_t>(r.nbad);
+    stats->g_min_model = static_cast<double>(cmin) / fh;
+    stats->g_max_model = static_cast<double>(cmax) / fh;
+    return done(r.nbad ? HELM27_EINVAL : HELM27_OK);
+}

@@ -225,6 +225,12 @@ extern "C" int helm27_create(helm27_ctx** out, int device, size_t hbm_budget_byt
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget_bytes = static_cast<size_t>(0.9 * fr);
     }
     c->hbm_budget = hbm_budget_bytes;
+    // the no-allocation entry point's scratch array: its address on this device
+    const int st = h27::noalloc_init(device);
+    if (st) {
+        delete c;
+        return st;
+    }
     *out = c;
     return HELM27_OK;
 }
