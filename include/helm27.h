@@ -144,6 +144,9 @@ typedef struct {
     double   g_min_model;   /* smallest / largest G = c/(f h) of the model */
     double   g_max_model;
     size_t   device_bytes;  /* device memory held by the operator */
+    /* recompute-kernel shape (helm27_set_* / helm27_tune); auto_tile = 1 while
+     * every launch still chooses its own shape from its work size */
+    int      auto_tile, kernel_variant, rows_fp32, rows_fp64, zchunk, rhs_block, rhs_order;
 } helm27_op_desc;
 
 /* Build the operator for velocity `vel` (float32 [nz][ny][nx], host or device

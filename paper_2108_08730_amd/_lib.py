@@ -31,7 +31,9 @@ class OpDesc(C.Structure):
                 ("h", C.c_double), ("freq", C.c_double), ("omega", C.c_double),
                 ("n_g", C.c_int), ("n_clamped", C.c_int64),
                 ("g_min_model", C.c_double), ("g_max_model", C.c_double),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t),
+                ("auto_tile", C.c_int), ("kernel_variant", C.c_int), ("rows_fp32", C.c_int),
+                ("rows_fp64", C.c_int), ("zchunk", C.c_int), ("rhs_block", C.c_int), ("rhs_order", C.c_int)]
 
 
 class SolveOpts(C.Structure):

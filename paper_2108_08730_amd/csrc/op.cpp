@@ -400,6 +400,13 @@ extern "C" int helm27_op_info(const helm27_op* op, helm27_op_desc* o) {
     o->g_min_model = op->g_min_model;
     o->g_max_model = op->g_max_model;
     o->device_bytes = op->g.bytes;
+    o->auto_tile = op->g.auto_tile ? 1 : 0;
+    o->kernel_variant = op->g.kernel_variant;
+    o->rows_fp32 = op->g.plain_ry[0];
+    o->rows_fp64 = op->g.plain_ry[1];
+    o->zchunk = op->g.wave_zchunk;
+    o->rhs_block = op->g.rhs_block;
+    o->rhs_order = op->g.rhs_order;
     return HELM27_OK;
 }
 
