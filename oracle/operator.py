@@ -59,14 +59,17 @@ __all__ = [
 ]
 
 
-def select_index(c, f, h, gmin, dg, n_g):
+def select_index(c, f, h, gmin, dg, n_g, spacing="G"):
     """Table index of every grid point (Sec. 3.1: each row gets the weights of
-    its local wavelength).  ``c`` is widened to binary64 exactly; returns
-    (idx int64 array, number of clamped points)."""
+    its local wavelength): the nearest table abscissa, ties upward, clamped to
+    the table.  spacing "G": the abscissa is G = c/(f h); "invG": it is
+    s = 1/G = (f h)/c.  ``c`` is widened to binary64 exactly; every step is
+    one binary64 operation.  Returns (idx int64 array, number of clamped
+    points)."""
     c = np.asarray(c, dtype=np.float32).astype(np.float64)
     fh = np.float64(f) * np.float64(h)
-    G = c / fh
-    t = (G - np.float64(gmin)) / np.float64(dg)
+    v = c / fh if spacing == "G" else fh / c
+    t = (v - np.float64(gmin)) / np.float64(dg)
     raw = np.floor(t + 0.5)
     idx = np.clip(raw, 0, n_g - 1).astype(np.int64)
     n_clamped = int(np.count_nonzero((raw < 0) | (raw > n_g - 1)))

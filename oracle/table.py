@@ -28,6 +28,12 @@ Readings of points the paper leaves open:
 * Angle grid: theta and phi both take 0, 10, 20, 30, 40 degrees (the figure
   caption's 0-45 degrees by 10), 25 plane waves per G.
 * D is the first difference along G with free ends ((N_G-1) x N_G per weight).
+* Table axis: the configuration's G-uniform grid, or the paper's own axis
+  (figure caption of the dispersion curves: 1/G from 0 to 0.4 by 0.001),
+  uniform in s = 1/G.  On the 1/G axis the rows are written in s directly,
+  so s = 0 (G infinite) is a regular point where every row vanishes (any
+  consistent stencil is exact there) and only the smoothing term fixes the
+  weights.
 * The fixed-weight problems ("G4": N_G = 1) are rank deficient; their
   minimum-norm least-squares solution is used.
 """
@@ -41,7 +47,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "angle_grid", "abc", "complete_weights", "phase_velocity", "dispersion_rows",
-    "g_grid", "build_table", "fit_fixed", "table_normal_residual",
+    "g_grid", "build_table", "fit_fixed", "table_normal_residual", "dispersion_rows_inv",
 ]
 
 
@@ -119,6 +125,29 @@ def dispersion_rows(G, theta, phi):
     return H, g
 
 
+def dispersion_rows_inv(s, theta, phi):
+    """The same rows as ``dispersion_rows`` as functions of s = 1/G (the
+    paper's 1/G table axis, Sec. 2.2 figure caption): the phases are
+    2 pi s n_a and k2 = 2 pi^2 s^2, so s = 0 gives all-zero rows."""
+    s = np.asarray(s, dtype=np.float64)
+    ca = np.cos(2.0 * np.pi * np.cos(phi) * np.cos(theta) * s)
+    cb = np.cos(2.0 * np.pi * np.cos(phi) * np.sin(theta) * s)
+    cc = np.cos(2.0 * np.pi * np.sin(phi) * s)
+    A = ca * cb * cc
+    B = ca * cb + ca * cc + cb * cc
+    C = ca + cb + cc
+    k2 = 2.0 * np.pi ** 2 * s ** 2
+    H = np.stack([
+        0.5 * (3.0 + 3.0 * A - B - C),
+        0.5 * (1.0 + 3.0 * A - 5.0 * B / 3.0 + C / 3.0),
+        k2 * (A - 1.0),
+        k2 * (6.0 * A - 2.0 * C),
+        k2 * (12.0 * A - 4.0 * B),
+    ], axis=-1)
+    g = 0.5 * ((2.0 * k2 + 3.0) * A - B + C - 3.0)
+    return H, g
+
+
 def g_grid(gmin: float, gmax: float, dg: float) -> np.ndarray:
     """Tabulated G values G_i = gmin + i dg, i = 0 .. N_G - 1, with
     N_G = round((gmax - gmin) / dg) + 1 (each computed directly, not as a
@@ -127,12 +156,14 @@ def g_grid(gmin: float, gmax: float, dg: float) -> np.ndarray:
     return gmin + np.arange(n, dtype=np.float64) * dg
 
 
-def _stack_H(Gs, theta, phi):
+def _stack_H(Gs, theta, phi, spacing="G"):
     """Block-diagonal H (one block of len(theta) rows x 5 per G) and stacked g
-    (Sec. 2.2, the block-diagonal H of dimension (N_theta N_phi N_G) x (5 N_G))."""
+    (Sec. 2.2, the block-diagonal H of dimension (N_theta N_phi N_G) x (5 N_G));
+    with spacing "invG" the abscissae are s = 1/G."""
+    rows = dispersion_rows if spacing == "G" else dispersion_rows_inv
     blocks, gs = [], []
     for Gi in Gs:
-        H, g = dispersion_rows(Gi, theta, phi)
+        H, g = rows(Gi, theta, phi)
         blocks.append(H)
         gs.append(g)
     return sp.block_diag(blocks, format="csr"), np.concatenate(gs)
@@ -158,21 +189,25 @@ def _smoothing_operator(n_g: int, diff: str = "first"):
 
 
 def build_table(gmin=3.0, gmax=20.0, dg=0.05, lam=1e-3, theta=None, phi=None,
-                diff="first"):
+                diff="first", spacing="G"):
     """Adaptive weight table (Sec. 2.2, Tikhonov-regularised block problem):
 
         minimize ||H w - g||^2 + lambda ||D P w||^2
 
     solved as the stacked least-squares problem [H; sqrt(lambda) L] w = [g; 0]
-    with a dense LAPACK solver.  Returns (G grid [N_G], W [N_G, 5]) with the
-    columns (w_s1, w_s2, w_m0, w_m1, w_m2)."""
+    with a dense LAPACK solver.  spacing "G": abscissae G_i = gmin + i dg;
+    spacing "invG": abscissae s_i = gmin + i dg with s = 1/G (then gmin may be
+    0).  Returns (abscissae [N_G], W [N_G, 5]) with the columns
+    (w_s1, w_s2, w_m0, w_m1, w_m2)."""
     if theta is None:
         theta, phi = angle_grid()
     Gs = g_grid(gmin, gmax, dg)
     if lam == 0:
         # no coupling: every G is its own (rank-deficient) fit
+        if spacing != "G":
+            raise ValueError("lam = 0 needs the G axis")
         return Gs, np.stack([fit_fixed([G], theta, phi) for G in Gs])
-    H, g = _stack_H(Gs, theta, phi)
+    H, g = _stack_H(Gs, theta, phi, spacing)
     L = _smoothing_operator(len(Gs), diff)
     K = sp.vstack([H, np.sqrt(lam) * L]).toarray()
     rhs = np.concatenate([g, np.zeros(L.shape[0])])
@@ -180,12 +215,12 @@ def build_table(gmin=3.0, gmax=20.0, dg=0.05, lam=1e-3, theta=None, phi=None,
     return Gs, w.reshape(len(Gs), 5)
 
 
-def table_normal_residual(Gs, W, lam, theta=None, phi=None, diff="first"):
+def table_normal_residual(Gs, W, lam, theta=None, phi=None, diff="first", spacing="G"):
     """Relative residual of the normal equations (H^T H + lambda L^T L) w = H^T g
     for a given table: a property any minimiser of the Tikhonov problem has."""
     if theta is None:
         theta, phi = angle_grid()
-    H, g = _stack_H(Gs, theta, phi)
+    H, g = _stack_H(Gs, theta, phi, spacing)
     L = _smoothing_operator(len(Gs), diff)
     w = np.asarray(W, dtype=np.float64).reshape(-1)
     lhs = H.T @ (H @ w) + lam * (L.T @ (L @ w))

@@ -155,3 +155,74 @@ def test_g_grid_direct():
     Gs = T.g_grid(3.0, 20.0, 0.05)
     assert len(Gs) == 341
     assert Gs[140] == 3.0 + 140 * 0.05
+
+
+# ---- the paper's own table axis: uniform in s = 1/G (0 to 0.4 by 0.001) ----
+
+@pytest.fixture(scope="module")
+def table_inv():
+    S, W = T.build_table(0.0, 0.4, 0.001, 1e-3, spacing="invG")
+    return S, W
+
+
+def test_inverse_rows_match_phase_velocity_equation():
+    """Rows written in s = 1/G obey the same rearranged v~ = 1 equation:
+    sum_l H_l w_l - g = 2 pi^2 s^2 J (v~^2 - 1), with v~ and J evaluated from
+    the paper's phase-velocity formula at G = 1/s."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        s = rng.uniform(0.01, 0.45)
+        th = rng.uniform(0, np.pi / 2)
+        ph = rng.uniform(0, np.pi / 4)
+        w7 = T.complete_weights(rng.uniform(-0.5, 1.0, 5))
+        H, g = T.dispersion_rows_inv(s, th, ph)
+        A, B, C = T.abc(1.0 / s, th, ph)
+        J = w7[3] + 2 * w7[4] * C + 4 * w7[5] * B + 8 * w7[6] * A
+        if J <= 0:
+            continue
+        v = T.phase_velocity(1.0 / s, th, ph, w7)
+        lhs = float(H @ np.delete(w7, [2, 6]) - g)
+        rhs = 2 * np.pi ** 2 * s ** 2 * J * (v ** 2 - 1.0)
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+def test_inverse_rows_vanish_at_infinite_G():
+    """At s = 0 (G infinite) every stencil satisfying sum w_s = 1 and the mass
+    normalisation is exact, so every row and the right-hand side vanish."""
+    th, ph = T.angle_grid()
+    H, g = T.dispersion_rows_inv(np.zeros_like(th), th, ph)
+    assert np.all(H == 0.0) and np.all(g == 0.0)
+
+
+def test_inverse_table_paper_axis(table_inv):
+    """The Tikhonov table on the paper's axis 1/G in [0, 0.4] by 0.001 (401
+    entries): it satisfies the normal equations, the consistency constraints,
+    and keeps the phase-velocity error small over G >= 2.5 -- about as small
+    on G in [3, 20] as the G-axis table of the configuration."""
+    S, W = table_inv
+    assert len(S) == 401 and S[0] == 0.0 and abs(S[-1] - 0.4) < 1e-15
+    assert T.table_normal_residual(S, W, 1e-3, spacing="invG") <= 1e-12
+    w7 = T.complete_weights(W)
+    assert np.allclose(w7[:, :3].sum(axis=1), 1.0, atol=1e-14)
+    assert np.allclose(w7[:, 3] + 6 * w7[:, 4] + 12 * w7[:, 5] + 8 * w7[:, 6], 1.0, atol=1e-14)
+    th, ph = T.angle_grid()
+    err = [float(np.max(np.abs(T.phase_velocity(1.0 / s, th, ph, w) - 1.0))) for s, w in zip(S[1:], w7[1:])]
+    assert max(err) <= 2e-3
+    band = [e for s, e in zip(S[1:], err) if 1 / 20.0 - 1e-12 <= s <= 1 / 3.0 + 1e-12]
+    assert max(band) <= 5e-4
+
+
+def test_select_index_inverse_is_nearest_entry():
+    """Index on the 1/G axis: the nearest tabulated s = (f h)/c, ties upward,
+    clamped at both ends (brute force over the table entries)."""
+    from oracle import operator as O
+    rng = np.random.default_rng(3)
+    c = rng.uniform(300.0, 9000.0, 5000).astype(np.float32)
+    f, h, s0, ds, n = 7.5, 20.0, 0.0, 0.001, 401
+    idx, ncl = O.select_index(c, f, h, s0, ds, n, spacing="invG")
+    s_tab = s0 + np.arange(n) * ds
+    v = (f * h) / c.astype(np.float64)
+    d = np.abs(v[:, None] - s_tab[None, :])
+    best = n - 1 - np.argmin(d[:, ::-1], axis=1)   # ties go to the larger index
+    assert np.array_equal(idx, best)
+    assert ncl == int(np.count_nonzero(v > s_tab[-1] + ds / 2))
