@@ -70,6 +70,9 @@ extern "C" {
 #define HELM27_WEIGHTS_GAM    0x2   /* mean of the 27 stencil points' entries (Sec. 3.1 "GAm") */
 #define HELM27_STORE_C64      0x10  /* also keep 27 stored complex-float coefficients per point */
 #define HELM27_STORE_C128     0x20  /* also keep 27 stored complex-double coefficients per point */
+#define HELM27_EXTEND_TABLE   0x40  /* widen the table (same axis, step and fit settings) until no row
+                                       clamps; the solver's coarse multigrid levels then get tables
+                                       widened for their own G range (G / 2^l) as well */
 
 /* ---- opaque handles ----------------------------------------------------- */
 typedef struct helm27_ctx   helm27_ctx;
@@ -85,15 +88,24 @@ const char* helm27_strerror(int status);
 
 /* ---- (a0) weight table ---------------------------------------------------
  * Options of the dispersion fit (Sec. 2.2).  NULL selects the defaults:
- * theta and phi both on 0, 10, 20, 30, 40 degrees; first-difference smoother. */
+ * theta and phi both on 0, 10, 20, 30, 40 degrees; first-difference smoother;
+ * a G-uniform axis. */
+#define HELM27_SPACING_G     0   /* abscissae G_i = g_min + i dg */
+#define HELM27_SPACING_INVG  1   /* abscissae s_i = g_min + i dg with s = 1/G (the paper's
+                                    axis, figure caption of the dispersion curves:
+                                    1/G from 0 to 0.4 by 0.001) */
 typedef struct {
     int    n_angles;        /* angles per axis (default 5) */
     double angle_step_deg;  /* spacing (default 10) */
     int    diff_order;      /* 1 = first difference (default), 2 = second */
+    int    spacing;         /* HELM27_SPACING_G (default) or HELM27_SPACING_INVG */
 } helm27_table_opts;
 
 /* Build the adaptive table on the host in FP64 (Sec. 2.2): for
- * G_i = g_min + i dg (i = 0 .. round((g_max - g_min)/dg)), solve
+ * G_i = g_min + i dg (i = 0 .. round((g_max - g_min)/dg)) -- or, with
+ * HELM27_SPACING_INVG, for s_i = 1/G_i = g_min + i dg, where g_min, g_max and
+ * dg bound and step s and g_min may be 0 (G infinite; every dispersion row
+ * vanishes there and the smoothing term alone fixes the entry) -- solve
  *     min ||H w - g||^2 + lambda ||D P w||^2
  * over the five free weights of every G_i by banded Givens QR of the stacked
  * matrix [H; sqrt(lambda) D P] (unknowns in G-major order, so the stacked
@@ -102,16 +114,19 @@ typedef struct {
  * including its constant 1/2, as the elimination gives).
  * lambda = 0 decouples the G values; each is then solved for its minimum-norm
  * least-squares weights (one-sided Jacobi SVD), since alone it is rank deficient.
- * Errors: EINVAL (g_min <= 0, dg <= 0, g_max < g_min, lambda < 0, more than
- * 65535 entries), ENUMERIC, ENOMEM. */
+ * Errors: EINVAL (g_min <= 0 on the G axis or < 0 on the 1/G axis, dg <= 0,
+ * g_max < g_min, lambda < 0, lambda = 0 on the 1/G axis, more than 65535
+ * entries, bad options), ENUMERIC, ENOMEM. */
 int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, double dg, double lambda,
                        const helm27_table_opts* opts, helm27_table** out);
 
-/* A table from caller-given weights: `w5` is host memory [n_g][5] holding
+/* A table from caller-given weights on the axis `spacing` (abscissae
+ * g_min + i dg of G, or of s = 1/G): `w5` is host memory [n_g][5] holding
  * (w_s1, w_s2, w_m0, w_m1, w_m2) per entry, the rest following from
  * sum w_s = 1 and w_m0 + 6 w_m1 + 12 w_m2 + 8 w_m3 = 1.  n_g = 1 gives fixed
- * weights.  The data are copied.  Errors: EINVAL. */
-int helm27_table_from_weights(helm27_ctx* ctx, double g_min, double dg, int n_g,
+ * weights.  The data are copied.  Such a table cannot be widened by
+ * HELM27_EXTEND_TABLE (its fit settings are unknown).  Errors: EINVAL. */
+int helm27_table_from_weights(helm27_ctx* ctx, int spacing, double g_min, double dg, int n_g,
                               const double* w5, helm27_table** out);
 
 /* Non-adaptive weights (Sec. 2.2, joint misfit over several G with one weight
@@ -127,6 +142,9 @@ int helm27_fit_fixed(helm27_ctx* ctx, const double* g_list, int n_list, const he
  * (w_s1, w_s2, w_s3, w_m0, w_m1, w_m2, w_m3) per entry (per-point mass
  * weights); n_g, g_min, dg may be NULL.  Errors: EINVAL. */
 int helm27_table_weights(const helm27_table* t, double* w7, int* n_g, double* g_min, double* dg);
+/* The table's axis: spacing (HELM27_SPACING_*), first abscissa, step, entries
+ * (any pointer may be NULL).  Errors: EINVAL. */
+int helm27_table_axis(const helm27_table* t, int* spacing, double* v_min, double* dv, int* n_g);
 void helm27_table_destroy(helm27_table* t);
 
 /* ---- (a1) assembly ------------------------------------------------------- */
@@ -147,21 +165,36 @@ typedef struct {
     /* recompute-kernel shape (helm27_set_* / helm27_tune); auto_tile = 1 while
      * every launch still chooses its own shape from its work size */
     int      auto_tile, kernel_variant, rows_fp32, rows_fp64, zchunk, rhs_block, rhs_order;
+    /* the table the operator uses (the given one, or its widened copy under
+     * HELM27_EXTEND_TABLE): axis, first abscissa, step (n_g entries above) */
+    int      table_spacing;
+    double   table_min, table_step;
 } helm27_op_desc;
 
 /* Build the operator for velocity `vel` (float32 [nz][ny][nx], host or device
  * pointer, copied), grid step h (m), frequency freq (Hz), PML `pml` (NULL: 8
  * nodes, R = 1e-3) and `flags` (HELM27_WEIGHTS_*, HELM27_STORE_*).
  * Per point it stores the table index
- *     idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, N_G - 1)
- * (binary64, no contraction; bit-identical to the same formula on any IEEE
- * machine) and keeps the velocity; the coefficients are rebuilt from them by
- * the recompute kernels.  Errors: EINVAL (dims < 3, h or freq <= 0, npml too
- * large for the grid, non-positive velocity), ENOMEM, EDEVICE. */
+ *     idx = clamp(floor((v - v_min)/dv + 1/2), 0, N_G - 1),
+ *     v = c/(f h) on the G axis, v = (f h)/c on the 1/G axis
+ * (binary64, no contraction, f h formed first; bit-identical to the same
+ * formula on any IEEE machine) and keeps the velocity; the coefficients are
+ * rebuilt from them by the recompute kernels.  With HELM27_EXTEND_TABLE and
+ * rows outside the table, the operator builds its own wider table on the same
+ * axis grid (v_min - k dv .. v_max + k' dv, same lambda, angles, smoother;
+ * the first abscissa stays > 0 on the G axis and >= 0 on the 1/G axis) over
+ * the model's range, so no row clamps (helm27_op_info reports the axis,
+ * helm27_op_table_weights the weights).  Errors: EINVAL (dims < 3, h or
+ * freq <= 0, npml too large for the grid, non-positive velocity,
+ * HELM27_EXTEND_TABLE with a table not made by helm27_build_table), ERANGE
+ * (a widened table would need more than 65535 entries), ENOMEM, EDEVICE. */
 int helm27_assemble(helm27_ctx* ctx, const helm27_table* t, const float* vel,
                     int nx, int ny, int nz, double h, double freq,
                     const helm27_pml* pml, int flags, helm27_op** out);
 int helm27_op_info(const helm27_op* op, helm27_op_desc* out);
+/* Weights of the table the operator uses, host [n_g][7] (as
+ * helm27_table_weights).  Errors: EINVAL. */
+int helm27_op_table_weights(const helm27_op* op, double* w7);
 void helm27_op_destroy(helm27_op* op);
 
 /* Table index of every point with no allocation, for callers that cannot
@@ -298,6 +331,9 @@ typedef struct {
     int    converged;        /* 1 if every RHS reached tol */
     double max_relres;       /* max over RHS of the FP64 relative residual */
     double seconds;          /* wall time of the call */
+    int    mg_levels;        /* multigrid levels of the preconditioner (1: none coarse) */
+    int64_t coarse_clamped;  /* coarse-level rows whose G = c/(f 2^l h) fell outside their table */
+    int    coarse_tables;    /* coarse levels that use a table widened for their own G range */
 } helm27_solve_stats;
 
 /* Fill `opts` with the defaults above. */

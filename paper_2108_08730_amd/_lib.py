@@ -18,8 +18,13 @@ WEIGHTS_GA, WEIGHTS_FIXED, WEIGHTS_GAM = 0x0, 0x1, 0x2
 STORE_C64, STORE_C128 = 0x10, 0x20
 
 
+SPACING_G, SPACING_INVG = 0, 1
+EXTEND_TABLE = 0x40
+
+
 class TableOpts(C.Structure):
-    _fields_ = [("n_angles", C.c_int), ("angle_step_deg", C.c_double), ("diff_order", C.c_int)]
+    _fields_ = [("n_angles", C.c_int), ("angle_step_deg", C.c_double), ("diff_order", C.c_int),
+                ("spacing", C.c_int)]
 
 
 class Pml(C.Structure):
@@ -33,7 +38,8 @@ class OpDesc(C.Structure):
                 ("g_min_model", C.c_double), ("g_max_model", C.c_double),
                 ("device_bytes", C.c_size_t),
                 ("auto_tile", C.c_int), ("kernel_variant", C.c_int), ("rows_fp32", C.c_int),
-                ("rows_fp64", C.c_int), ("zchunk", C.c_int), ("rhs_block", C.c_int), ("rhs_order", C.c_int)]
+                ("rows_fp64", C.c_int), ("zchunk", C.c_int), ("rhs_block", C.c_int), ("rhs_order", C.c_int),
+                ("table_spacing", C.c_int), ("table_min", C.c_double), ("table_step", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -52,7 +58,8 @@ class IndexStats(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int), ("converged", C.c_int),
-                ("max_relres", C.c_double), ("seconds", C.c_double)]
+                ("max_relres", C.c_double), ("seconds", C.c_double), ("mg_levels", C.c_int),
+                ("coarse_clamped", C.c_int64), ("coarse_tables", C.c_int)]
 
 
 class ServeOpts(C.Structure):
@@ -84,8 +91,11 @@ def _load():
         "helm27_strerror": (C.c_char_p, [C.c_int]),
         "helm27_build_table": (C.c_int, [P, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.POINTER(TableOpts), C.POINTER(P)]),
-        "helm27_table_from_weights": (C.c_int, [P, C.c_double, C.c_double, C.c_int,
+        "helm27_table_from_weights": (C.c_int, [P, C.c_int, C.c_double, C.c_double, C.c_int,
                                                 C.POINTER(C.c_double), C.POINTER(P)]),
+        "helm27_table_axis": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int)]),
+        "helm27_op_table_weights": (C.c_int, [P, C.POINTER(C.c_double)]),
         "helm27_fit_fixed": (C.c_int, [P, C.POINTER(C.c_double), C.c_int, C.POINTER(TableOpts), C.POINTER(P)]),
         "helm27_table_weights": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),

@@ -29,6 +29,9 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+_SPACING = {"G": L.SPACING_G, "invG": L.SPACING_INVG}
+
+
 class Table:
     def __init__(self, handle):
         self._h = handle
@@ -46,6 +49,12 @@ class Table:
         w = np.zeros((n.value, 7), np.float64)
         L.check(L.lib.helm27_table_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_double)), None, None, None))
         return w, g0.value, dg.value
+
+    def axis(self):
+        """(spacing "G" | "invG", first abscissa, step, entries)."""
+        sp, v0, dv, n = C.c_int(), C.c_double(), C.c_double(), C.c_int()
+        L.check(L.lib.helm27_table_axis(self._h, C.byref(sp), C.byref(v0), C.byref(dv), C.byref(n)), "table_axis")
+        return ("G" if sp.value == L.SPACING_G else "invG"), v0.value, dv.value, n.value
 
     def close(self):
         if self._h:
@@ -72,6 +81,13 @@ class Operator:
     @property
     def handle(self):
         return self._h
+
+    def table_weights(self):
+        """Weights [n_g, 7] of the table the operator uses (widened under extend_table)."""
+        n = self.info()["n_g"]
+        w = np.zeros((n, 7), np.float64)
+        L.check(L.lib.helm27_op_table_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_double))), "op_table_weights")
+        return w
 
     def info(self):
         d = L.OpDesc()
@@ -219,22 +235,23 @@ class Context:
         return self._h
 
     def build_table(self, g_min=3.0, g_max=20.0, dg=0.05, lam=1e-3, n_angles=5, angle_step_deg=10.0,
-                    diff_order=1) -> Table:
-        opts = L.TableOpts(n_angles, angle_step_deg, diff_order)
+                    diff_order=1, spacing="G") -> Table:
+        """spacing "G": abscissae G = g_min + i dg; "invG": s = 1/G = g_min + i dg."""
+        opts = L.TableOpts(n_angles, angle_step_deg, diff_order, _SPACING[spacing])
         h = C.c_void_p()
         L.check(L.lib.helm27_build_table(self._h, g_min, g_max, dg, lam, C.byref(opts), C.byref(h)), "build_table")
         return Table(h)
 
-    def table_from_weights(self, g_min, dg, w5) -> Table:
+    def table_from_weights(self, g_min, dg, w5, spacing="G") -> Table:
         w5 = np.ascontiguousarray(np.asarray(w5, np.float64).reshape(-1, 5))
         h = C.c_void_p()
-        L.check(L.lib.helm27_table_from_weights(self._h, g_min, dg, w5.shape[0],
+        L.check(L.lib.helm27_table_from_weights(self._h, _SPACING[spacing], g_min, dg, w5.shape[0],
                                                 w5.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)),
                 "table_from_weights")
         return Table(h)
 
     def assemble(self, table: Table, vel, h: float, freq: float, npml=8, R=1e-3, c_ref=0.0,
-                 weights="GA", store: Iterable[str] = ()) -> Operator:
+                 weights="GA", store: Iterable[str] = (), extend_table=False) -> Operator:
         """vel: numpy float32 [nz, ny, nx] or a device tensor of that shape."""
         if hasattr(vel, "data_ptr"):
             _check_device_velocity(vel)
@@ -251,6 +268,8 @@ class Context:
         flags = _WEIGHTS[weights]
         for s in store:
             flags |= {"c64": L.STORE_C64, "c128": L.STORE_C128}[s]
+        if extend_table:
+            flags |= L.EXTEND_TABLE
         hnd = C.c_void_p()
         L.check(L.lib.helm27_assemble(self._h, table.handle, ptr, nx, ny, nz, h, freq, C.byref(p), flags,
                                       C.byref(hnd)), "assemble")

@@ -116,9 +116,15 @@ struct helm27_ctx {
 };
 
 struct helm27_table {
-    double g_min = 0, dg = 0;
+    double g_min = 0, dg = 0;   // first abscissa and step (of G, or of s = 1/G when spacing = 1)
     int n_g = 0;
-    std::vector<double> w7;   // [n_g][7]
+    int spacing = 0;            // 0: G-uniform, 1: uniform in s = 1/G
+    std::vector<double> w7;     // [n_g][7]
+    // how it was built (helm27_build_table), so that a wider table can be
+    // built the same way; lambda < 0: caller-given weights
+    double lambda = -1.0;
+    int n_ang = 5, diff_order = 1;
+    double angle_step = 10.0;
 };
 
 namespace h27 {
@@ -174,8 +180,7 @@ struct helm27_op {
     double g_min_model = 0, g_max_model = 0;
     void* d_coef_f = nullptr;        // stored: float2[27][N]
     void* d_coef_d = nullptr;        // stored: double2[27][N]
-    std::vector<double> w7;          // table weights [n_g][7] (host copy)
-    double table_gmin = 0, table_dg = 0;
+    helm27_table table;              // the table it uses (a copy, or the widened one): weights, axis, fit settings
     void* solver = nullptr;          // solver workspace (solver.cpp)
 };
 
@@ -183,7 +188,12 @@ namespace h27 {
 
 // table.cpp
 void dispersion_rows(double G, double theta, double phi, double H[5], double* g);
+void dispersion_rows_inv(double s, double theta, double phi, double H[5], double* g);
 void complete_weights(const double w5[5], double w7[7]);
+// Tikhonov table over v_min + i dv (i = 0 .. n_g - 1) with the settings of
+// `like` (spacing, lambda, angles, difference order); like must come from
+// helm27_build_table
+int build_table_like(const helm27_table* like, double v_min, int n_g, helm27_table** out);
 
 // op.cpp
 int op_build(helm27_ctx* ctx, const double* w7, int n_g, double g_min, double dg,
@@ -199,7 +209,12 @@ void make_tiling(int nx, int ny, const int plain_lo[2], const int plain_hi[2], T
 void axis_nodes(int n, double h, double x_lo, double x_hi, double L, double omega, double c_ref, double R,
                 std::vector<AxisNode<double>>* out);
 int grid_setup(GridOp* g, const double* w7, int n_g, int fixed);
-int host_index(float c, double fh, double gmin, double dg, int n_g);
+int host_index(float c, double fh, double gmin, double dg, int n_g, int invg);
+// the smallest range on table t's axis grid (v_min - k dv .. v_max + k' dv)
+// that covers abscissae need_lo .. need_hi, within the axis' domain (v > 0 on
+// the G axis, v >= 0 on the 1/G axis): its first abscissa and entry count
+// (ERANGE beyond 65535 entries)
+int widen_range(const helm27_table* t, double need_lo, double need_hi, double* v_min, int* n_g);
 
 // kernels (kernels_*.hip): host-side launchers
 // d_counts: 4 entries, initialised by the caller to {0, 0, bits of +inf, 0}:
@@ -208,7 +223,7 @@ int host_index(float c, double fh, double gmin, double dg, int n_g);
 // (the device must be current)
 int noalloc_init(int device);
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
-                        int n_g, unsigned long long* d_counts, hipStream_t s);
+                        int n_g, int invg, unsigned long long* d_counts, hipStream_t s);
 // y = A u (MODE_APPLY), y = b - A u (MODE_RESID), y = u + omega_j D^-1 (b - A u)
 // (MODE_JACOBI) or y = omega_j D^-1 b (MODE_JACOBI0, u not read; wavefront
 // kernel only) with A's mass scaled by (shift_re + i shift_im); (1, 0) is the

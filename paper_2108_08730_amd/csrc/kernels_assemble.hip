@@ -10,15 +10,15 @@
 
 namespace h27 {
 
-// idx = clamp(floor((c/(f h) - g_min)/dG + 1/2), 0, n_g - 1)   (paper Sec. 3.1:
-// every row picks the table entry of its local G = c/(f h); nearest entry,
-// ties upwards).  counts[0] += clamped points, counts[1] += invalid velocities,
+// idx = clamp(floor((v - v_min)/dv + 1/2), 0, n_g - 1) with v = c/(f h) on the
+// G axis and v = (f h)/c on the 1/G axis (paper Sec. 3.1: every row picks the
+// table entry of its local G = c/(f h); nearest entry, ties upwards).  counts[0] += clamped points, counts[1] += invalid velocities,
 // counts[2] / counts[3] = min / max bit pattern of the valid velocities (the
 // bits of positive floats order like the values; the caller initialises them
 // to +inf and 0).
 // One point: its table index, and the running clamp / invalid counts and
 // velocity range of the calling thread.
-__device__ __forceinline__ uint16_t index_point(float cv, double fh, double gmin, double dg, int n_g,
+__device__ __forceinline__ uint16_t index_point(float cv, double fh, double gmin, double dg, int n_g, int invg,
                                                 unsigned long long& ncl, unsigned long long& nbad, float& vmin,
                                                 float& vmax) {
     const double top = static_cast<double>(n_g - 1);
@@ -28,7 +28,7 @@ __device__ __forceinline__ uint16_t index_point(float cv, double fh, double gmin
         vmin = fminf(vmin, cv);
         vmax = fmaxf(vmax, cv);
     }
-    const double G = static_cast<double>(cv) / fh;
+    const double G = invg ? fh / static_cast<double>(cv) : static_cast<double>(cv) / fh;
     const double t = (G - gmin) / dg;
     const double raw = floor(t + 0.5);
     int k;
@@ -45,7 +45,7 @@ __device__ __forceinline__ uint16_t index_point(float cv, double fh, double gmin
 }
 
 __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __restrict__ idx, int64_t N,
-                                    double fh, double gmin, double dg, int n_g,
+                                    double fh, double gmin, double dg, int n_g, int invg,
                                     unsigned long long* __restrict__ counts) {
     __shared__ unsigned long long red[2][kBlock / 64];
     __shared__ float rmm[2][kBlock / 64];
@@ -53,7 +53,7 @@ __global__ void select_index_kernel(const float* __restrict__ c, uint16_t* __res
     float vmin = __builtin_inff(), vmax = 0.0f;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        idx[i] = index_point(c[i], fh, gmin, dg, n_g, ncl, nbad, vmin, vmax);
+        idx[i] = index_point(c[i], fh, gmin, dg, n_g, invg, ncl, nbad, vmin, vmax);
     // wavefront reduction, then one atomic per block
     for (int off = 32; off > 0; off >>= 1) {
         ncl += __shfl_down(ncl, off, 64);
@@ -140,14 +140,14 @@ __device__ __forceinline__ void block_reduce_record(unsigned long long ncl, unsi
 
 __global__ __launch_bounds__(kBlock) void select_index_blocks_kernel(const float* __restrict__ c,
                                                                      uint16_t* __restrict__ idx, int64_t N, double fh,
-                                                                     double gmin, double dg, int n_g,
+                                                                     double gmin, double dg, int n_g, int invg,
                                                                      NaRecord* __restrict__ rec) {
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kNaPerBlock;
     const int64_t i1 = i0 + kNaPerBlock < N ? i0 + kNaPerBlock : N;
     unsigned long long ncl = 0, nbad = 0;
     float vmin = __builtin_inff(), vmax = 0.0f;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock)
-        idx[i] = index_point(c[i], fh, gmin, dg, n_g, ncl, nbad, vmin, vmax);
+        idx[i] = index_point(c[i], fh, gmin, dg, n_g, invg, ncl, nbad, vmin, vmax);
     block_reduce_record(ncl, nbad, vmin, vmax, rec + blockIdx.x);
 }
 
@@ -193,12 +193,12 @@ int noalloc_init(int device) {
 }
 
 int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, double gmin, double dg,
-                        int n_g, unsigned long long* d_counts, hipStream_t s) {
+                        int n_g, int invg, unsigned long long* d_counts, hipStream_t s) {
     int64_t blocks = (N + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(select_index_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, c, idx, N,
-                       fh, gmin, dg, n_g, d_counts);
+                       fh, gmin, dg, n_g, invg, d_counts);
     H27_CHECK_HIP(hipGetLastError());
     return HELM27_OK;
 }
@@ -444,7 +444,7 @@ extern "C" int helm27_select_index_noalloc(helm27_ctx* ctx, const helm27_table* 
     const int nblocks = static_cast<int>((n + kNaPerBlock - 1) / kNaPerBlock);
     const double fh = freq * h;
     hipLaunchKernelGGL(select_index_blocks_kernel, dim3(nblocks), dim3(kBlock), 0, s, vel, idx, n, fh, t->g_min,
-                       t->dg, t->n_g, rec);
+                       t->dg, t->n_g, t->spacing, rec);
     if (hipGetLastError() != hipSuccess) return done(HELM27_EDEVICE);
     hipLaunchKernelGGL(reduce_records_kernel, dim3(1), dim3(kBlock), 0, s, rec, nblocks, rec + kNaBlocks);
     if (hipGetLastError() != hipSuccess) return done(HELM27_EDEVICE);
@@ -459,7 +459,7 @@ extern "C" int helm27_select_index_noalloc(helm27_ctx* ctx, const helm27_table* 
     std::memcpy(&cmax, &hi, sizeof(float));
     stats->n_clamped = static_cast<int64_t>(r.ncl);
     stats->n_invalid = static_cast<int64_t>(r.nbad);
-    stats->g_min_model = static_cast<double>(cmin) / fh;
+    stats->g_min_model = static_cast<double>(cmin) / fh;   // G = c/(f h) on either table axis
     stats->g_max_model = static_cast<double>(cmax) / fh;
     return done(r.nbad ? HELM27_EINVAL : HELM27_OK);
 }

@@ -140,13 +140,28 @@ static EntryCoef<R> entry_from_w7(const double* w) {
 }
 
 // The same binary64 formula as the device index selection.
-int host_index(float c, double fh, double gmin, double dg, int n_g) {
-    const double G = static_cast<double>(c) / fh;
+int host_index(float c, double fh, double gmin, double dg, int n_g, int invg) {
+    const double G = invg ? fh / static_cast<double>(c) : static_cast<double>(c) / fh;
     const double t = (G - gmin) / dg;
     const double raw = std::floor(t + 0.5);
     if (!(raw >= 0.0)) return 0;
     if (raw > static_cast<double>(n_g - 1)) return n_g - 1;
     return static_cast<int>(raw);
+}
+
+int widen_range(const helm27_table* t, double need_lo, double need_hi, double* v_min, int* n_g) {
+    const double v0 = t->g_min, dv = t->dg;
+    const double v1 = v0 + (t->n_g - 1) * dv;
+    double k_lo = need_lo < v0 ? std::ceil((v0 - need_lo) / dv) : 0.0;
+    // keep the first abscissa in the axis' domain: G > 0, s = 1/G >= 0
+    const double k_max = t->spacing == HELM27_SPACING_INVG ? std::floor(v0 / dv + 1e-9) : std::ceil(v0 / dv) - 1.0;
+    if (k_lo > k_max) k_lo = std::max(0.0, k_max);
+    const double k_hi = need_hi > v1 ? std::ceil((need_hi - v1) / dv) : 0.0;
+    const double n = t->n_g + k_lo + k_hi;
+    if (n > 65535.0) return HELM27_ERANGE;
+    *v_min = k_lo > 0 ? v0 - k_lo * dv : v0;
+    *n_g = static_cast<int>(n);
+    return HELM27_OK;
 }
 
 // Fill the weight tables, PML axes and tiling of a grid whose velocity is
@@ -267,7 +282,8 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     if (nx < 3 || ny < 3 || nz < 3 || !(h > 0) || !(freq > 0)) return HELM27_EINVAL;
     const int wmode = flags & 0x3;
     if (wmode == 3) return HELM27_EINVAL;
-    if (flags & ~(0x3 | HELM27_STORE_C64 | HELM27_STORE_C128)) return HELM27_EINVAL;
+    if (flags & ~(0x3 | HELM27_STORE_C64 | HELM27_STORE_C128 | HELM27_EXTEND_TABLE)) return HELM27_EINVAL;
+    if ((flags & HELM27_EXTEND_TABLE) && t->lambda < 0) return HELM27_EINVAL;   // fit settings unknown
     helm27_pml P{{8, 8, 8}, 1e-3, 0.0};
     if (pml) P = *pml;
     const int dims[3] = {nx, ny, nz};
@@ -293,9 +309,7 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     g.R = P.R;
     op->freq = freq;
     op->flags = flags;
-    op->w7 = t->w7;
-    op->table_gmin = t->g_min;
-    op->table_dg = t->dg;
+    op->table = *t;
     const double fh = freq * h;
 
     int st = HELM27_OK;
@@ -314,16 +328,40 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
         return fail(HELM27_EDEVICE);
     unsigned long long cnt[4] = {0, 0, 0x7F800000ull, 0};   // clamped, invalid, min bits (+inf), max bits
     if (hipMalloc(&d_cnt, sizeof(cnt)) != hipSuccess) return fail(HELM27_ENOMEM);
-    if (hipMemcpyAsync(d_cnt, cnt, sizeof(cnt), hipMemcpyHostToDevice, stream) != hipSuccess)
-        return fail(HELM27_EDEVICE);
-    if ((st = launch_select_index(g.d_c, g.d_idx, N, fh, t->g_min, t->dg, t->n_g, d_cnt, stream)))
-        return fail(st);
-    if (hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
-        return fail(HELM27_EDEVICE);
+    // index pass with the operator's table: counts, validation, range
+    auto index_pass = [&]() {
+        unsigned long long c0[4] = {0, 0, 0x7F800000ull, 0};
+        const helm27_table& T = op->table;
+        if (hipMemcpyAsync(d_cnt, c0, sizeof(c0), hipMemcpyHostToDevice, stream) != hipSuccess) return HELM27_EDEVICE;
+        int s2 = launch_select_index(g.d_c, g.d_idx, N, fh, T.g_min, T.dg, T.n_g, T.spacing, d_cnt, stream);
+        if (s2) return s2;
+        if (hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return HELM27_EDEVICE;
+        return HELM27_OK;
+    };
+    if ((st = index_pass())) return fail(st);
+    if (cnt[1] != 0) return fail(HELM27_EINVAL);
+    if ((flags & HELM27_EXTEND_TABLE) && cnt[0] != 0) {
+        // widen the table over the model's range on the same axis grid and index again
+        float c_lo, c_hi;
+        const unsigned lo = static_cast<unsigned>(cnt[2]), hi = static_cast<unsigned>(cnt[3]);
+        std::memcpy(&c_lo, &lo, sizeof(float));
+        std::memcpy(&c_hi, &hi, sizeof(float));
+        const bool inv = t->spacing == HELM27_SPACING_INVG;
+        const double need_lo = inv ? fh / static_cast<double>(c_hi) : static_cast<double>(c_lo) / fh;
+        const double need_hi = inv ? fh / static_cast<double>(c_lo) : static_cast<double>(c_hi) / fh;
+        double v_min = 0;
+        int n_w = 0;
+        if ((st = widen_range(t, need_lo, need_hi, &v_min, &n_w))) return fail(st);
+        helm27_table* wide = nullptr;
+        if ((st = build_table_like(t, v_min, n_w, &wide))) return fail(st);
+        op->table = *wide;
+        delete wide;
+        if ((st = index_pass())) return fail(st);
+    }
     hipFree(d_cnt);
     d_cnt = nullptr;
-    if (cnt[1] != 0) return fail(HELM27_EINVAL);
     op->n_clamped = static_cast<int64_t>(cnt[0]);
     float cmin, cmax;
     {
@@ -337,7 +375,8 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     op->g_max_model = static_cast<double>(cmax) / fh;
     g.c_ref = P.c_ref > 0 ? P.c_ref : static_cast<double>(cmax);
 
-    if ((st = grid_setup(&g, t->w7.data(), t->n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
+    const helm27_table& T = op->table;
+    if ((st = grid_setup(&g, T.w7.data(), T.n_g, wmode == HELM27_WEIGHTS_FIXED ? 1 : 0))) return fail(st);
     // the explicit tile shape a large grid starts from when one of its
     // settings is changed (launches choose per call while auto_tile is set)
     if (g.N >= (int64_t(1) << 23)) {
@@ -345,9 +384,13 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
         g.plain_ry[0] = 1;
         g.wave_zchunk = 16;
     }
-    // idx is non-decreasing in c, so the smallest / largest velocities give its range
-    g.idx_lo = host_index(cmin, fh, t->g_min, t->dg, t->n_g);
-    g.idx_hi = host_index(cmax, fh, t->g_min, t->dg, t->n_g);
+    // idx is monotone in c, so the smallest / largest velocities give its range
+    {
+        const int ia = host_index(cmin, fh, T.g_min, T.dg, T.n_g, T.spacing);
+        const int ib = host_index(cmax, fh, T.g_min, T.dg, T.n_g, T.spacing);
+        g.idx_lo = std::min(ia, ib);
+        g.idx_hi = std::max(ia, ib);
+    }
     if (wmode == HELM27_WEIGHTS_GAM) {
         if (hipMalloc(&g.d_row_f, N * sizeof(EntryCoef<float>)) != hipSuccess) return fail(HELM27_ENOMEM);
         if (hipMalloc(&g.d_row_d, N * sizeof(EntryCoef<double>)) != hipSuccess) return fail(HELM27_ENOMEM);
@@ -407,6 +450,15 @@ extern "C" int helm27_op_info(const helm27_op* op, helm27_op_desc* o) {
     o->zchunk = op->g.wave_zchunk;
     o->rhs_block = op->g.rhs_block;
     o->rhs_order = op->g.rhs_order;
+    o->table_spacing = op->table.spacing;
+    o->table_min = op->table.g_min;
+    o->table_step = op->table.dg;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_op_table_weights(const helm27_op* op, double* w7) {
+    if (!op || !w7) return HELM27_EINVAL;
+    std::memcpy(w7, op->table.w7.data(), op->table.w7.size() * sizeof(double));
     return HELM27_OK;
 }
 

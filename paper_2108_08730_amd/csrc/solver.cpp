@@ -30,6 +30,8 @@ struct SolverState {
     int levels = 0;
     int req_levels = -1;             // levels asked for when the hierarchy was built
     std::vector<GridOp> coarse;
+    int64_t coarse_clamped = 0;      // coarse rows outside their table
+    int coarse_tables = 0;           // coarse levels with their own widened table
     // workspace
     int nrhs = 0, m = 0, prec = 0;   // prec = sizeof(real) of the inner precision
     int64_t N = 0;
@@ -158,12 +160,27 @@ static int auto_levels(const GridOp& g) {
 }
 
 // Coarse grids: node i of level l+1 sits on node 2i of level l.
+// Each coarse level rediscretises the operator at its own h_l = 2^l h, so its
+// rows have G = c/(f h_l).  They take the operator's table; if the operator
+// was assembled with HELM27_EXTEND_TABLE and that table does not reach the
+// level's G range, the level gets a table widened for it (same axis grid and
+// fit settings).  The rows that still fall outside are counted.
 static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_t s) {
     free_hierarchy(S);
+    S->coarse_clamped = 0;
+    S->coarse_tables = 0;
     const GridOp* prev = &op->g;
-    unsigned long long* d_cnt = nullptr;   // select-index counters (4 entries; only the layout matters here)
-    if (hipMalloc(&d_cnt, 4 * sizeof(unsigned long long)) != hipSuccess) return HELM27_ENOMEM;
+    // select-index counters, 4 per level (clamped rows, invalid, min, max bits)
+    const int n_lv = levels > 1 ? levels - 1 : 1;
+    unsigned long long* d_cnt = nullptr;
+    if (hipMalloc(&d_cnt, 4 * sizeof(unsigned long long) * n_lv) != hipSuccess) return HELM27_ENOMEM;
+    if (hipMemsetAsync(d_cnt, 0, 4 * sizeof(unsigned long long) * n_lv, s) != hipSuccess) {
+        hipFree(d_cnt);
+        return HELM27_EDEVICE;
+    }
     int st = HELM27_OK;
+    const helm27_table& base = op->table;
+    const bool widen = (op->flags & HELM27_EXTEND_TABLE) && base.lambda >= 0;
     S->coarse.reserve(levels > 1 ? levels - 1 : 0);
     for (int l = 1; l < levels; ++l) {
         const int cx = (prev->nx + 1) / 2, cy = (prev->ny + 1) / 2, cz = (prev->nz + 1) / 2;
@@ -192,19 +209,42 @@ static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_
         c.bytes += c.N * (sizeof(float) + sizeof(uint16_t));
         if ((st = inject_velocity(prev->d_c, prev->nx, prev->ny, c.d_c, cx, cy, cz, s))) break;
         const double fh = op->freq * c.h;
-        if (hipMemsetAsync(d_cnt, 0, 4 * sizeof(unsigned long long), s) != hipSuccess) {
-            st = HELM27_EDEVICE;
-            break;
+        const helm27_table* T = &base;
+        helm27_table* own = nullptr;
+        if (widen) {
+            const bool inv = base.spacing == HELM27_SPACING_INVG;
+            const double need_lo = inv ? fh / static_cast<double>(op->cmax) : static_cast<double>(op->cmin) / fh;
+            const double need_hi = inv ? fh / static_cast<double>(op->cmin) : static_cast<double>(op->cmax) / fh;
+            double v_min = 0;
+            int n_w = 0;
+            if ((st = widen_range(&base, need_lo, need_hi, &v_min, &n_w))) break;
+            if (n_w != base.n_g) {
+                if ((st = build_table_like(&base, v_min, n_w, &own))) break;
+                T = own;
+                ++S->coarse_tables;
+            }
         }
-        const int n_g = op->g.n_g;
-        if ((st = launch_select_index(c.d_c, c.d_idx, c.N, fh, op->table_gmin, op->table_dg, n_g, d_cnt, s))) break;
-        if ((st = grid_setup(&c, op->w7.data(), n_g, op->g.fixed))) break;
-        c.idx_lo = host_index(op->cmin, fh, op->table_gmin, op->table_dg, n_g);
-        c.idx_hi = host_index(op->cmax, fh, op->table_gmin, op->table_dg, n_g);
+        const int n_g = T->n_g;
+        st = launch_select_index(c.d_c, c.d_idx, c.N, fh, T->g_min, T->dg, n_g, T->spacing, d_cnt + 4 * (l - 1), s);
+        if (!st) st = grid_setup(&c, T->w7.data(), n_g, op->g.fixed);
+        if (!st) {
+            const int ia = host_index(op->cmin, fh, T->g_min, T->dg, n_g, T->spacing);
+            const int ib = host_index(op->cmax, fh, T->g_min, T->dg, n_g, T->spacing);
+            c.idx_lo = std::min(ia, ib);
+            c.idx_hi = std::max(ia, ib);
+        }
+        delete own;
+        if (st) break;
         prev = &c;
     }
-    if (hipStreamSynchronize(s) != hipSuccess && st == HELM27_OK) st = HELM27_EDEVICE;
+    std::vector<unsigned long long> cnt(4 * static_cast<size_t>(n_lv), 0);
+    if ((hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s) !=
+             hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess) &&
+        st == HELM27_OK)
+        st = HELM27_EDEVICE;
     hipFree(d_cnt);
+    for (size_t l = 0; l < S->coarse.size(); ++l) S->coarse_clamped += static_cast<int64_t>(cnt[4 * l]);
     S->levels = 1 + static_cast<int>(S->coarse.size());
     return st;
 }
@@ -710,6 +750,9 @@ static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, con
         stats->inner_iters = inner_total;
         stats->converged = converged ? 1 : 0;
         stats->max_relres = maxrel;
+        stats->mg_levels = o->mg_levels == 0 ? 1 : S->levels;
+        stats->coarse_clamped = o->mg_levels == 0 ? 0 : S->coarse_clamped;
+        stats->coarse_tables = o->mg_levels == 0 ? 0 : S->coarse_tables;
     }
     return converged ? HELM27_OK : HELM27_ENOCONV;
 }

@@ -49,6 +49,25 @@ void dispersion_rows(double G, double theta, double phi, double H[5], double* g)
     *g = k2 * A - 0.5 * (3.0 - 3.0 * A + B - C);
 }
 
+// The same rows as functions of s = 1/G (the paper's 1/G table axis): phases
+// 2 pi s n_a and k2 = 2 pi^2 s^2, so s = 0 (G infinite) gives zero rows.
+void dispersion_rows_inv(double s, double theta, double phi, double H[5], double* g) {
+    const double pi = 3.14159265358979323846;
+    const double ca = std::cos(2.0 * pi * std::cos(phi) * std::cos(theta) * s);
+    const double cb = std::cos(2.0 * pi * std::cos(phi) * std::sin(theta) * s);
+    const double cc = std::cos(2.0 * pi * std::sin(phi) * s);
+    const double A = ca * cb * cc;
+    const double B = ca * cb + ca * cc + cb * cc;
+    const double C = ca + cb + cc;
+    const double k2 = 2.0 * pi * pi * s * s;
+    H[0] = 0.5 * (3.0 + 3.0 * A - B - C);
+    H[1] = (3.0 + 9.0 * A - 5.0 * B + C) / 6.0;
+    H[2] = k2 * (A - 1.0);
+    H[3] = k2 * (6.0 * A - 2.0 * C);
+    H[4] = k2 * (12.0 * A - 4.0 * B);
+    *g = k2 * A - 0.5 * (3.0 - 3.0 * A + B - C);
+}
+
 void complete_weights(const double w5[5], double w7[7]) {
     w7[0] = w5[0];
     w7[1] = w5[1];
@@ -236,23 +255,28 @@ static int householder_rows(double* A, double* b, int m) {
     return nk;
 }
 
-extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, double dg, double lambda,
-                                  const helm27_table_opts* opts, helm27_table** out) {
-    (void)ctx;
-    if (!out || !(g_min > 0) || !(dg > 0) || !(g_max >= g_min) || !(lambda >= 0)) return HELM27_EINVAL;
-    const double nn = std::round((g_max - g_min) / dg) + 1.0;
-    if (nn > 65535.0) return HELM27_EINVAL;
-    const int n_g = static_cast<int>(nn);
-    int n_ang = 5;
-    double step = 10.0;
-    int order = 1;
-    if (opts) {
-        if (opts->n_angles > 0) n_ang = opts->n_angles;
-        if (opts->angle_step_deg > 0) step = opts->angle_step_deg;
-        if (opts->diff_order == 1 || opts->diff_order == 2) order = opts->diff_order;
-        else if (opts->diff_order != 0) return HELM27_EINVAL;
-    }
+namespace h27 {
+
+// the table over g_min + i dg, i < n_g (the abscissa is G, or s = 1/G when
+// spacing = 1), with the given fit settings
+static int build_table_impl(double g_min, int n_g, double dg, double lambda, int spacing, int n_ang, double step,
+                            int order, helm27_table** out) {
     if (order == 2 && n_g < 3 && lambda > 0) return HELM27_EINVAL;
+    if (spacing == 1 && lambda == 0.0) return HELM27_EINVAL;   // the decoupled fits need the G axis
+    auto rows = [spacing](double v, double th, double ph, double* H, double* g) {
+        if (spacing == 1) dispersion_rows_inv(v, th, ph, H, g);
+        else dispersion_rows(v, th, ph, H, g);
+    };
+    auto stamp = [&](helm27_table* t) {
+        t->g_min = g_min;
+        t->dg = dg;
+        t->n_g = n_g;
+        t->spacing = spacing;
+        t->lambda = lambda;
+        t->n_ang = n_ang;
+        t->angle_step = step;
+        t->diff_order = order;
+    };
     const double pi = 3.14159265358979323846;
     std::vector<double> ang(n_ang);
     for (int k = 0; k < n_ang; ++k) ang[k] = k * step * pi / 180.0;
@@ -261,9 +285,7 @@ extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, d
         // no smoothing: each G is its own (rank-deficient) problem
         helm27_table* t = new (std::nothrow) helm27_table;
         if (!t) return HELM27_ENOMEM;
-        t->g_min = g_min;
-        t->dg = dg;
-        t->n_g = n_g;
+        stamp(t);
         t->w7.resize(static_cast<size_t>(n_g) * 7);
         const int m = n_ang * n_ang;
         for (int i = 0; i < n_g; ++i) {
@@ -301,7 +323,7 @@ extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, d
             const double G = g_min + i * dg;
             int r = 0;
             for (int jp = 0; jp < n_ang; ++jp)
-                for (int jt = 0; jt < n_ang; ++jt, ++r) dispersion_rows(G, ang[jt], ang[jp], &Ab[5 * r], &bb[r]);
+                for (int jt = 0; jt < n_ang; ++jt, ++r) rows(G, ang[jt], ang[jp], &Ab[5 * r], &bb[r]);
             const int nk = householder_rows(Ab.data(), bb.data(), m_ang);
             nkb[i] = nk;
             for (int k = 0; k < nk; ++k) {
@@ -350,24 +372,55 @@ extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, d
     if (!ls.solve(&w)) return HELM27_ENUMERIC;
     helm27_table* t = new (std::nothrow) helm27_table;
     if (!t) return HELM27_ENOMEM;
-    t->g_min = g_min;
-    t->dg = dg;
-    t->n_g = n_g;
+    stamp(t);
     t->w7.resize(static_cast<size_t>(n_g) * 7);
     for (int i = 0; i < n_g; ++i) complete_weights(&w[5 * i], &t->w7[7 * i]);
     *out = t;
     return HELM27_OK;
 }
 
-extern "C" int helm27_table_from_weights(helm27_ctx* ctx, double g_min, double dg, int n_g, const double* w5,
-                                         helm27_table** out) {
+int build_table_like(const helm27_table* like, double v_min, int n_g, helm27_table** out) {
+    if (!like || !out || like->lambda < 0 || n_g < 1 || n_g > 65535) return HELM27_EINVAL;
+    return build_table_impl(v_min, n_g, like->dg, like->lambda, like->spacing, like->n_ang, like->angle_step,
+                            like->diff_order, out);
+}
+
+}  // namespace h27
+
+extern "C" int helm27_build_table(helm27_ctx* ctx, double g_min, double g_max, double dg, double lambda,
+                                  const helm27_table_opts* opts, helm27_table** out) {
     (void)ctx;
-    if (!out || !w5 || n_g <= 0 || n_g > 65535 || !(dg > 0) || !std::isfinite(g_min)) return HELM27_EINVAL;
+    int n_ang = 5, order = 1, spacing = HELM27_SPACING_G;
+    double step = 10.0;
+    if (opts) {
+        if (opts->n_angles > 0) n_ang = opts->n_angles;
+        if (opts->angle_step_deg > 0) step = opts->angle_step_deg;
+        if (opts->diff_order == 1 || opts->diff_order == 2) order = opts->diff_order;
+        else if (opts->diff_order != 0) return HELM27_EINVAL;
+        if (opts->spacing == HELM27_SPACING_G || opts->spacing == HELM27_SPACING_INVG) spacing = opts->spacing;
+        else return HELM27_EINVAL;
+    }
+    const bool lo_ok = spacing == HELM27_SPACING_G ? g_min > 0 : g_min >= 0;
+    if (!out || !lo_ok || !(dg > 0) || !(g_max >= g_min) || !(lambda >= 0) || !std::isfinite(g_max))
+        return HELM27_EINVAL;
+    const double nn = std::round((g_max - g_min) / dg) + 1.0;
+    if (nn > 65535.0) return HELM27_EINVAL;
+    return h27::build_table_impl(g_min, static_cast<int>(nn), dg, lambda, spacing, n_ang, step, order, out);
+}
+
+extern "C" int helm27_table_from_weights(helm27_ctx* ctx, int spacing, double g_min, double dg, int n_g,
+                                         const double* w5, helm27_table** out) {
+    (void)ctx;
+    if (!out || !w5 || n_g <= 0 || n_g > 65535 || !(dg > 0) || !std::isfinite(g_min) ||
+        (spacing != HELM27_SPACING_G && spacing != HELM27_SPACING_INVG) ||
+        (spacing == HELM27_SPACING_INVG && g_min < 0))
+        return HELM27_EINVAL;
     helm27_table* t = new (std::nothrow) helm27_table;
     if (!t) return HELM27_ENOMEM;
     t->g_min = g_min;
     t->dg = dg;
     t->n_g = n_g;
+    t->spacing = spacing;
     t->w7.resize(static_cast<size_t>(n_g) * 7);
     for (int i = 0; i < n_g; ++i) {
         for (int k = 0; k < 5; ++k)
@@ -387,6 +440,15 @@ extern "C" int helm27_table_weights(const helm27_table* t, double* w7, int* n_g,
     if (n_g) *n_g = t->n_g;
     if (g_min) *g_min = t->g_min;
     if (dg) *dg = t->dg;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_table_axis(const helm27_table* t, int* spacing, double* v_min, double* dv, int* n_g) {
+    if (!t) return HELM27_EINVAL;
+    if (spacing) *spacing = t->spacing;
+    if (v_min) *v_min = t->g_min;
+    if (dv) *dv = t->dg;
+    if (n_g) *n_g = t->n_g;
     return HELM27_OK;
 }
 

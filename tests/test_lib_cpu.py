@@ -100,13 +100,19 @@ def test_table_errors():
     assert L.lib.helm27_build_table(None, 3.0, 20.0, 0.0, 1e-3, None, C.byref(h)) == L.EINVAL
     assert L.lib.helm27_build_table(None, 3.0, 20.0, 0.05, -1.0, None, C.byref(h)) == L.EINVAL
     assert L.lib.helm27_build_table(None, 1.0, 1e6, 1.0, 1e-3, None, C.byref(h)) == L.EINVAL
+    # 1/G axis: s_min may be 0 but not negative; lambda = 0 (decoupled fits) needs the G axis
+    opts = L.TableOpts(5, 10.0, 1, L.SPACING_INVG)
+    assert L.lib.helm27_build_table(None, -0.1, 0.4, 0.001, 1e-3, C.byref(opts), C.byref(h)) == L.EINVAL
+    assert L.lib.helm27_build_table(None, 0.0, 0.4, 0.001, 0.0, C.byref(opts), C.byref(h)) == L.EINVAL
+    assert L.lib.helm27_build_table(None, 3.0, 20.0, 0.05, 1e-3, C.byref(L.TableOpts(5, 10.0, 1, 7)),
+                                    C.byref(h)) == L.EINVAL
 
 
 def test_table_from_weights_roundtrip():
     w5 = np.array([[0.5, 0.3, 0.6, 0.04, 0.01], [0.2, 0.7, 0.62, 0.035, 0.018]])
     h = C.c_void_p()
-    L.check(L.lib.helm27_table_from_weights(None, 4.0, 1.0, 2, w5.ctypes.data_as(C.POINTER(C.c_double)),
-                                            C.byref(h)))
+    L.check(L.lib.helm27_table_from_weights(None, L.SPACING_G, 4.0, 1.0, 2,
+                                            w5.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
     w = np.zeros((2, 7))
     n = C.c_int()
     g0 = C.c_double()
@@ -121,3 +127,24 @@ def test_table_from_weights_roundtrip():
 def test_strerror():
     for code in (L.OK, L.EINVAL, L.ENOCONV, L.ERANGE, L.EADMIT):
         assert len(L.lib.helm27_strerror(code)) > 0
+
+
+def test_inverse_axis_table_matches_oracle():
+    """The table on the paper's own axis, 1/G from 0 to 0.4 by 0.001 (Sec. 2.2,
+    figure caption): the library's banded QR against the oracle's dense
+    least squares on the same stacked problem, to 1e-9 (as on the G axis)."""
+    S, W = T.build_table(0.0, 0.4, 0.001, 1e-3, spacing="invG")
+    opts = L.TableOpts(5, 10.0, 1, L.SPACING_INVG)
+    h = C.c_void_p()
+    L.check(L.lib.helm27_build_table(None, 0.0, 0.4, 0.001, 1e-3, C.byref(opts), C.byref(h)))
+    n = C.c_int()
+    sp = C.c_int()
+    v0 = C.c_double()
+    dv = C.c_double()
+    L.check(L.lib.helm27_table_axis(h, C.byref(sp), C.byref(v0), C.byref(dv), C.byref(n)))
+    assert sp.value == L.SPACING_INVG and n.value == 401 and v0.value == 0.0 and dv.value == 0.001
+    w = np.zeros((401, 7))
+    L.check(L.lib.helm27_table_weights(h, w.ctypes.data_as(C.POINTER(C.c_double)), None, None, None))
+    L.lib.helm27_table_destroy(h)
+    ref = T.complete_weights(W)
+    assert np.max(np.abs(w - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref)))

@@ -37,8 +37,10 @@ def test_noalloc_index_matches_assemble_two_calls():
     tab = ctx.build_table(3.0, 20.0, 0.05, 1e-3)
     # first call: 64 x 48 x 40 random field at 8 Hz (G below and above the
     # table, so some points clamp); second call: a smaller 20 x 17 x 9 model
-    cases = [((64, 48, 40), 25.0, 8.0, 3), ((20, 17, 9), 20.0, 6.0, 5)]
-    for dims, h, f, seed in cases:
+    # a third call on the 1/G table axis (smaller still)
+    tab_inv = ctx.build_table(0.0, 0.4, 0.001, 1e-3, spacing="invG")
+    cases = [((64, 48, 40), 25.0, 8.0, 3, tab), ((20, 17, 9), 20.0, 6.0, 5, tab), ((12, 10, 8), 25.0, 30.0, 7, tab_inv)]
+    for dims, h, f, seed, tab in cases:
         c = synth.random_field_model(dims, h, seed=seed)
         vel = torch.from_numpy(c).cuda().reshape(-1)
         idx = torch.full((vel.numel(),), -1, dtype=torch.int16, device="cuda")
