@@ -171,22 +171,28 @@ def solve_only(args, torch, api, synth):
     dims = tuple(int(v) for v in args.grid.split(","))
     h, npml = 25.0, 8
     ctx = api.Context(0)
-    tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
+    tv = tuple(float(v) for v in args.table.split(","))
+    tab = ctx.build_table(tv[0], tv[1], tv[2], tv[3], spacing=args.table_spacing)
     c = synth.random_field_model(dims, h, seed=1)
-    op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, args.freq, npml=npml)
+    op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, args.freq, npml=npml, extend_table=args.extend_table)
     info = op.info()
     xs = np.linspace(npml + 2, dims[0] - npml - 3, args.nrhs).astype(int)
     src = [(int(x), dims[1] // 2, npml + 2) for x in xs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    u, st = op.solve(src, tol=1e-6, max_inner=args.max_inner, verbose=1)
+    extra = {} if args.mg_levels is None else {"mg_levels": args.mg_levels}
+    extra["mg_coarse_table"] = args.mg_coarse_table
+    u, st = op.solve(src, tol=1e-6, max_inner=args.max_inner, verbose=1, **extra)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     print(json.dumps({"grid": list(dims), "nrhs": args.nrhs, "freq": args.freq, "h": h, "npml": npml,
                       "g_range": [info["g_min_model"], info["g_max_model"]], "solve_s": sec,
                       "rhs_per_s": args.nrhs / sec, "inner_iters": st["inner_iters"],
                       "outer_iters": st["outer_iters"], "max_relres": st["max_relres"],
-                      "converged": bool(st["converged"])}), flush=True)
+                      "converged": bool(st["converged"]), "mg_levels": st["mg_levels"],
+                      "coarse_clamped": st["coarse_clamped"], "coarse_tables": st["coarse_tables"],
+                      "table": [args.table, args.table_spacing, bool(args.extend_table)],
+                      "mg_coarse_table": args.mg_coarse_table}), flush=True)
 
 
 def solve_steps(args, torch, api, synth, ctx):
@@ -360,6 +366,14 @@ def main():
                     help="one multi-RHS solve on --grid with --nrhs surface sources at --freq")
     ap.add_argument("--freq", type=float, default=10.0)
     ap.add_argument("--max-inner", type=int, default=3000)
+    ap.add_argument("--table", type=str, default="2.5,60,0.05,1e-3",
+                    help="--solve-only: table v_min,v_max,dv,lambda (G, or s = 1/G with --table-spacing invG)")
+    ap.add_argument("--table-spacing", choices=("G", "invG"), default="G")
+    ap.add_argument("--extend-table", action="store_true",
+                    help="--solve-only: widen the table (and the coarse levels' tables) to the model's G range")
+    ap.add_argument("--mg-levels", type=int, default=None)
+    ap.add_argument("--mg-coarse-table", type=int, default=0,
+                    help="--solve-only: 1 = coarse levels take tables widened for their own G range")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving-mix requests (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="serving-mix Poisson arrival rate (1/s)")
     args = ap.parse_args()

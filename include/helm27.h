@@ -70,9 +70,12 @@ extern "C" {
 #define HELM27_WEIGHTS_GAM    0x2   /* mean of the 27 stencil points' entries (Sec. 3.1 "GAm") */
 #define HELM27_STORE_C64      0x10  /* also keep 27 stored complex-float coefficients per point */
 #define HELM27_STORE_C128     0x20  /* also keep 27 stored complex-double coefficients per point */
+#define HELM27_MASS_A         0x80  /* first consistent-mass form (Sec. 2.1, eq. 8): the mass term of row i
+                                       takes each neighbour's own bulk modulus, A = S + M diag(k^2),
+                                       instead of the collocation point's (second form, the default) */
 #define HELM27_EXTEND_TABLE   0x40  /* widen the table (same axis, step and fit settings) until no row
-                                       clamps; the solver's coarse multigrid levels then get tables
-                                       widened for their own G range (G / 2^l) as well */
+                                       clamps (see helm27_solve_opts.mg_coarse_table for the coarse
+                                       multigrid levels) */
 
 /* ---- opaque handles ----------------------------------------------------- */
 typedef struct helm27_ctx   helm27_ctx;
@@ -323,6 +326,15 @@ typedef struct {
     int    reorth_always;/* 1: second classical Gram-Schmidt pass at every Arnoldi step;
                             0 (default): per right-hand side only when the first pass
                             leaves less than 1/sqrt(2) of the vector's norm */
+    int    mg_coarse_table; /* weights of the coarse levels, whose rows have G = c/(f 2^l h):
+                            0 (default) = the operator's table, clamped at its ends (the
+                            clamped rows are counted in the stats); 1 = each level gets a
+                            table widened for its own G range (needs a table made by
+                            helm27_build_table).  Measured: below about 2.5 points per
+                            wavelength the dispersion-fitted weights make the shifted
+                            coarse operators a poor correction and GMRES stagnates
+                            (201x201x101 at 8 Hz: 811 steps with 0, no convergence in
+                            30000 with 1) */
 } helm27_solve_opts;
 
 typedef struct {

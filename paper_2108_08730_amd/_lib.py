@@ -20,6 +20,7 @@ STORE_C64, STORE_C128 = 0x10, 0x20
 
 SPACING_G, SPACING_INVG = 0, 1
 EXTEND_TABLE = 0x40
+MASS_A = 0x80
 
 
 class TableOpts(C.Structure):
@@ -48,7 +49,7 @@ class SolveOpts(C.Structure):
                 ("mg_levels", C.c_int), ("mg_shift", C.c_double), ("mg_pre", C.c_int),
                 ("mg_post", C.c_int), ("mg_omega", C.c_double), ("mg_coarse_sweeps", C.c_int),
                 ("use_graph", C.c_int), ("verbose", C.c_int), ("mg_shift_re", C.c_double),
-                ("reorth_always", C.c_int)]
+                ("reorth_always", C.c_int), ("mg_coarse_table", C.c_int)]
 
 
 class IndexStats(C.Structure):

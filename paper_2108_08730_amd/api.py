@@ -251,7 +251,7 @@ class Context:
         return Table(h)
 
     def assemble(self, table: Table, vel, h: float, freq: float, npml=8, R=1e-3, c_ref=0.0,
-                 weights="GA", store: Iterable[str] = (), extend_table=False) -> Operator:
+                 weights="GA", store: Iterable[str] = (), extend_table=False, mass_form="b") -> Operator:
         """vel: numpy float32 [nz, ny, nx] or a device tensor of that shape."""
         if hasattr(vel, "data_ptr"):
             _check_device_velocity(vel)
@@ -270,6 +270,10 @@ class Context:
             flags |= {"c64": L.STORE_C64, "c128": L.STORE_C128}[s]
         if extend_table:
             flags |= L.EXTEND_TABLE
+        if mass_form == "a":
+            flags |= L.MASS_A
+        elif mass_form != "b":
+            raise ValueError(mass_form)
         hnd = C.c_void_p()
         L.check(L.lib.helm27_assemble(self._h, table.handle, ptr, nx, ny, nz, h, freq, C.byref(p), flags,
                                       C.byref(hnd)), "assemble")

@@ -158,6 +158,7 @@ struct GridOp {
     int wave_zchunk = 0;                       // z planes per wavefront work item (0: automatic)
     int rhs_block = 0;                         // right-hand sides per box wavefront (FP32 block tiles):
                                                // 0 = automatic (1), 1, 2 or 4
+    int mass_a = 0;                            // 1: first consistent-mass form (neighbour bulk modulus)
     int rhs_order = 0;                         // work-item order of a multi-RHS launch: 0 = automatic
                                                // (right-hand side slowest), 1 = fastest, 2 = slowest
     bool auto_tile = true;                     // kernel variant, rows and z chunk chosen per launch from

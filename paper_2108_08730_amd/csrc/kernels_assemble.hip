@@ -260,7 +260,16 @@ __global__ void fill_stored_kernel(GridData<R> g, typename V2<R>::T* __restrict_
                         mass = mass + (R(2) * E.m1) * (ux * xy * xz + xx * uy * xz + xx * xy * uz);
                         mass = mass + (R(4) * E.m2) * (ux * uy * xz + ux * xy * uz + xx * uy * uz);
                         mass = mass + (R(8) * E.m3) * (ux * uy * uz);
-                        val = sig * stiff + kc * mass;
+                        if (g.mass_a) {
+                            // first mass form: the neighbour's own bulk modulus
+                            const int64_t j = i + (dx - 1) + (dy - 1) * static_cast<int64_t>(g.nx) +
+                                              (dz - 1) * g.plane;
+                            const R cj = static_cast<R>(g.c[j]);
+                            const R kj = g.omega2 / (cj * cj);
+                            val = sig * stiff + mk(kj * g.shift_re, kj * g.shift_im) * mass;
+                        } else {
+                            val = sig * stiff + kc * mass;
+                        }
                     }
                     st<R>(coef + static_cast<int64_t>(s) * N + i, val);
                 }
@@ -272,7 +281,7 @@ static GridData<R> make_grid_data(const GridOp& g, double shift_re, double shift
 
 template <>
 GridData<float> make_grid_data<float>(const GridOp& g, double shift_re, double shift_im) {
-    GridData<float> d;
+    GridData<float> d{};
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
     d.N = g.N;
@@ -282,12 +291,13 @@ GridData<float> make_grid_data<float>(const GridOp& g, double shift_re, double s
     d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
     d.shift_re = static_cast<float>(shift_re);
     d.shift_im = static_cast<float>(shift_im);
+    d.mass_a = g.mass_a;
     return d;
 }
 
 template <>
 GridData<double> make_grid_data<double>(const GridOp& g, double shift_re, double shift_im) {
-    GridData<double> d;
+    GridData<double> d{};
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
     d.N = g.N;
@@ -297,6 +307,7 @@ GridData<double> make_grid_data<double>(const GridOp& g, double shift_re, double
     d.inv_h2 = 1.0 / (g.h * g.h);
     d.shift_re = shift_re;
     d.shift_im = shift_im;
+    d.mass_a = g.mass_a;
     return d;
 }
 

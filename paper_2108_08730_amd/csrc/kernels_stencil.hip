@@ -366,7 +366,7 @@ static GridData<R> grid_data(const GridOp& g, double shift_re, double shift_im);
 
 template <>
 GridData<float> grid_data<float>(const GridOp& g, double shift_re, double shift_im) {
-    GridData<float> d;
+    GridData<float> d{};
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
     d.N = g.N;
@@ -376,12 +376,13 @@ GridData<float> grid_data<float>(const GridOp& g, double shift_re, double shift_
     d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
     d.shift_re = static_cast<float>(shift_re);
     d.shift_im = static_cast<float>(shift_im);
+    d.mass_a = g.mass_a;
     return d;
 }
 
 template <>
 GridData<double> grid_data<double>(const GridOp& g, double shift_re, double shift_im) {
-    GridData<double> d;
+    GridData<double> d{};
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.plane = static_cast<int64_t>(g.nx) * g.ny;
     d.N = g.N;
@@ -391,6 +392,7 @@ GridData<double> grid_data<double>(const GridOp& g, double shift_re, double shif
     d.inv_h2 = 1.0 / (g.h * g.h);
     d.shift_re = shift_re;
     d.shift_im = shift_im;
+    d.mass_a = g.mass_a;
     return d;
 }
 
@@ -422,9 +424,10 @@ bool stencil_wave_path(const GridOp& g, bool fp64) {
     const int n_tab = g.idx_hi - g.idx_lo + 1;   // the table slice the grid's indices span
     // the wavefront kernel addresses one right-hand side with 32-bit buffer
     // offsets: its byte size must stay below 2^31
-    const int ry = g.plain_ry[fp64 ? 1 : 0];
-    const size_t ring = g.kernel_variant == 2 ? static_cast<size_t>(2 * (4 * ry + 2) * 64) * (fp64 ? 16 : 8) : 0;
-    return (g.kernel_variant == 0 || g.kernel_variant == 2) && n_tab > 0 &&
+    const int ry = g.mass_a ? 1 : g.plain_ry[fp64 ? 1 : 0];
+    const size_t ring = g.kernel_variant == 2 ? wave_ring_bytes(ry, 1, fp64, g.mass_a != 0) : 0;
+    // the first mass form runs on the wavefront kernels only
+    return (g.kernel_variant == 0 || g.kernel_variant == 2 || g.mass_a) && n_tab > 0 &&
            static_cast<int64_t>(g.N) * (fp64 ? 16 : 8) < (int64_t(1) << 31) &&
            wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit();
 }
@@ -460,7 +463,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     // work items in one launch).  Variant 1 keeps the LDS-tiled kernel below.
     const int n_tab = g.idx_hi - g.idx_lo + 1;
     const bool use_wave = stencil_wave_path(g, sizeof(R) == 8);
-    if (mode == MODE_JACOBI0 && !use_wave) return HELM27_EINVAL;   // wavefront kernel only
+    if ((mode == MODE_JACOBI0 || g.mass_a) && !use_wave) return HELM27_EINVAL;   // wavefront kernel only
     if (use_wave) {
         WaveArgs<R> w{};
         w.g = a.g;
@@ -478,7 +481,7 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
             RY = fp64 ? g.plain_ry[1] : (big && nrhs >= 2 ? 2 : (big ? 1 : 2));
             variant = 0;
             zc_set = 0;
-            const size_t ring = static_cast<size_t>(2 * (4 * RY + 2) * 64) * sizeof(typename V2<R>::T);
+            const size_t ring = wave_ring_bytes(g.mass_a ? 1 : RY, 1, fp64, g.mass_a != 0);
             if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit()) {
                 variant = 2;
                 zc_set = nrhs == 1 ? 32 : 16;
@@ -492,8 +495,12 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
         // 400x400x200 x 16 and 201x201x101 x 64: groups of 2 or 4 change the
         // time by -4 % to +4 %; the per-RHS cost is the row traffic of u
         // and y, not the per-point data the groups share)
+        if (g.mass_a) {   // first mass form: one row per wavefront (two spill registers)
+            RY = 1;
+            if (variant == 1) variant = 0;
+        }
         int NB = 1;
-        if (!fp64 && nrhs >= 2 && g.rhs_block > 1) {
+        if (!fp64 && nrhs >= 2 && g.rhs_block > 1 && !g.mass_a) {
             NB = g.rhs_block;
             const bool fits = static_cast<int64_t>(g.N) * 8 * NB < (int64_t(1) << 31) &&
                               wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + wave_ring_bytes(1, NB, fp64) <=

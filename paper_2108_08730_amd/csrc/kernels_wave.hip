@@ -30,9 +30,9 @@ size_t wave_ring_offset(int n_tab, int nz, bool fp64) {
     return (wave_lds_bytes(n_tab, nz, fp64) + 15) & ~static_cast<size_t>(15);
 }
 
-size_t wave_ring_bytes(int ry, int nb, bool fp64) {
+size_t wave_ring_bytes(int ry, int nb, bool fp64, bool mass_a) {
     const size_t rows = nb > 1 ? static_cast<size_t>(nb) * 6 : static_cast<size_t>(4 * ry + 2);
-    return 2 * rows * 64 * (fp64 ? 16 : 8);
+    return 2 * rows * 64 * (fp64 ? 16 : 8) * (mass_a ? 2 : 1);
 }
 
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64) {

@@ -282,7 +282,8 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     if (nx < 3 || ny < 3 || nz < 3 || !(h > 0) || !(freq > 0)) return HELM27_EINVAL;
     const int wmode = flags & 0x3;
     if (wmode == 3) return HELM27_EINVAL;
-    if (flags & ~(0x3 | HELM27_STORE_C64 | HELM27_STORE_C128 | HELM27_EXTEND_TABLE)) return HELM27_EINVAL;
+    if (flags & ~(0x3 | HELM27_STORE_C64 | HELM27_STORE_C128 | HELM27_EXTEND_TABLE | HELM27_MASS_A))
+        return HELM27_EINVAL;
     if ((flags & HELM27_EXTEND_TABLE) && t->lambda < 0) return HELM27_EINVAL;   // fit settings unknown
     helm27_pml P{{8, 8, 8}, 1e-3, 0.0};
     if (pml) P = *pml;
@@ -310,6 +311,7 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
     op->freq = freq;
     op->flags = flags;
     op->table = *t;
+    g.mass_a = (flags & HELM27_MASS_A) ? 1 : 0;
     const double fh = freq * h;
 
     int st = HELM27_OK;

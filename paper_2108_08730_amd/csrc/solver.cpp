@@ -29,6 +29,7 @@ struct SolverState {
     // hierarchy (levels 1..L-1 owned here; level 0 is the operator's grid)
     int levels = 0;
     int req_levels = -1;             // levels asked for when the hierarchy was built
+    int req_coarse_table = 0;        // coarse-table choice it was built with
     std::vector<GridOp> coarse;
     int64_t coarse_clamped = 0;      // coarse rows outside their table
     int coarse_tables = 0;           // coarse levels with their own widened table
@@ -161,11 +162,11 @@ static int auto_levels(const GridOp& g) {
 
 // Coarse grids: node i of level l+1 sits on node 2i of level l.
 // Each coarse level rediscretises the operator at its own h_l = 2^l h, so its
-// rows have G = c/(f h_l).  They take the operator's table; if the operator
-// was assembled with HELM27_EXTEND_TABLE and that table does not reach the
-// level's G range, the level gets a table widened for it (same axis grid and
-// fit settings).  The rows that still fall outside are counted.
-static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_t s) {
+// rows have G = c/(f h_l).  They take the operator's table (clamped); with
+// `widen` (mg_coarse_table = 1) a level whose G range that table does not
+// reach gets a table widened for it (same axis grid and fit settings).  The
+// rows that still fall outside are counted.
+static int build_hierarchy(helm27_op* op, SolverState* S, int levels, bool widen_coarse, hipStream_t s) {
     free_hierarchy(S);
     S->coarse_clamped = 0;
     S->coarse_tables = 0;
@@ -180,7 +181,7 @@ static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_
     }
     int st = HELM27_OK;
     const helm27_table& base = op->table;
-    const bool widen = (op->flags & HELM27_EXTEND_TABLE) && base.lambda >= 0;
+    const bool widen = widen_coarse && base.lambda >= 0;
     S->coarse.reserve(levels > 1 ? levels - 1 : 0);
     for (int l = 1; l < levels; ++l) {
         const int cx = (prev->nx + 1) / 2, cy = (prev->ny + 1) / 2, cz = (prev->nz + 1) / 2;
@@ -195,6 +196,7 @@ static int build_hierarchy(helm27_op* op, SolverState* S, int levels, hipStream_
         c.omega = prev->omega;
         c.R = prev->R;
         c.c_ref = prev->c_ref;
+        c.mass_a = prev->mass_a;
         for (int a = 0; a < 3; ++a) {
             c.npml[a] = 0;
             c.pml_lo[a] = prev->pml_lo[a];
@@ -683,14 +685,15 @@ static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, con
                       helm27_solve_stats* stats, hipStream_t s) {
     SolverState* S = static_cast<SolverState*>(op->solver);
     const int want_levels = o->mg_levels > 0 ? o->mg_levels : (o->mg_levels < 0 ? auto_levels(op->g) : 0);
-    if (want_levels != S->req_levels) {
+    if (want_levels != S->req_levels || o->mg_coarse_table != S->req_coarse_table) {
         free_workspace(S);
         free_hierarchy(S);
         if (want_levels > 0) {
-            const int st = build_hierarchy(op, S, want_levels, s);
+            const int st = build_hierarchy(op, S, want_levels, o->mg_coarse_table == 1, s);
             if (st) return st;
         }
         S->req_levels = want_levels;
+        S->req_coarse_table = o->mg_coarse_table;
     }
     const int prec = o->precision == HELM27_C128 ? 8 : 4;
     int st = ensure_workspace(op, S, nrhs, o->restart, prec);
@@ -793,6 +796,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->mg_coarse_sweeps = 3;
     o->use_graph = 1;
     o->reorth_always = 0;
+    o->mg_coarse_table = 0;
     o->verbose = 0;
 }
 
@@ -800,7 +804,8 @@ static int check_opts(const helm27_solve_opts* o) {
     if (!(o->tol > 0) || o->restart < 1 || o->restart > 63 || o->max_inner < 1 || o->max_outer < 0 ||
         !(o->inner_tol > 0) || o->inner_tol >= 1 || (o->precision != HELM27_C64 && o->precision != HELM27_C128) ||
         o->mg_levels < -1 || o->mg_levels > 8 || o->mg_pre < 0 || o->mg_post < 0 || o->mg_coarse_sweeps < 0 ||
-        !(o->mg_omega > 0) || !std::isfinite(o->mg_shift) || !std::isfinite(o->mg_shift_re))
+        !(o->mg_omega > 0) || !std::isfinite(o->mg_shift) || !std::isfinite(o->mg_shift_re) ||
+        (o->mg_coarse_table != 0 && o->mg_coarse_table != 1))
         return HELM27_EINVAL;
     return HELM27_OK;
 }

@@ -30,6 +30,7 @@ struct GridData {
     R omega2;                      // omega^2 (k^2 = omega^2 / c^2)
     R inv_h2;                      // 1 / h^2
     R shift_re, shift_im;          // mass scaled by (shift_re + i shift_im); (1, 0) = physical
+    int mass_a;                    // 1: first consistent-mass form (bulk modulus of each neighbour)
 };
 
 template <typename R>
@@ -90,7 +91,8 @@ int frame_rows();
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64);
 size_t wave_ring_offset(int n_tab, int nz, bool fp64);
 // LDS bytes of the block kernel's row ring: two planes of 4 ry + 2 rows per
-// right-hand side of a wavefront (nb: 2 or 4 take one row, 6 rows each)
-size_t wave_ring_bytes(int ry, int nb, bool fp64);
+// right-hand side of a wavefront (nb: 2 or 4 take one row, 6 rows each);
+// twice that with the first mass form (v = k^2 u rows beside the u rows)
+size_t wave_ring_bytes(int ry, int nb, bool fp64, bool mass_a = false);
 
 }  // namespace h27

@@ -204,10 +204,29 @@ struct Meta {
     typename V2<R>::T b[NR];
 };
 
-template <typename R, int NR>
+// plane sums of a box tile: centre, 4-face sum and 4-diagonal sum of u and,
+// for the first mass form (MA), of v = k^2 u
+template <typename R, int NR, bool MA = false>
 struct BoxPlane {
     Cx<R> c[NR], f[NR], e[NR];
+    Cx<R> cv[MA ? NR : 1], fv[MA ? NR : 1], ev[MA ? NR : 1];
 };
+
+// the rows of one plane a wavefront loads: u, and for the first mass form
+// the velocity at the same points
+template <typename R, int NL, bool MA>
+struct RowSlot {
+    typename V2<R>::T u[NL];
+    float c[MA ? NL : 1];
+};
+
+// k^2 = omega^2 / c^2 at a loaded point (0 where the point lies outside the
+// grid: the load returned c = 0 and u = 0 there)
+template <typename R>
+__device__ __forceinline__ R k2_at(R omega2, float c) {
+    const R cr = static_cast<R>(c);
+    return c > 0.0f ? omega2 * rcp_of(cr * cr) : R(0);
+}
 
 // the arrays of one work item (one right-hand side) as buffer resources
 template <typename R, int MODE>
@@ -267,11 +286,17 @@ struct ItemBuf {
 // others through a two-plane LDS ring, so each row is read from memory once
 // per block instead of once per tile that needs it (1 + 2/(4 RY) instead of
 // 1 + 2/RY loads per output row), at one barrier per plane.
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK>
+// MA: first consistent-mass form (Sec. 2.1, eq. 8): the mass term of row i
+// weighs neighbour j by its own bulk modulus, i.e. the row's mass stencil acts
+// on v = k^2 u with k^2 = omega^2 / c_j^2 taken at each loaded point, while
+// the stiffness acts on u; the rows' velocities are loaded with u (and v
+// shared through the ring beside u).
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, bool MA = false>
 __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                          typename V2<R>::T* ring, int tile, int zc, int rhs, int wave, int lane) {
     using V = typename V2<R>::T;
     constexpr unsigned SV = sizeof(V);
+    using Plane = BoxPlane<R, RY, MA>;
     constexpr int NL = BLK ? RY + 1 : RY + 2;   // rows this wavefront loads per plane
     constexpr int KB = 4 * RY + 2;              // rows of a block plane in the ring
     const GridData<R>& g = a.g;
@@ -286,6 +311,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     const int z1 = min(z0 + a.zchunk, g.nz);
     const int yend = a.py0 + a.ph;
     unsigned lo[NL];          // byte offsets of the loaded rows (kOff outside the grid)
+    unsigned lc[MA ? NL : 1]; // byte offsets of the loaded rows' velocities (MA)
     unsigned so[RY];          // byte offsets of the stored rows (kOff: no output)
     unsigned mo[RY];          // element offsets of the output rows (clamped, always valid)
 #pragma unroll
@@ -298,7 +324,9 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
         } else {
             yy = y0 - 1 + k;
         }
-        lo[k] = (use && inx && yy >= 0 && yy < g.ny) ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
+        const bool ok = use && inx && yy >= 0 && yy < g.ny;
+        lo[k] = ok ? static_cast<unsigned>(yy * g.nx + gx) * SV : kOff;
+        if constexpr (MA) lc[k] = ok ? static_cast<unsigned>(yy * g.nx + gx) * 4u : kOff;
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -309,8 +337,8 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     const ItemBuf<R, MODE> B_(a, rhs);
     const R sig = g.inv_h2;
 
-    auto output = [&](int zo, const Meta<R, RY>& M, const BoxPlane<R, RY>& A, const BoxPlane<R, RY>& B,
-                      const BoxPlane<R, RY>& C) __attribute__((always_inline)) {
+    auto output = [&](int zo, const Meta<R, RY>& M, const Plane& A, const Plane& B, const Plane& C)
+                      __attribute__((always_inline)) {
         const AxisNode<R> Z = zn[zo];
         const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
 #pragma unroll
@@ -326,7 +354,31 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
             const R cvr = static_cast<R>(M.c[r]);
             const R kap = g.omega2 * rcp_of(cvr * cvr);
             Cx<R> acc, diag;
-            if (Z.plain) {
+            if (MA && Z.plain) {
+                // stiffness on u, mass on v = k^2 u (k^2 already inside v)
+                const Cx<R> Fc = B.f[r] + A.c[r] + C.c[r];
+                const Cx<R> Ec = B.e[r] + A.f[r] + C.f[r];
+                const Cx<R> Co = A.e[r] + C.e[r];
+                const Cx<R> Fv = B.fv[r] + A.cv[r] + C.cv[r];
+                const Cx<R> Ev = B.ev[r] + A.fv[r] + C.fv[r];
+                const Cx<R> Cv = A.ev[r] + C.ev[r];
+                Cx<R> st = s[0] * B.c[r];
+                rmac(st, s[1], Fc);
+                rmac(st, s[2], Ec);
+                rmac(st, s[3], Co);
+                Cx<R> ms = m[0] * B.cv[r];
+                rmac(ms, m[1], Fv);
+                rmac(ms, m[2], Ev);
+                rmac(ms, m[3], Cv);
+                if (SHIFTED) {
+                    acc = st;
+                    cmac(acc, Cx<R>{g.shift_re, g.shift_im}, ms);
+                    diag = Cx<R>{s[0] + kap * g.shift_re * m[0], kap * g.shift_im * m[0]};
+                } else {
+                    acc = st + ms;
+                    diag = Cx<R>{s[0] + kap * m[0], R(0)};
+                }
+            } else if (Z.plain) {
                 const Cx<R> Fc = B.f[r] + A.c[r] + C.c[r];
                 const Cx<R> Ec = B.e[r] + A.f[r] + C.f[r];
                 const Cx<R> Co = A.e[r] + C.e[r];
@@ -358,10 +410,21 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
                 rmac(Sp, s[2], C.f[r]); rmac(Sp, s[3], C.e[r]);
                 rmac(S0, s[2], B.f[r]); rmac(S0, s[3], B.e[r]);
                 rmac(SX, x1, B.f[r]); rmac(SX, b2, B.e[r]);
-                Cx<R> Mm = m[1] * A.c[r], Mp = m[1] * C.c[r], MX = m[0] * B.c[r];
-                rmac(Mm, m[2], A.f[r]); rmac(Mm, m[3], A.e[r]);
-                rmac(Mp, m[2], C.f[r]); rmac(Mp, m[3], C.e[r]);
-                rmac(MX, m[1], B.f[r]); rmac(MX, m[2], B.e[r]);
+                // mass sums: of u (second form, k^2 of the row applied below)
+                // or of v = k^2 u (first form)
+                const Cx<R>* const Ac = MA ? A.cv : A.c;
+                const Cx<R>* const Af = MA ? A.fv : A.f;
+                const Cx<R>* const Ae = MA ? A.ev : A.e;
+                const Cx<R>* const Bc = MA ? B.cv : B.c;
+                const Cx<R>* const Bf = MA ? B.fv : B.f;
+                const Cx<R>* const Be = MA ? B.ev : B.e;
+                const Cx<R>* const Cc = MA ? C.cv : C.c;
+                const Cx<R>* const Cf = MA ? C.fv : C.f;
+                const Cx<R>* const Ce = MA ? C.ev : C.e;
+                Cx<R> Mm = m[1] * Ac[r], Mp = m[1] * Cc[r], MX = m[0] * Bc[r];
+                rmac(Mm, m[2], Af[r]); rmac(Mm, m[3], Ae[r]);
+                rmac(Mp, m[2], Cf[r]); rmac(Mp, m[3], Ce[r]);
+                rmac(MX, m[1], Bf[r]); rmac(MX, m[2], Be[r]);
                 const Cx<R> tm{Z.tm_re, Z.tm_im}, tp{Z.tp_re, Z.tp_im};
                 const Cx<R> t0 = -(tm + tp);
                 const Cx<R> xz{Z.xi_re, Z.xi_im};
@@ -373,13 +436,14 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
                 Cx<R> ms = um2 * Mm;
                 cmac(ms, up2, Mp);
                 cmac(ms, xz, MX);
+                const R kr = MA ? R(1) : kap;   // first form: k^2 is inside v
                 if (SHIFTED) {
-                    const Cx<R> kc{kap * g.shift_re, kap * g.shift_im};
+                    const Cx<R> kc{kr * g.shift_re, kr * g.shift_im};
                     acc = st;
                     cmac(acc, kc, ms);
                 } else {
                     acc = st;
-                    rmac(acc, kap, ms);
+                    rmac(acc, kr, ms);
                 }
                 if (MODE == MODE_JACOBI || MODE == MODE_JACOBI0) {
                     const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
@@ -397,49 +461,88 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     // the per-point data of plane q + 1 are loaded two steps ahead of their
     // use; past the chunk the last plane is loaded again, so every step issues
     // the same loads and the waits stay exact.
-    auto step = [&](int q, bool out, const V (&Lc)[NL], V (&Ln)[NL], const BoxPlane<R, RY>& A,
-                    const BoxPlane<R, RY>& B, BoxPlane<R, RY>& C, const Meta<R, RY>& Mc, Meta<R, RY>& Mn)
-                    __attribute__((always_inline)) {
-        B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
-        B_.template load_meta<RY, ROWC>(min(q + 1, z1 - 1), mo, Mn);
-        Cx<R> U[RY + 2];
-        if constexpr (BLK) {
-            // ring[slot][row of the block plane][lane]; slot alternates with q
-            V* pl = ring + ((q & 1) * KB) * 64;
+    using Slot = RowSlot<R, NL, MA>;
+    // plane q of u (and, MA, of the velocity) into a slot; zero outside the grid
+    auto load = [&](int q, Slot& L) __attribute__((always_inline)) {
+        B_.load_plane(q, g.nz, lo, L.u);
+        if constexpr (MA) {
+            const bool in = q >= 0 && q < g.nz;
+            const Rsrc r = rsrc(g.c, in ? static_cast<unsigned>(g.N) * 4u : 0u);
+            const unsigned sq = in ? static_cast<unsigned>(q) * B_.plane * 4u : 0u;
 #pragma unroll
-            for (int k = 0; k < RY; ++k) pl[(1 + wave * RY + k) * 64 + lane] = Lc[k];
-            if (wave == 0) pl[lane] = Lc[RY];
-            if (wave == 3) pl[(KB - 1) * 64 + lane] = Lc[RY];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) {
-                const V v = pl[(wave * RY + k) * 64 + lane];
-                U[k] = Cx<R>{v.x, v.y};
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < RY + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
+            for (int k = 0; k < NL; ++k) L.c[k] = bld_f32(r, lc[k], sq);
         }
+    };
+    // sums of one plane's rows (centre, faces, diagonals)
+    auto sums = [&](const Cx<R> (&U)[RY + 2], Cx<R>* pc, Cx<R>* pf, Cx<R>* pe) __attribute__((always_inline)) {
         Cx<R> sx[RY + 2];
 #pragma unroll
         for (int k = 0; k < RY + 2; ++k) sx[k] = nxt_g<64>(U[k]) + prv_g<64>(U[k]);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            C.c[r] = U[r + 1];
-            C.f[r] = sx[r + 1] + U[r] + U[r + 2];
-            C.e[r] = sx[r] + sx[r + 2];
+            pc[r] = U[r + 1];
+            pf[r] = sx[r + 1] + U[r] + U[r + 2];
+            pe[r] = sx[r] + sx[r + 2];
         }
+    };
+    auto step = [&](int q, bool out, const Slot& Lc, Slot& Ln, const Plane& A, const Plane& B, Plane& C,
+                    const Meta<R, RY>& Mc, Meta<R, RY>& Mn) __attribute__((always_inline)) {
+        load(min(q + 2, z1), Ln);
+        B_.template load_meta<RY, ROWC>(min(q + 1, z1 - 1), mo, Mn);
+        Cx<R> U[RY + 2];
+        Cx<R> Vv[MA ? RY + 2 : 1];
+        if constexpr (BLK) {
+            // ring[slot][row of the block plane][lane]; slot alternates with q;
+            // (MA) the v rows follow the u rows of the slot
+            V* pl = ring + ((q & 1) * KB * (MA ? 2 : 1)) * 64;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) pl[(1 + wave * RY + k) * 64 + lane] = Lc.u[k];
+            if (wave == 0) pl[lane] = Lc.u[RY];
+            if (wave == 3) pl[(KB - 1) * 64 + lane] = Lc.u[RY];
+            if constexpr (MA) {
+                V* pv = pl + KB * 64;
+                auto kv = [&](int k) {
+                    const R k2 = k2_at<R>(g.omega2, Lc.c[k]);
+                    V w;
+                    w.x = k2 * Lc.u[k].x;
+                    w.y = k2 * Lc.u[k].y;
+                    return w;
+                };
+#pragma unroll
+                for (int k = 0; k < RY; ++k) pv[(1 + wave * RY + k) * 64 + lane] = kv(k);
+                if (wave == 0) pv[lane] = kv(RY);
+                if (wave == 3) pv[(KB - 1) * 64 + lane] = kv(RY);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < RY + 2; ++k) {
+                const V v = pl[(wave * RY + k) * 64 + lane];
+                U[k] = Cx<R>{v.x, v.y};
+                if constexpr (MA) {
+                    const V w = pl[(KB + wave * RY + k) * 64 + lane];
+                    Vv[k] = Cx<R>{w.x, w.y};
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RY + 2; ++k) {
+                U[k] = Cx<R>{Lc.u[k].x, Lc.u[k].y};
+                if constexpr (MA) Vv[k] = k2_at<R>(g.omega2, Lc.c[k]) * U[k];
+            }
+        }
+        sums(U, C.c, C.f, C.e);
+        if constexpr (MA) sums(Vv, C.cv, C.fv, C.ev);
         if (out) output(q - 1, Mc, A, B, C);
     };
 
     // slot k % 3 (k = q - z0 + 1) holds the loads, the plane sums and the
     // per-point data of plane q
-    V L0[NL], L1[NL], L2[NL];
-    BoxPlane<R, RY> P0, P1, P2;
+    Slot L0, L1, L2;
+    Plane P0, P1, P2;
     Meta<R, RY> M0, M1, M2;
     if (BLK) __syncthreads();   // the previous item's last ring reads are done
-    B_.load_plane(z0 - 1, g.nz, lo, L0);
-    B_.load_plane(z0, g.nz, lo, L1);
+    load(z0 - 1, L0);
+    load(z0, L1);
     // planes z0 - 1 and z0 enter without an output; then one output per step
     step(z0 - 1, false, L0, L2, P1, P2, P0, M2, M1);
     step(z0, false, L1, L0, P2, P0, P1, M0, M2);
@@ -713,14 +816,18 @@ __device__ __forceinline__ Factors<R> factors(const AxisNode<R>& n) {
     return f;
 }
 
-template <typename R, int NR>
+// contractions of a frame plane; with the first mass form (MA) the mass ones
+// (a, d, e) are also taken of v = k^2 u (av, d, e) while the stiffness keeps a of u
+template <typename R, int NR, bool MA = false>
 struct FramePlane {
     Cx<R> a[NR], b[NR], c[NR], d[NR], e[NR], u[NR];
+    Cx<R> av[MA ? NR : 1];
 };
 
-template <typename R, int MODE, bool SHIFTED, int RQ, int LW, bool ROWC>
+template <typename R, int MODE, bool SHIFTED, int RQ, int LW, bool ROWC, bool MA = false>
 __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                            int fr, int ft, int zc, int rhs, int lane) {
+    using Plane = FramePlane<R, RQ, MA>;
     using V = typename V2<R>::T;
     constexpr unsigned SV = sizeof(V);
     constexpr bool QPLAIN = LW == 16;   // left / right strips: rows unstretched
@@ -741,10 +848,13 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
     Factors<R> FQ[RQ];
     Cx<R> xLQ[RQ];
     unsigned lo[RQ + 2], so[RQ], mo[RQ];
+    unsigned lcv[MA ? RQ + 2 : 1];   // velocity offsets of the loaded rows (MA)
 #pragma unroll
     for (int k = 0; k < RQ + 2; ++k) {
         const int qq = q0 - 1 + k;
-        lo[k] = (inl && qq >= 0 && qq < g.ny) ? static_cast<unsigned>(qq * g.nx + lc) * SV : kOff;
+        const bool ok = inl && qq >= 0 && qq < g.ny;
+        lo[k] = ok ? static_cast<unsigned>(qq * g.nx + lc) * SV : kOff;
+        if constexpr (MA) lcv[k] = ok ? static_cast<unsigned>(qq * g.nx + lc) * 4u : kOff;
     }
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
@@ -757,8 +867,8 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
     const ItemBuf<R, MODE> B_(a, rhs);
     const R sig = g.inv_h2;
 
-    auto output = [&](int zo, const Meta<R, RQ>& M, const FramePlane<R, RQ>& A, const FramePlane<R, RQ>& B,
-                      const FramePlane<R, RQ>& C) __attribute__((always_inline)) {
+    auto output = [&](int zo, const Meta<R, RQ>& M, const Plane& A, const Plane& B, const Plane& C)
+                      __attribute__((always_inline)) {
         const AxisNode<R> Z = zn[zo];
         const bool plainz = Z.plain != 0;
         const Factors<R> FZ = factors<R>(Z);
@@ -779,12 +889,16 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
             rmac(PTB, b2, B.b[r]); rmac(PTB, b3, B.c[r]);
             rmac(PTC, b2, C.b[r]); rmac(PTC, b3, C.c[r]);
             const R w1 = R(2) * m[1], w2 = R(4) * m[2], w3 = R(8) * m[3];
-            Cx<R> PUA = w1 * A.a[r], PUC = w1 * C.a[r];
+            // mass contractions: of u (second form) or of v = k^2 u (first form)
+            const Cx<R>* const Aa = MA ? A.av : A.a;
+            const Cx<R>* const Ba = MA ? B.av : B.a;
+            const Cx<R>* const Ca = MA ? C.av : C.a;
+            Cx<R> PUA = w1 * Aa[r], PUC = w1 * Ca[r];
             rmac(PUA, w2, A.d[r]); rmac(PUA, w3, A.e[r]);
             rmac(PUC, w2, C.d[r]); rmac(PUC, w3, C.e[r]);
             Cx<R> PXs = B.b[r];
             rmac(PXs, b2, B.c[r]);
-            Cx<R> PXm = m[0] * B.a[r];
+            Cx<R> PXm = m[0] * Ba[r];
             rmac(PXm, w1, B.d[r]); rmac(PXm, w2, B.e[r]);
             Cx<R> stiff, mass;
             if (plainz) {   // T_z = (1, -2, 1), X_z = 1, U_z = (1/2, 0, 1/2)
@@ -800,10 +914,11 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
                 cmac(mass, FZ.xi, PXm);
             }
             Cx<R> acc = sig * stiff;
+            const R kr = MA ? R(1) : kap;   // first form: k^2 is inside v
             if (SHIFTED) {
-                cmac(acc, Cx<R>{kap * g.shift_re, kap * g.shift_im}, mass);
+                cmac(acc, Cx<R>{kr * g.shift_re, kr * g.shift_im}, mass);
             } else {
-                rmac(acc, kap, mass);
+                rmac(acc, kr, mass);
             }
             Cx<R> diag = zero<R>();
             if (MODE == MODE_JACOBI || MODE == MODE_JACOBI0) {
@@ -824,36 +939,53 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
             bst(finish<R, MODE>(a.omega_j, acc, diag, B.u[r], bb), B_.ry, so[r], pso);
         }
     };
-    auto step = [&](int q, bool out, const V (&Lc)[RQ + 2], V (&Ln)[RQ + 2], const FramePlane<R, RQ>& A,
-                    const FramePlane<R, RQ>& B, FramePlane<R, RQ>& C, const Meta<R, RQ>& Mc, Meta<R, RQ>& Mn)
-                    __attribute__((always_inline)) {
-        B_.load_plane(min(q + 2, z1), g.nz, lo, Ln);
+    using Slot = RowSlot<R, RQ + 2, MA>;
+    auto load = [&](int q, Slot& L) __attribute__((always_inline)) {
+        B_.load_plane(q, g.nz, lo, L.u);
+        if constexpr (MA) {
+            const bool in = q >= 0 && q < g.nz;
+            const Rsrc r = rsrc(g.c, in ? static_cast<unsigned>(g.N) * 4u : 0u);
+            const unsigned sq = in ? static_cast<unsigned>(q) * B_.plane * 4u : 0u;
+#pragma unroll
+            for (int k = 0; k < RQ + 2; ++k) L.c[k] = bld_f32(r, lcv[k], sq);
+        }
+    };
+    auto step = [&](int q, bool out, const Slot& Lc, Slot& Ln, const Plane& A, const Plane& B, Plane& C,
+                    const Meta<R, RQ>& Mc, Meta<R, RQ>& Mn) __attribute__((always_inline)) {
+        load(min(q + 2, z1), Ln);
         B_.template load_meta<RQ, ROWC>(min(q + 1, z1 - 1), mo, Mn);
         Cx<R> U[RQ + 2];
 #pragma unroll
-        for (int k = 0; k < RQ + 2; ++k) U[k] = Cx<R>{Lc[k].x, Lc[k].y};
+        for (int k = 0; k < RQ + 2; ++k) U[k] = Cx<R>{Lc.u[k].x, Lc.u[k].y};
+        // the mass contractions act on W: u (second form) or v = k^2 u (first)
+        Cx<R> W[RQ + 2];
+#pragma unroll
+        for (int k = 0; k < RQ + 2; ++k) W[k] = MA ? k2_at<R>(g.omega2, Lc.c[MA ? k : 0]) * U[k] : U[k];
         Cx<R> RT[RQ + 2], RU[RQ + 2];
 #pragma unroll
         for (int k = 0; k < RQ + 2; ++k) {
             const Cx<R> vm = prv_g<LW>(U[k]), vp = nxt_g<LW>(U[k]);
             RT[k] = FL.tm * vm + FL.t0 * U[k] + FL.tp * vp;
-            RU[k] = FL.um * vm + FL.up * vp;
+            const Cx<R> wm = MA ? prv_g<LW>(W[k]) : vm, wp = MA ? nxt_g<LW>(W[k]) : vp;
+            RU[k] = FL.um * wm + FL.up * wp;
         }
 #pragma unroll
         for (int r = 0; r < RQ; ++r) {
             C.u[r] = U[r + 1];
             C.a[r] = xLQ[r] * U[r + 1];
+            if constexpr (MA) C.av[r] = xLQ[r] * W[r + 1];
             if (QPLAIN) {   // row factors T = (1, -2, 1), X = 1, U = (1/2, 0, 1/2)
                 const Cx<R> ys = U[r] + U[r + 2];
+                const Cx<R> ysw = W[r] + W[r + 2];
                 C.b[r] = RT[r + 1] + FL.xi * (ys - R(2) * U[r + 1]);
                 C.c[r] = RT[r] + RT[r + 2] - R(2) * RT[r + 1];
-                C.d[r] = RU[r + 1] + R(0.5) * (FL.xi * ys);
+                C.d[r] = RU[r + 1] + R(0.5) * (FL.xi * ysw);
                 C.e[r] = R(0.5) * (RU[r] + RU[r + 2]);
             } else {
                 const Factors<R>& Q = FQ[r];
                 C.b[r] = Q.xi * RT[r + 1] + FL.xi * (Q.tm * U[r] + Q.t0 * U[r + 1] + Q.tp * U[r + 2]);
                 C.c[r] = Q.tm * RT[r] + Q.t0 * RT[r + 1] + Q.tp * RT[r + 2];
-                C.d[r] = Q.xi * RU[r + 1] + FL.xi * (Q.um * U[r] + Q.up * U[r + 2]);
+                C.d[r] = Q.xi * RU[r + 1] + FL.xi * (Q.um * W[r] + Q.up * W[r + 2]);
                 C.e[r] = Q.um * RU[r] + Q.up * RU[r + 2];
             }
         }
@@ -862,11 +994,11 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
 
     // slot k % 3 (k = q - z0 + 1) holds the loads, the plane sums and the
     // per-point data of plane q
-    V L0[RQ + 2], L1[RQ + 2], L2[RQ + 2];
-    FramePlane<R, RQ> P0, P1, P2;
+    Slot L0, L1, L2;
+    Plane P0, P1, P2;
     Meta<R, RQ> M0, M1, M2;
-    B_.load_plane(z0 - 1, g.nz, lo, L0);
-    B_.load_plane(z0, g.nz, lo, L1);
+    load(z0 - 1, L0);
+    load(z0, L1);
     step(z0 - 1, false, L0, L2, P1, P2, P0, M2, M1);
     step(z0, false, L1, L0, P2, P0, P1, M0, M2);
     int q = z0 + 1;
@@ -884,7 +1016,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
 // NB > 1 (FP32 block tiles, one row per wavefront): box items take NB
 // right-hand sides per wavefront (box_item_nb); frame items run their NB
 // right-hand sides one after another.
-template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB>
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 void wave27_kernel(WaveArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -931,12 +1063,12 @@ void wave27_kernel(WaveArgs<R> a) {
                 int k = 0;
                 while (k < 3 && tile >= a.fstart[k + 1]) ++k;
                 if (a.flx[k])
-                    frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                    frame_item<R, MODE, SHIFTED, RQ, 64, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
                 else
-                    frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                    frame_item<R, MODE, SHIFTED, RQ, 16, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
             } else {
-                box_item<R, MODE, SHIFTED, RY, ROWC, false>(a, tab, zn, ring, tile - a.n_frame, zc, rhs, wave,
-                                                            lane);
+                box_item<R, MODE, SHIFTED, RY, ROWC, false, MA>(a, tab, zn, ring, tile - a.n_frame, zc, rhs, wave,
+                                                                lane);
             }
         }
     } else {
@@ -960,17 +1092,17 @@ void wave27_kernel(WaveArgs<R> a) {
                     const int nv = min(NB, a.nrhs - rhs);
                     for (int v = 0; v < nv; ++v) {
                         if (a.flx[k])
-                            frame_item<R, MODE, SHIFTED, RQ, 64, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
+                            frame_item<R, MODE, SHIFTED, RQ, 64, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
                                                                        lane);
                         else
-                            frame_item<R, MODE, SHIFTED, RQ, 16, ROWC>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
+                            frame_item<R, MODE, SHIFTED, RQ, 16, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
                                                                        lane);
                     }
                 }
             } else if constexpr (NB > 1) {
                 box_item_nb<R, MODE, SHIFTED, ROWC, NB>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
             } else {
-                box_item<R, MODE, SHIFTED, RY, ROWC, true>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
+                box_item<R, MODE, SHIFTED, RY, ROWC, true, MA>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
             }
         }
     }
@@ -1000,23 +1132,35 @@ inline int resident_blocks(const void* fn, size_t lds) {
     return blocks;
 }
 
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, int NB>
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, int NB, bool MA = false>
 inline int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
     constexpr int RQ = FrameRows<R>::value;
-    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB>);
+    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA>);
     const int n_tab = ROWC ? 0 : a.n_tab;
     const size_t lds = wave_ring_offset(n_tab, a.g.nz, sizeof(R) == 8) +
-                       (BLK ? wave_ring_bytes(RY, NB, sizeof(R) == 8) : 0);
+                       (BLK ? wave_ring_bytes(RY, NB, sizeof(R) == 8, MA) : 0);
     int blocks = BLK ? a.n_items : (a.n_items + (kBlock / 64) - 1) / (kBlock / 64);
     const int cap = resident_blocks(fn, lds);
     if (cap <= 0) return HELM27_EDEVICE;
     if (blocks > cap) blocks = cap;
-    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB>, dim3(blocks), dim3(kBlock), lds, s, a));
+    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA>, dim3(blocks), dim3(kBlock), lds, s,
+                         a));
     return HELM27_OK;
 }
 
 template <typename R, int MODE, bool SHIFTED, int RY>
 inline int launch_wave_ry(const WaveArgs<R>& a, hipStream_t s) {
+    if (a.g.mass_a) {   // first mass form: one right-hand side and one row per wavefront
+        if constexpr (RY == 1) {
+            if (a.nb > 1) return HELM27_EINVAL;
+            if (a.blk)
+                return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true, true, 1, true>(a, s)
+                                   : launch_wave_k<R, MODE, SHIFTED, RY, false, true, 1, true>(a, s);
+            return a.g.rowcoef ? launch_wave_k<R, MODE, SHIFTED, RY, true, false, 1, true>(a, s)
+                               : launch_wave_k<R, MODE, SHIFTED, RY, false, false, 1, true>(a, s);
+        }
+        return HELM27_EINVAL;
+    }
     if (a.nb > 1) {   // several right-hand sides per box wavefront: FP32 block tiles, one row
         if constexpr (sizeof(R) == 4 && RY == 1) {
             if (!a.blk) return HELM27_EINVAL;

@@ -1,0 +1,136 @@
+"""GPU parity of the first consistent-mass form (HELM27_MASS_A) against the
+oracle.
+
+Sec. 2.1 (eq. 8) gives two consistent-mass forms: the first divides each
+neighbour's pressure by that neighbour's bulk modulus, the second by the
+collocation point's.  With HELM27_MASS_A the operator is S + M diag(k^2)
+(row i's mass weights, column j's k^2); the oracle builds it from its pinned
+``assemble(mass_form="a")``.  Bars as for the second form: CSR structure
+bit-exact and values <= 1e-12, FP64 apply <= 1e-12, FP32 apply <= 1e-5
+(recompute and stored), solves certified by the oracle's FP64 residual.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator as O
+from oracle import solve as S
+from oracle import table as T
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CASES = [
+    ((77, 37, 19), (4, 3, 2), 6.0, 25.0),
+    ((131, 70, 11), (8, 8, 3), 8.0, 25.0),
+    ((152, 12, 10), (8, 3, 2), 6.0, 25.0),
+    ((20, 5, 6), (2, 2, 2), 5.0, 25.0),
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2108_08730_amd import api
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    return api.Context(0)
+
+
+@pytest.fixture(scope="module")
+def oracle_table():
+    Gs, W = T.build_table(3.0, 20.0, 0.05, 1e-3)
+    return Gs, W, T.complete_weights(W)
+
+
+@pytest.fixture(scope="module")
+def table(ctx, oracle_table):
+    return ctx.table_from_weights(3.0, 0.05, oracle_table[1])
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _model(dims, h, seed=11):
+    c = synth.random_field_model(dims, h, seed=seed)
+    c[c.shape[0] // 2:] *= np.float32(1.3)   # a sharp jump: neighbouring k^2 differ strongly
+    return c
+
+
+def _weights(c, f, h, W7, mode="GA"):
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, len(W7))
+    nz, ny, nx = c.shape
+    return O.row_weights(mode, idx, W7, fixed_w=W7[0], dims=(nx, ny, nz))
+
+
+@pytest.mark.parametrize("dims,npml,f,h", CASES[:2])
+def test_mass_a_csr_export(ctx, table, oracle_table, dims, npml, f, h):
+    c = _model(dims, h)
+    op = ctx.assemble(table, c, h, f, npml=npml, mass_form="a")
+    ip, ind, val = op.csr()
+    ipo, indo, valo, _ = O.assemble_csr(c, f, h, npml, _weights(c, f, h, oracle_table[2]), mass_form="a")
+    assert np.array_equal(ip, ipo) and np.array_equal(ind, indo)
+    assert np.max(np.abs(val - valo)) <= 1e-12 * np.max(np.abs(valo))
+
+
+@pytest.mark.parametrize("dims,npml,f,h", CASES)
+@pytest.mark.parametrize("variant", [0, 2])
+def test_mass_a_apply(ctx, table, oracle_table, dims, npml, f, h, variant):
+    """Both wavefront kernel variants, 1 and 3 right-hand sides, FP64 and FP32,
+    recompute and stored coefficients; the two forms really differ here."""
+    c = _model(dims, h)
+    op = ctx.assemble(table, c, h, f, npml=npml, mass_form="a", store=("c64", "c128"))
+    op.set_kernel_variant(variant)
+    w = _weights(c, f, h, oracle_table[2])
+    A = O.assemble(c, f, h, npml, w, mass_form="a")
+    Ab = O.assemble(c, f, h, npml, w, mass_form="b")
+    N = int(np.prod(dims))
+    for nrhs in (1, 3):
+        u = synth.random_vectors(N, nrhs, seed=5 + nrhs)
+        y_ref = (A @ u.T).T
+        assert _relerr((Ab @ u.T).T[0], y_ref[0]) > 1e-4
+        ud = torch.from_numpy(u).cuda()
+        y64 = op.apply(ud).cpu().numpy()
+        y64s = op.apply(ud, variant="stored").cpu().numpy()
+        y32 = op.apply(ud.to(torch.complex64)).cpu().numpy()
+        y32s = op.apply(ud.to(torch.complex64), variant="stored").cpu().numpy()
+        for r in range(nrhs):
+            assert _relerr(y64[r], y_ref[r]) <= 1e-12
+            assert _relerr(y64s[r], y_ref[r]) <= 1e-12
+            assert _relerr(y32[r], y_ref[r]) <= 1e-5
+            assert _relerr(y32s[r], y_ref[r]) <= 1e-5
+
+
+def test_mass_a_gam_weights(ctx, table, oracle_table):
+    """The first form with the 27-point-averaged weights ("GAm", Sec. 3.1)."""
+    dims, npml, f, h = (40, 23, 12), (3, 3, 2), 6.0, 25.0
+    c = _model(dims, h, seed=5)
+    op = ctx.assemble(table, c, h, f, npml=npml, weights="GAm", mass_form="a")
+    A = O.assemble(c, f, h, npml, _weights(c, f, h, oracle_table[2], "GAm"), mass_form="a")
+    u = synth.random_vectors(int(np.prod(dims)), 2, seed=8)
+    y_ref = (A @ u.T).T
+    ud = torch.from_numpy(u).cuda()
+    y64 = op.apply(ud).cpu().numpy()
+    y32 = op.apply(ud.to(torch.complex64)).cpu().numpy()
+    for r in range(2):
+        assert _relerr(y64[r], y_ref[r]) <= 1e-12
+        assert _relerr(y32[r], y_ref[r]) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_mass_a_solve_certified(ctx, table, oracle_table, precision):
+    """A solve of the first-form operator (its multigrid levels use the first
+    form too) certified by the oracle's FP64 residual and compared with the
+    oracle's direct solve."""
+    dims, npml, f, h = (16, 14, 12), 3, 6.0, 25.0
+    c = _model(dims, h, seed=4)
+    op = ctx.assemble(table, c, h, f, npml=npml, mass_form="a")
+    src = [(7, 6, 5), (8, 7, 4)]
+    u, st = op.solve(src, tol=1e-10, precision=precision)
+    assert st["converged"] == 1
+    A = O.assemble(c, f, h, npml, _weights(c, f, h, oracle_table[2]), mass_form="a")
+    b = S.point_source_rhs(dims, h, src)
+    ud = u.cpu().numpy()
+    assert np.all(S.relative_residual(A, ud.T, b) <= 1.01e-10)
+    ref = S.solve(A, b).T
+    for k in range(2):
+        assert _relerr(ud[k], ref[k]) < 1e-8

@@ -109,10 +109,10 @@ def test_extend_table_to_model_range(ctx, spacing, v0, v1, dv):
 def test_coarse_levels_get_widened_tables(ctx):
     """48 x 40 x 36 random field at 6 Hz (G 16.1..43.3) with a G-axis table
     over [5, 50]: the fine rows are all in the table; the third multigrid
-    level (G / 4 from 4.06) is not.  Without widening the solve reports its clamped
-    coarse rows; with HELM27_EXTEND_TABLE the coarse levels get tables of
-    their own and nothing clamps.  Both solves reach 1e-7 certified by the
-    oracle's FP64 residual."""
+    level (G / 4 from 4.06) is not.  With the default coarse weights the solve
+    reports its clamped coarse rows; with mg_coarse_table = 1 the coarse levels
+    get tables of their own and nothing clamps.  Both solves reach 1e-7
+    certified by the oracle's FP64 residual."""
     dims, npml, f, h = (48, 40, 36), 6, 6.0, 25.0
     c = synth.random_field_model(dims, h, seed=9)
     tab = ctx.build_table(5.0, 50.0, 0.05, 1e-3)
@@ -127,7 +127,7 @@ def test_coarse_levels_get_widened_tables(ctx):
     for ext in (False, True):
         op = ctx.assemble(tab, c, h, f, npml=npml, extend_table=ext)
         assert op.info()["n_clamped"] == 0 and op.info()["n_g"] == len(W7)
-        u, st = op.solve(src, tol=1e-7, mg_levels=3)
+        u, st = op.solve(src, tol=1e-7, mg_levels=3, mg_coarse_table=int(ext))
         assert st["converged"] == 1 and st["mg_levels"] == 3
         assert np.all(S.relative_residual(A, u.cpu().numpy().T, b) <= 1.01e-7)
         res[ext] = st
