@@ -150,8 +150,19 @@ def _k3(fz, fy, fx):
     return sp.kron(fz, sp.kron(fy, fx, format="csr"), format="csr")
 
 
+def complex_velocity(c, Q=None):
+    """Velocity with constant-Q attenuation (the paper's medium parameters
+    allow a complex bulk modulus): c (1 - i/(2Q)) for the exp(-i omega t)
+    convention, so that k = omega / c~ has a positive imaginary part and
+    outgoing waves decay; c itself without attenuation (Q None or inf)."""
+    c = np.asarray(c, dtype=np.float64)
+    if Q is None or not np.isfinite(Q):
+        return c
+    return c * (1.0 - 0.5j / Q)
+
+
 def assemble(c, f, h, npml, w_rows, omega=None, c_ref=None, R=1e-3, mass_form="b",
-             shift=0.0):
+             shift=0.0, Q=None):
     """Assemble A = M + S (Sec. 2.1) as a scipy sparse matrix (values only;
     use ``assemble_csr`` for the full 27-entry pattern).
 
@@ -163,6 +174,9 @@ def assemble(c, f, h, npml, w_rows, omega=None, c_ref=None, R=1e-3, mass_form="b
                (first consistent-mass form of Sec. 2.1)
     shift    : k^2 -> (1 + i shift) k^2 in the mass (complex-shifted operator
                used by the multigrid preconditioner; 0 for the physical one)
+    Q        : constant quality factor: k^2 = (omega / c~)^2 with the complex
+               velocity c~ = c (1 - i/(2Q)) (None: no attenuation); the table
+               index and the PML use the real c
     """
     c = np.asarray(c, dtype=np.float32).astype(np.float64)
     nz, ny, nx = c.shape
@@ -189,7 +203,7 @@ def assemble(c, f, h, npml, w_rows, omega=None, c_ref=None, R=1e-3, mass_form="b
     M3 = 8.0 * _k3(Uz, Uy, Ux)
 
     w = np.asarray(w_rows, np.float64)
-    k2 = (omega / c.ravel()) ** 2 * (1.0 + 1j * shift)
+    k2 = (omega / complex_velocity(c.ravel(), Q)) ** 2 * (1.0 + 1j * shift)
     D = lambda v: sp.diags([v], [0], format="csr")  # noqa: E731
     A = D(w[:, 0]) @ S1 + D(w[:, 1]) @ S2 + D(w[:, 2]) @ S3
     if mass_form == "b":
@@ -245,7 +259,7 @@ def _row_vec(M, r):
     return sp.csr_matrix(M.getrow(r))
 
 
-def assemble_rows(c, f, h, npml, w_rows, rows, omega=None, c_ref=None, R=1e-3, shift=0.0):
+def assemble_rows(c, f, h, npml, w_rows, rows, omega=None, c_ref=None, R=1e-3, shift=0.0, Q=None):
     """Selected rows of the same A as ``assemble`` (second mass form), for
     grids too large to assemble whole: row (i, j, k) of a Kronecker product
     kron(Z, kron(Y, X)) is kron(Z[k], kron(Y[j], X[i])), so each row is the
@@ -281,7 +295,7 @@ def assemble_rows(c, f, h, npml, w_rows, rows, omega=None, c_ref=None, R=1e-3, s
         m1 = 2.0 * (_k3(xz, xy, ux) + _k3(xz, uy, xx) + _k3(uz, xy, xx))
         m2 = 4.0 * (_k3(xz, uy, ux) + _k3(uz, xy, ux) + _k3(uz, uy, xx))
         m3 = 8.0 * _k3(uz, uy, ux)
-        k2 = (omega / cflat[r]) ** 2 * (1.0 + 1j * shift)
+        k2 = (omega / complex_velocity(cflat[r], Q)) ** 2 * (1.0 + 1j * shift)
         row = (w[0] * s1 + w[1] * s2 + w[2] * s3
                + k2 * (w[3] * m0 + w[4] * m1 + w[5] * m2 + w[6] * m3))
         out.append(row)

@@ -272,3 +272,30 @@ def test_mass_forms_entry_by_entry_heterogeneous(w7_table, form):
     assert np.abs((A - S) - M).max() <= 1e-13 * np.abs(M).max()
     other = _mass_entry_by_entry(c, f, h, npml, w, "b" if form == "a" else "a")
     assert np.abs(other - M).max() > 1e-3 * np.abs(M).max()
+
+
+def test_attenuation_dst_eigenvalues(w7_table):
+    """Constant-Q attenuation: in a uniform PML-free medium the operator is
+    still diagonalised by the 3D DST-I, now with eigenvalues of the symbol at
+    the complex wavenumber k~ = omega / (c (1 - i/(2Q))).  A conjugated factor
+    or a sign error in it moves every eigenvalue's imaginary part."""
+    Gs, W7 = w7_table
+    nx, ny, nz = 7, 6, 5
+    h, f, cv, Q = 20.0, 10.0, 2000.0, 30.0
+    c = synth.homogeneous((nx, ny, nz), cv)
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, len(Gs))
+    A = O.assemble(c, f, h, 0, O.row_weights("GA", idx, W7), Q=Q)
+    u = synth.random_vectors(nx * ny * nz, 1, 4)[0]
+    uh = dstn(u.reshape(nz, ny, nx), type=1, norm="ortho")
+    mz, my, mx = np.meshgrid(np.arange(1, nz + 1) * np.pi / (nz + 1),
+                             np.arange(1, ny + 1) * np.pi / (ny + 1),
+                             np.arange(1, nx + 1) * np.pi / (nx + 1), indexing="ij")
+    kt = 2 * math.pi * f / (cv * (1 - 0.5j / Q))
+    assert kt.imag > 0   # outgoing waves decay under exp(-i omega t)
+    lam = An.symbol(np.stack([mx, my, mz], -1) / h, h, kt, W7[idx.ravel()[0]])
+    y_ref = idstn(lam * uh, type=1, norm="ortho").ravel()
+    assert np.linalg.norm(A @ u - y_ref) / np.linalg.norm(y_ref) < 1e-14
+    # and it reduces to the unattenuated operator as Q grows
+    A0 = O.assemble(c, f, h, 0, O.row_weights("GA", idx, W7))
+    A9 = O.assemble(c, f, h, 0, O.row_weights("GA", idx, W7), Q=1e9)
+    assert abs(A9 - A0).max() <= 1e-8 * abs(A0).max()
