@@ -63,6 +63,8 @@ extern "C" {
 
 #define HELM27_RECOMPUTE 0    /* apply: coefficients rebuilt from table index + velocity */
 #define HELM27_STORED    1    /* apply: 27 stored complex coefficients per point */
+#define HELM27_STORED_T  2    /* apply the transpose A^T from the stored coefficients (adjoint
+                                 problems of waveform inversion, Sec. 1; A^H u = conj(A^T conj(u))) */
 
 /* assembly flags (helm27_assemble) */
 #define HELM27_WEIGHTS_GA     0x0   /* per-row table entry of the row's own G (Sec. 3.1 "GA") */
@@ -277,6 +279,13 @@ int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows
  * All compute the same operator.  Switches off the per-launch choice (see
  * helm27_tune).  Errors: EINVAL. */
 int helm27_set_kernel_variant(helm27_op* op, int variant);
+/* Constant-Q attenuation of the medium: k^2 = omega^2 / c~^2 with the complex
+ * velocity c~ = c (1 - i/(2Q)) (exp(-i omega t): outgoing waves decay), for
+ * every later apply, residual and solve of the operator (its stored
+ * coefficients are refilled, its multigrid hierarchy rebuilt; the table
+ * index and the PML keep the real velocity).  Q = 0 or infinite: none.
+ * Errors: EINVAL (Q negative or NaN), EDEVICE. */
+int helm27_set_attenuation(helm27_op* op, double Q);
 /* Right-hand sides per box wavefront of the FP32 recompute kernels: with
  * nb = 2 or 4 a wavefront computes one output row (62 columns) of nb
  * consecutive right-hand sides at once (block tiles of four wavefronts that
@@ -335,6 +344,12 @@ typedef struct {
                             coarse operators a poor correction and GMRES stagnates
                             (201x201x101 at 8 Hz: 811 steps with 0, no convergence in
                             30000 with 1) */
+    int    transpose;    /* 1: solve the transposed system A^T u = b (adjoint problems of
+                            waveform inversion, Sec. 1) with A^T applied from the stored
+                            coefficients (assemble with HELM27_STORE_C128, and also
+                            HELM27_STORE_C64 for the mixed precision; else EINVAL); the
+                            preconditioner is the multigrid of A, whose rows differ from
+                            A^T's only where the weights vary between neighbours */
 } helm27_solve_opts;
 
 typedef struct {
@@ -360,6 +375,19 @@ void helm27_solve_opts_default(helm27_solve_opts* opts);
  * returning.  Errors: EINVAL, ERANGE, ENOCONV, ENUMERIC, ENOMEM, EDEVICE. */
 int helm27_solve(helm27_op* op, const double* src, void* u, int nrhs,
                  const helm27_solve_opts* opts, helm27_solve_stats* stats, void* stream);
+
+/* Several operators solved at once -- typically one model at several
+ * frequencies (waveform inversion proceeds frequency by frequency, Sec. 1):
+ * ops[k] (distinct operators) with its point sources src[k] (host
+ * [nrhs[k]][5], as helm27_solve) into u[k] (device [nrhs[k]][N_k]
+ * complex128).  Each solve runs from its own host thread on its own stream,
+ * so the frequencies' kernels overlap on the device; each result is
+ * bit-identical to the same solve alone.  stats: [nops] or NULL.  Returns
+ * OK, ENOCONV if any solve stopped short of the tolerance, or the first
+ * other error.  Synchronises before returning.  Errors: EINVAL (null
+ * pointers, a repeated operator), ERANGE, ENUMERIC, ENOMEM, EDEVICE. */
+int helm27_solve_many(helm27_op* const* ops, int nops, const double* const* src, const int* nrhs,
+                      void* const* u, const helm27_solve_opts* opts, helm27_solve_stats* stats);
 
 /* Same with a general right-hand side: `b` device pointer [nrhs][N]
  * complex128 (the Xi-scaled system's right-hand side). */

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libhelm27.so")
 
 OK, EINVAL, ENOMEM, EADMIT, ENOCONV, ENUMERIC, EDEVICE, ERANGE, ENOTFOUND, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 C64, C128 = 1, 2
-RECOMPUTE, STORED = 0, 1
+RECOMPUTE, STORED, STORED_T = 0, 1, 2
 WEIGHTS_GA, WEIGHTS_FIXED, WEIGHTS_GAM = 0x0, 0x1, 0x2
 STORE_C64, STORE_C128 = 0x10, 0x20
 
@@ -49,7 +49,7 @@ class SolveOpts(C.Structure):
                 ("mg_levels", C.c_int), ("mg_shift", C.c_double), ("mg_pre", C.c_int),
                 ("mg_post", C.c_int), ("mg_omega", C.c_double), ("mg_coarse_sweeps", C.c_int),
                 ("use_graph", C.c_int), ("verbose", C.c_int), ("mg_shift_re", C.c_double),
-                ("reorth_always", C.c_int), ("mg_coarse_table", C.c_int)]
+                ("reorth_always", C.c_int), ("mg_coarse_table", C.c_int), ("transpose", C.c_int)]
 
 
 class IndexStats(C.Structure):
@@ -114,6 +114,10 @@ def _load():
         "helm27_set_kernel_variant": (C.c_int, [P, C.c_int]),
         "helm27_set_zchunk": (C.c_int, [P, C.c_int]),
         "helm27_set_rhs_block": (C.c_int, [P, C.c_int]),
+        "helm27_set_attenuation": (C.c_int, [P, C.c_double]),
+        "helm27_solve_many": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(C.POINTER(C.c_double)),
+                                        C.POINTER(C.c_int), C.POINTER(P), C.POINTER(SolveOpts),
+                                        C.POINTER(SolveStats)]),
         "helm27_set_rhs_order": (C.c_int, [P, C.c_int]),
         "helm27_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
         "helm27_solve_opts_default": (None, [C.POINTER(SolveOpts)]),

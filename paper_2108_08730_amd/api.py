@@ -125,7 +125,7 @@ class Operator:
             raise TypeError(u.dtype)
         if y is None:
             y = torch.empty_like(u)
-        var = L.RECOMPUTE if variant == "recompute" else L.STORED
+        var = {"recompute": L.RECOMPUTE, "stored": L.STORED, "stored_t": L.STORED_T}[variant]
         L.check(L.lib.helm27_apply(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(y.data_ptr()), u.shape[0], dt,
                                    var, _stream_handle(stream)), "apply")
         return y
@@ -144,6 +144,10 @@ class Operator:
     def set_rhs_block(self, nb):
         """Right-hand sides per box wavefront of FP32 launches: 1, 2, 4, or 0 (automatic)."""
         L.check(L.lib.helm27_set_rhs_block(self._h, nb), "set_rhs_block")
+
+    def set_attenuation(self, Q):
+        """Constant-Q attenuation, complex velocity c (1 - i/(2Q)); Q = 0: none."""
+        L.check(L.lib.helm27_set_attenuation(self._h, float(Q)), "set_attenuation")
 
     def set_rhs_order(self, order):
         """Multi-RHS work-item order: 2 right-hand side slowest, 1 fastest, 0 automatic."""
@@ -205,6 +209,33 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def solve_many(ops, sources, **opts):
+    """helm27_solve_many: ops[k] (distinct operators, e.g. one model at several
+    frequencies) with point sources sources[k]; returns ([u_k], [stats_k])."""
+    torch = _torch()
+    n = len(ops)
+    srcs, outs = [], []
+    for op, sl in zip(ops, sources):
+        a = np.zeros((len(sl), 5), np.float64)
+        for s, p in enumerate(sl):
+            a[s, :3] = p
+            a[s, 3] = 1.0
+        srcs.append(a)
+        outs.append(torch.empty((len(sl), op.N), dtype=torch.complex128, device="cuda"))
+    P = C.c_void_p
+    h_ops = (P * n)(*[op.handle for op in ops])
+    h_src = (C.POINTER(C.c_double) * n)(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in srcs])
+    h_n = (C.c_int * n)(*[a.shape[0] for a in srcs])
+    h_u = (P * n)(*[P(o.data_ptr()) for o in outs])
+    o = solve_opts(**opts)
+    st = (L.SolveStats * n)()
+    status = L.lib.helm27_solve_many(h_ops, n, h_src, h_n, h_u, C.byref(o), st)
+    if status not in (L.OK, L.ENOCONV):
+        L.check(status, "solve_many")
+    stats = [{f: getattr(st[k], f) for f, _ in L.SolveStats._fields_} for k in range(n)]
+    return outs, stats
 
 
 def _check_device_velocity(vel):

@@ -159,6 +159,7 @@ struct GridOp {
     int rhs_block = 0;                         // right-hand sides per box wavefront (FP32 block tiles):
                                                // 0 = automatic (1), 1, 2 or 4
     int mass_a = 0;                            // 1: first consistent-mass form (neighbour bulk modulus)
+    double att_re = 1.0, att_im = 0.0;         // attenuation factor of k^2: (1 - i/(2Q))^-2 (1 without)
     int rhs_order = 0;                         // work-item order of a multi-RHS launch: 0 = automatic
                                                // (right-hand side slowest), 1 = fastest, 2 = slowest
     bool auto_tile = true;                     // kernel variant, rows and z chunk chosen per launch from
@@ -242,5 +243,9 @@ int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* 
                         hipStream_t s);
 template <typename R>
 int launch_gam_average(const GridOp& g, EntryCoef<R>* rowcoef, hipStream_t s);
+// y = A^T u, or y = b - A^T u with b, from the stored coefficients
+template <typename R>
+int launch_apply_stored_t(const GridOp& g, const void* coef, const void* u, void* y, const void* b, int nrhs,
+                          hipStream_t s);
 
 }  // namespace h27

@@ -289,8 +289,9 @@ GridData<float> make_grid_data<float>(const GridOp& g, double shift_re, double s
     d.ax = g.d_ax_f[0]; d.ay = g.d_ax_f[1]; d.az = g.d_ax_f[2];
     d.omega2 = static_cast<float>(g.omega * g.omega);
     d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
-    d.shift_re = static_cast<float>(shift_re);
-    d.shift_im = static_cast<float>(shift_im);
+    // mass factor = requested shift x the medium's attenuation factor
+    d.shift_re = static_cast<float>(shift_re * g.att_re - shift_im * g.att_im);
+    d.shift_im = static_cast<float>(shift_re * g.att_im + shift_im * g.att_re);
     d.mass_a = g.mass_a;
     return d;
 }
@@ -305,8 +306,8 @@ GridData<double> make_grid_data<double>(const GridOp& g, double shift_re, double
     d.ax = g.d_ax_d[0]; d.ay = g.d_ax_d[1]; d.az = g.d_ax_d[2];
     d.omega2 = g.omega * g.omega;
     d.inv_h2 = 1.0 / (g.h * g.h);
-    d.shift_re = shift_re;
-    d.shift_im = shift_im;
+    d.shift_re = shift_re * g.att_re - shift_im * g.att_im;
+    d.shift_im = shift_re * g.att_im + shift_im * g.att_re;
     d.mass_a = g.mass_a;
     return d;
 }
@@ -369,6 +370,58 @@ int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* 
 }
 template int launch_apply_stored<float>(const GridOp&, const void*, const void*, void*, int, hipStream_t);
 template int launch_apply_stored<double>(const GridOp&, const void*, const void*, void*, int, hipStream_t);
+
+// Transposed stored-coefficient apply: y_i = sum_s A[i + off_s][i] u[i + off_s]
+// = sum_s coef[26 - s][i + off_s] u[i + off_s] (the entry of row j = i + off_s
+// towards i sits at the opposite offset), or with b: y = b - A^T u.  The
+// coefficients are read at the neighbour's index, as coalesced as u.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void apply_stored_t_kernel(GridData<R> g,
+                                                                const typename V2<R>::T* __restrict__ coef,
+                                                                const typename V2<R>::T* __restrict__ u,
+                                                                const typename V2<R>::T* __restrict__ b,
+                                                                typename V2<R>::T* __restrict__ y, int nrhs) {
+    const int64_t N = g.N;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(i % g.nx);
+        const int yy = static_cast<int>((i / g.nx) % g.ny);
+        const int z = static_cast<int>(i / g.plane);
+        const bool xm = x > 0, xp = x < g.nx - 1, ym = yy > 0, yp = yy < g.ny - 1, zm = z > 0, zp = z < g.nz - 1;
+        for (int r = 0; r < nrhs; ++r) {
+            const typename V2<R>::T* ur = u + static_cast<int64_t>(r) * N;
+            Cx<R> acc = zero<R>();
+#pragma unroll
+            for (int s = 0; s < 27; ++s) {
+                const int dz = s / 9 - 1, dy = (s / 3) % 3 - 1, dx = s % 3 - 1;
+                const bool ok = (dx < 0 ? xm : (dx > 0 ? xp : true)) && (dy < 0 ? ym : (dy > 0 ? yp : true)) &&
+                                (dz < 0 ? zm : (dz > 0 ? zp : true));
+                if (ok) {
+                    const int64_t j = i + dx + static_cast<int64_t>(g.nx) * dy + g.plane * dz;
+                    cmac(acc, ld<R>(coef + static_cast<int64_t>(26 - s) * N + j), ld<R>(ur + j));
+                }
+            }
+            if (b) acc = ld<R>(b + static_cast<int64_t>(r) * N + i) - acc;
+            st<R>(y + static_cast<int64_t>(r) * N + i, acc);
+        }
+    }
+}
+
+template <typename R>
+int launch_apply_stored_t(const GridOp& g, const void* coef, const void* u, void* y, const void* b, int nrhs,
+                          hipStream_t s) {
+    GridData<R> d = make_grid_data<R>(g, 1.0, 0.0);
+    const int64_t blocks = (g.N + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(apply_stored_t_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
+                       static_cast<const typename V2<R>::T*>(coef), static_cast<const typename V2<R>::T*>(u),
+                       static_cast<const typename V2<R>::T*>(b), static_cast<typename V2<R>::T*>(y), nrhs);
+    H27_CHECK_HIP(hipGetLastError());
+    return HELM27_OK;
+}
+template int launch_apply_stored_t<float>(const GridOp&, const void*, const void*, void*, const void*, int,
+                                          hipStream_t);
+template int launch_apply_stored_t<double>(const GridOp&, const void*, const void*, void*, const void*, int,
+                                           hipStream_t);
 
 // ---------------------------------------------------------------------------
 // "GAm": every row takes the mean of the table entries of its in-grid stencil

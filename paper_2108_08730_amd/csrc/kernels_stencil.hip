@@ -374,8 +374,9 @@ GridData<float> grid_data<float>(const GridOp& g, double shift_re, double shift_
     d.ax = g.d_ax_f[0]; d.ay = g.d_ax_f[1]; d.az = g.d_ax_f[2];
     d.omega2 = static_cast<float>(g.omega * g.omega);
     d.inv_h2 = static_cast<float>(1.0 / (g.h * g.h));
-    d.shift_re = static_cast<float>(shift_re);
-    d.shift_im = static_cast<float>(shift_im);
+    // mass factor = requested shift x the medium's attenuation factor
+    d.shift_re = static_cast<float>(shift_re * g.att_re - shift_im * g.att_im);
+    d.shift_im = static_cast<float>(shift_re * g.att_im + shift_im * g.att_re);
     d.mass_a = g.mass_a;
     return d;
 }
@@ -390,8 +391,8 @@ GridData<double> grid_data<double>(const GridOp& g, double shift_re, double shif
     d.ax = g.d_ax_d[0]; d.ay = g.d_ax_d[1]; d.az = g.d_ax_d[2];
     d.omega2 = g.omega * g.omega;
     d.inv_h2 = 1.0 / (g.h * g.h);
-    d.shift_re = shift_re;
-    d.shift_im = shift_im;
+    d.shift_re = shift_re * g.att_re - shift_im * g.att_im;
+    d.shift_im = shift_re * g.att_im + shift_im * g.att_re;
     d.mass_a = g.mass_a;
     return d;
 }
@@ -439,7 +440,8 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     const Tiling& t = g.tiling;
     StencilArgs<R> a{};
     a.g = grid_data<R>(g, shift_re, shift_im);
-    const bool shifted = !(shift_re == 1.0 && shift_im == 0.0);
+    const bool shifted = !(shift_re * g.att_re - shift_im * g.att_im == 1.0 &&
+                           shift_re * g.att_im + shift_im * g.att_re == 0.0);
     if (!a.g.entry || !a.g.ax || !a.g.ay || !a.g.az) return HELM27_EINVAL;
     a.px0 = t.plain_x0; a.py0 = t.plain_y0; a.pw = t.plain_w; a.ph = t.plain_h;
     a.ptx = t.n_plain_tiles_x > 0 ? t.n_plain_tiles_x : 1;

@@ -528,6 +528,16 @@ extern "C" int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int
             return launch_apply_stored<double>(op->g, op->d_coef_d, u, y, nrhs, s);
         }
     }
+    if (variant == HELM27_STORED_T) {
+        if (dtype == HELM27_C64) {
+            if (!op->d_coef_f) return HELM27_EINVAL;
+            return launch_apply_stored_t<float>(op->g, op->d_coef_f, u, y, nullptr, nrhs, s);
+        }
+        if (dtype == HELM27_C128) {
+            if (!op->d_coef_d) return HELM27_EINVAL;
+            return launch_apply_stored_t<double>(op->g, op->d_coef_d, u, y, nullptr, nrhs, s);
+        }
+    }
     return HELM27_EINVAL;
 }
 
@@ -618,6 +628,28 @@ extern "C" int helm27_set_kernel_variant(helm27_op* op, int variant) {
     if (!op || variant < 0 || variant > 2) return HELM27_EINVAL;
     op->g.kernel_variant = variant;
     op->g.auto_tile = false;
+    return HELM27_OK;
+}
+
+extern "C" int helm27_set_attenuation(helm27_op* op, double Q) {
+    if (!op || std::isnan(Q) || Q < 0) return HELM27_EINVAL;
+    // k^2 = omega^2 / c~^2 with c~ = c (1 - i/(2Q)): factor 1 / (1 - i/(2Q))^2
+    double re = 1.0, im = 0.0;
+    if (Q > 0 && std::isfinite(Q)) {
+        const double a = 1.0, b = -0.5 / Q;             // 1 - i/(2Q)
+        const double sr = a * a - b * b, si = 2.0 * a * b;   // (1 - i/(2Q))^2
+        const double d = sr * sr + si * si;
+        re = sr / d;
+        im = -si / d;
+    }
+    op->g.att_re = re;
+    op->g.att_im = im;
+    solver_free(op);   // coarse levels are rebuilt with the new factor
+    hipStream_t s = nullptr;
+    int st = HELM27_OK;
+    if (op->d_coef_f && (st = h27::launch_fill_stored<float>(op->g, op->d_coef_f, 1.0, 0.0, s))) return st;
+    if (op->d_coef_d && (st = h27::launch_fill_stored<double>(op->g, op->d_coef_d, 1.0, 0.0, s))) return st;
+    H27_CHECK_HIP(hipStreamSynchronize(s));
     return HELM27_OK;
 }
 

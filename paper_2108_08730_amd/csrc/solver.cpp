@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "krylov.h"
@@ -197,6 +198,8 @@ static int build_hierarchy(helm27_op* op, SolverState* S, int levels, bool widen
         c.R = prev->R;
         c.c_ref = prev->c_ref;
         c.mass_a = prev->mass_a;
+        c.att_re = prev->att_re;
+        c.att_im = prev->att_im;
         for (int a = 0; a < 3; ++a) {
             c.npml[a] = 0;
             c.pml_lo[a] = prev->pml_lo[a];
@@ -367,6 +370,19 @@ struct Ctx {
     hipStream_t s;
     int nrhs;
 };
+
+// the physical operator of the solve (MODE_APPLY: y = A x, MODE_RESID:
+// y = b - A x): the recompute kernels, or for the transposed problem the
+// stored coefficients read transposed
+template <typename R>
+static int phys_apply(const Ctx& c, int mode, const void* x, void* y, const void* b) {
+    if (c.o->transpose) {
+        const void* coef = sizeof(R) == 4 ? c.op->d_coef_f : c.op->d_coef_d;
+        if (!coef) return HELM27_EINVAL;
+        return launch_apply_stored_t<R>(c.op->g, coef, x, y, mode == MODE_RESID ? b : nullptr, c.nrhs, c.s);
+    }
+    return launch_stencil<R>(c.op->g, mode, 1.0, 0.0, x, y, b, 0.0, c.nrhs, c.s);
+}
 
 // omega D^-1 of the shifted operator on every level that has a Dv buffer:
 // the first-sweep kernel applied to b = 1 (recomputed when the shift, omega
@@ -559,7 +575,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
         if (first) {
             r = rhs;
         } else {
-            if ((st = launch_stencil<R>(G, MODE_RESID, 1.0, 0.0, x, S->w, rhs, 0.0, nrhs, c.s))) return st;
+            if ((st = phys_apply<R>(c, MODE_RESID, x, S->w, rhs))) return st;
             r = S->w;
         }
         if ((st = norms<R>(r, N, nrhs, S->d_partial, S->max_blocks, S->d_beta, c.s))) return st;
@@ -583,7 +599,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             void* vj = static_cast<char*>(S->V) + static_cast<size_t>(j) * vstride * eb;
             void* z = nullptr;
             if ((st = g ? precond_vin<R>(c, &z) : precond<R>(c, vj, &z))) return st;
-            if ((st = launch_stencil<R>(G, MODE_APPLY, 1.0, 0.0, z, S->w, nullptr, 0.0, nrhs, c.s))) return st;
+            if ((st = phys_apply<R>(c, MODE_APPLY, z, S->w, nullptr))) return st;
             // classical Gram-Schmidt: h = V^H w (and ||w||); w -= V h (and ||w||);
             // then, per right-hand side only where the first pass cancelled
             // more than 1 - 1/sqrt(2) of the norm: h2 = V^H w (h += h2 in the
@@ -711,7 +727,7 @@ static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, con
     bool converged = false;
     double maxrel = 0;
     for (;;) {
-        if ((st = launch_stencil<double>(G, MODE_RESID, 1.0, 0.0, u, S->r64, b, 0.0, nrhs, s))) return st;
+        if ((st = phys_apply<double>(c, MODE_RESID, u, S->r64, b))) return st;
         if ((st = norms<double>(S->r64, N, nrhs, S->d_partial, S->max_blocks, S->d_rn, s))) return st;
         if ((st = read_host(&rn, S->d_rn, nrhs, s))) return st;
         maxrel = 0;
@@ -797,6 +813,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->use_graph = 1;
     o->reorth_always = 0;
     o->mg_coarse_table = 0;
+    o->transpose = 0;
     o->verbose = 0;
 }
 
@@ -805,7 +822,7 @@ static int check_opts(const helm27_solve_opts* o) {
         !(o->inner_tol > 0) || o->inner_tol >= 1 || (o->precision != HELM27_C64 && o->precision != HELM27_C128) ||
         o->mg_levels < -1 || o->mg_levels > 8 || o->mg_pre < 0 || o->mg_post < 0 || o->mg_coarse_sweeps < 0 ||
         !(o->mg_omega > 0) || !std::isfinite(o->mg_shift) || !std::isfinite(o->mg_shift_re) ||
-        (o->mg_coarse_table != 0 && o->mg_coarse_table != 1))
+        (o->mg_coarse_table != 0 && o->mg_coarse_table != 1) || (o->transpose != 0 && o->transpose != 1))
         return HELM27_EINVAL;
     return HELM27_OK;
 }
@@ -911,4 +928,54 @@ size_t h27::solve_footprint(int64_t N, int nrhs, int restart, int precision, int
     bytes += static_cast<double>(N) * 7.0;                      // coarse grids (velocity + index + ...)
     bytes += static_cast<double>(nrhs) * (restart + 2) * 1024 * 16;   // reduction partials
     return static_cast<size_t>(bytes * 1.05) + (16u << 20);
+}
+
+// Several operators at once (one model at several frequencies, Sec. 1):
+// every solve runs from its own host thread on its own stream, so their
+// kernels overlap on the device; each operator's solve is the same sequence
+// of launches as alone, so its result is bit-identical to a lone solve.
+extern "C" int helm27_solve_many(helm27_op* const* ops, int nops, const double* const* src, const int* nrhs,
+                                 void* const* u, const helm27_solve_opts* opts, helm27_solve_stats* stats) {
+    if (!ops || !src || !nrhs || !u || nops <= 0) return HELM27_EINVAL;
+    for (int k = 0; k < nops; ++k) {
+        if (!ops[k] || !src[k] || !u[k] || nrhs[k] <= 0) return HELM27_EINVAL;
+        for (int j = 0; j < k; ++j)
+            if (ops[j] == ops[k]) return HELM27_EINVAL;   // one solve per operator at a time
+    }
+    int dev = 0;
+    H27_CHECK_HIP(hipGetDevice(&dev));
+    std::vector<int> status(nops, HELM27_OK);
+    std::vector<hipStream_t> streams(nops, nullptr);
+    for (int k = 0; k < nops; ++k) {
+        if (hipSetDevice(ops[k]->ctx->device) != hipSuccess || hipStreamCreate(&streams[k]) != hipSuccess) {
+            for (int j = 0; j < k; ++j) hipStreamDestroy(streams[j]);
+            (void)hipSetDevice(dev);
+            return HELM27_EDEVICE;
+        }
+    }
+    auto work = [&](int k) {
+        if (hipSetDevice(ops[k]->ctx->device) != hipSuccess) {
+            status[k] = HELM27_EDEVICE;
+            return;
+        }
+        status[k] = helm27_solve(ops[k], src[k], u[k], nrhs[k], opts, stats ? &stats[k] : nullptr, streams[k]);
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (int k = 1; k < nops; ++k) pool.emplace_back(work, k);
+    } catch (...) {
+        for (std::thread& t : pool) t.join();
+        for (hipStream_t st : streams) hipStreamDestroy(st);
+        (void)hipSetDevice(dev);
+        return HELM27_ENOMEM;
+    }
+    work(0);
+    for (std::thread& t : pool) t.join();
+    for (hipStream_t st : streams) hipStreamDestroy(st);
+    (void)hipSetDevice(dev);
+    for (int k = 0; k < nops; ++k)
+        if (status[k] != HELM27_OK && status[k] != HELM27_ENOCONV) return status[k];
+    for (int k = 0; k < nops; ++k)
+        if (status[k] == HELM27_ENOCONV) return HELM27_ENOCONV;
+    return HELM27_OK;
 }

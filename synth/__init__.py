@@ -12,7 +12,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "homogeneous", "gradient_z", "random_field_model", "surface_sources",
+    "homogeneous", "gradient_z", "random_field_model", "smooth_random_model", "surface_sources",
     "random_vectors", "serving_requests", "WORKLOADS",
 ]
 
@@ -38,7 +38,8 @@ def random_field_model(dims, h, seed, c_top=1500.0, c_bottom=4500.0, std=300.0,
     depth, a smooth Gaussian random field (white noise smoothed by
     exp(-r^2 / corr^2), rescaled to ``std``), ``n_planes`` dipping planes that
     multiply the velocity below them by U(jump), one ellipsoidal body of
-    ``body_c`` at the centre, clipped.  float32 [nz, ny, nx]."""
+    ``body_c`` at the centre (semi-axes at most a quarter of the extent),
+    clipped.  float32 [nz, ny, nx]."""
     nx, ny, nz = dims
     rng = np.random.Generator(np.random.PCG64(seed))
     z = np.arange(nz) * h
@@ -69,12 +70,36 @@ def random_field_model(dims, h, seed, c_top=1500.0, c_bottom=4500.0, std=300.0,
         x0, y0 = x[-1] / 2, y[-1] / 2
         s = nvec[0] * (X - x0) + nvec[1] * (Y - y0) + nvec[2] * (Z - depth)
         c = np.where(s > 0, c * rng.uniform(*jump), c)
-    # ellipsoidal body
+    # ellipsoidal body; its semi-axes are capped at a quarter of the model's
+    # extent so that small grids keep their background (the 1000 x 750 x 400 m
+    # body of the paper-sized grids would fill them)
     cx, cy, cz = x[-1] / 2, y[-1] / 2, z[-1] / 2
-    ax, ay, az_ = body_axes
+    ax, ay, az_ = (min(b, 0.25 * max(e, h)) for b, e in zip(body_axes, (x[-1], y[-1], z[-1])))
     inside = ((X - cx) / ax) ** 2 + ((Y - cy) / ay) ** 2 + ((Z - cz) / az_) ** 2 <= 1.0
     c = np.where(inside, body_c, c)
     return np.clip(c, *clip).astype(np.float32)
+
+
+def smooth_random_model(dims, h, seed, c_range=(1600.0, 2800.0), corr=None):
+    """A small heterogeneous model whose velocity spans ``c_range`` exactly:
+    white noise (PCG64) smoothed by exp(-r^2 / corr^2) (corr = 3 h by
+    default), mapped linearly onto the range.  For grids too small for the
+    random-field model, whose interfaces and body saturate them.  float32
+    [nz, ny, nx]."""
+    nx, ny, nz = dims
+    corr = 3.0 * h if corr is None else corr
+    rng = np.random.Generator(np.random.PCG64(seed))
+    noise = rng.standard_normal((nz, ny, nx))
+    kz = np.fft.fftfreq(nz, d=h) * 2 * np.pi
+    ky = np.fft.fftfreq(ny, d=h) * 2 * np.pi
+    kx = np.fft.rfftfreq(nx, d=h) * 2 * np.pi
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    filt = np.exp(-(KZ ** 2 + KY ** 2 + KX ** 2) * corr ** 2 / 4.0)
+    field = np.fft.irfftn(np.fft.rfftn(noise) * filt, s=(nz, ny, nx), axes=(0, 1, 2))
+    lo, hi = c_range
+    span = field.max() - field.min()
+    t = (field - field.min()) / span if span > 0 else np.zeros_like(field)
+    return (lo + (hi - lo) * t).astype(np.float32)
 
 
 def surface_sources(dims, nsrc, depth_index, margin):

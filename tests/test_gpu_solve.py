@@ -51,7 +51,7 @@ def _certify(A, u, b):
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_small_solve_matches_direct_solve(ctx, table, oracle_table, precision):
     dims, npml, f, h = (16, 14, 12), 3, 6.0, 25.0
-    c = synth.random_field_model(dims, h, seed=4)
+    c = synth.smooth_random_model(dims, h, seed=4)
     op = ctx.assemble(table, c, h, f, npml=npml)
     src = [(7, 6, 5), (8, 7, 4)]
     u, st = op.solve(src, tol=1e-10, precision=precision)
