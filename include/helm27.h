@@ -361,6 +361,10 @@ typedef struct {
     int    mg_levels;        /* multigrid levels of the preconditioner (1: none coarse) */
     int64_t coarse_clamped;  /* coarse-level rows whose G = c/(f 2^l h) fell outside their table */
     int    coarse_tables;    /* coarse levels that use a table widened for their own G range */
+    double inner_est;        /* last inner GMRES solve: its Givens (Hessenberg least-squares)
+                                estimate of the residual it leaves, relative to its right-hand
+                                side, max over RHS (a check of the Arnoldi recurrence: with one
+                                FP64 refinement step it equals max_relres to rounding) */
 } helm27_solve_stats;
 
 /* Fill `opts` with the defaults above. */

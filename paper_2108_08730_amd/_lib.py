@@ -60,7 +60,7 @@ class IndexStats(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int), ("converged", C.c_int),
                 ("max_relres", C.c_double), ("seconds", C.c_double), ("mg_levels", C.c_int),
-                ("coarse_clamped", C.c_int64), ("coarse_tables", C.c_int)]
+                ("coarse_clamped", C.c_int64), ("coarse_tables", C.c_int), ("inner_est", C.c_double)]
 
 
 class ServeOpts(C.Structure):

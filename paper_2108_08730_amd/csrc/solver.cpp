@@ -34,6 +34,7 @@ struct SolverState {
     std::vector<GridOp> coarse;
     int64_t coarse_clamped = 0;      // coarse rows outside their table
     int coarse_tables = 0;           // coarse levels with their own widened table
+    double last_est = 0;             // last inner solve: Givens residual estimate / its rhs norm (max over RHS)
     // workspace
     int nrhs = 0, m = 0, prec = 0;   // prec = sizeof(real) of the inner precision
     int64_t N = 0;
@@ -570,6 +571,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
     int it = 0;
     *conv = false;
     bool first = true;
+    int last_k = -1;   // steps of the last cycle that updated x
     while (it < max_it) {
         const void* r;
         if (first) {
@@ -660,6 +662,9 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             }
         }
         if (beta_conv) {   // converged before this cycle: x is final
+            S->last_est = 0;
+            for (int q = 0; q < nrhs; ++q) S->last_est = std::max(S->last_est, h_beta[q] / bn[q]);
+            last_k = -1;
             *conv = true;
             break;
         }
@@ -671,6 +676,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
                 if (h_beta[q] > thr[q] * bn[q]) all = false;
             }
             if (all) *conv = true;
+            last_k = 0;   // g was re-initialised: g_0 = beta, the residual x leaves
             break;
         }
         if (!cyc_conv && k > 0) {
@@ -679,6 +685,7 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
             cyc_conv = done;
         }
         if ((st = upper_solve(k, m, nrhs, S->d_H, S->d_g, S->d_y, ldh, c.s))) return st;
+        last_k = k;
         void* z = nullptr;
         if (g) {
             if ((st = combine<R>(S->V, vstride, k, S->d_y, ldh, S->vin, N, nrhs, 0, c.s, dv0, y0))) return st;
@@ -691,6 +698,19 @@ static int gmres_inner(const Ctx& c, const void* rhs, void* x, const std::vector
         if (cyc_conv) {
             *conv = true;
             break;
+        }
+    }
+    if (last_k >= 0 && S->last_est >= 0) {
+        // the last cycle's Givens estimate |g_k| of the residual it leaves
+        // (absolute: g_0 = beta is the cycle's starting residual); g is
+        // re-initialised only when a cycle starts, so it is still that cycle's
+        std::vector<double2> gk(static_cast<size_t>(nrhs) * ldh);
+        H27_CHECK_HIP(hipMemcpyAsync(gk.data(), S->d_g, gk.size() * sizeof(double2), hipMemcpyDeviceToHost, c.s));
+        H27_CHECK_HIP(hipStreamSynchronize(c.s));
+        S->last_est = 0;
+        for (int q = 0; q < nrhs; ++q) {
+            const double2 v = gk[static_cast<size_t>(q) * ldh + last_k];
+            S->last_est = std::max(S->last_est, std::hypot(v.x, v.y) / bn[q]);
         }
     }
     *iters = it;
@@ -772,6 +792,7 @@ static int solve_core(helm27_op* op, const double2* b, double2* u, int nrhs, con
         stats->mg_levels = o->mg_levels == 0 ? 1 : S->levels;
         stats->coarse_clamped = o->mg_levels == 0 ? 0 : S->coarse_clamped;
         stats->coarse_tables = o->mg_levels == 0 ? 0 : S->coarse_tables;
+        stats->inner_est = S->last_est;
     }
     return converged ? HELM27_OK : HELM27_ENOCONV;
 }

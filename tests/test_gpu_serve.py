@@ -101,3 +101,31 @@ def test_operator_reuse_same_result(ctx):
     srv.stop()
     assert r2["status"] == 0
     assert torch.equal(o1, o2)
+
+
+def test_served_results_certified_by_oracle(ctx):
+    """Every result the request loop returns solves its own problem: the
+    oracle assembles each request's operator with its own table (the server's
+    table agrees with it to 1e-9) and its FP64 residual of the served
+    solution meets the tolerance (1e-8 plus the table difference's share,
+    1e-9)."""
+    from paper_2108_08730_amd import api
+    from oracle import operator as O
+    from oracle import solve as S
+    from oracle import table as T
+    reqs = _requests()[:4]
+    vels = [synth.random_field_model(d, h, seed=s) for d, h, f, p, src, s in reqs]
+    srv = api.Server(ctx, max_slots=3, table=TABLE, tol=1e-8)
+    tickets = [srv.submit(v, h, f, src, npml=p, model_key=s)
+               for (d, h, f, p, src, s), v in zip(reqs, vels)]
+    results = [srv.wait(t) for t, _ in tickets]
+    outs = [out.cpu().numpy() for _, out in tickets]
+    srv.stop()
+    Gs, W = T.build_table(*TABLE)
+    W7 = T.complete_weights(W)
+    for (d, h, f, p, src, s), v, r, u in zip(reqs, vels, results, outs):
+        assert r["status"] == 0 and r["converged"] == 1
+        idx, _ = O.select_index(v, f, h, TABLE[0], TABLE[2], len(Gs))
+        A = O.assemble(v, f, h, p, O.row_weights("GA", idx, W7))
+        b = S.point_source_rhs(d, h, src)
+        assert np.all(S.relative_residual(A, u.T, b) <= 1e-8 * 1.01 + 1e-9)

@@ -94,23 +94,29 @@ def test_homogeneous_41_greens_function(ctx, table, oracle_table):
 
 def test_gradient_101_mixed_and_fp64(ctx, table, oracle_table):
     """101^3 vertical gradient c = 1500 + 0.7 z, h = 25 m, f = 5 Hz, 10-node PML,
-    one source near the top: complex-FP32 GMRES with FP64 refinement and the
-    all-FP64 solve both reach 1e-6 certified by the oracle; their difference
-    is bounded by the conditioning of the tolerance."""
+    one source near the top.  The reference: an all-FP64 solve to 1e-11,
+    certified by the oracle's own FP64 CSR residual (the oracle cannot
+    factorise 10^6 unknowns, so its residual certifies the GPU solution
+    instead).  Against it, the mixed-precision solve (complex-FP32 GMRES with
+    FP64 refinement) to 1e-6 -- also certified by the oracle -- has an error
+    of 4e-7 measured; the test bounds it by 1e-5 (error <= condition x
+    residual; the measured ratio error / residual is below 1)."""
     dims, npml, f, h = (101, 101, 101), 10, 5.0, 25.0
     c = synth.gradient_z(dims, h, 1500.0, 0.7)
     op = ctx.assemble(table, c, h, f, npml=npml)
     src = [(50, 50, 11)]
     um, stm = op.solve(src, tol=1e-6)
-    u6, st6 = op.solve(src, tol=1e-6, precision="fp64")
-    assert stm["converged"] == 1 and st6["converged"] == 1
+    ur, str_ = op.solve(src, tol=1e-11, precision="fp64", max_inner=3000)
+    assert stm["converged"] == 1 and str_["converged"] == 1
     A = _oracle_A(c, f, h, npml, oracle_table[2])
     b = S.point_source_rhs(dims, h, src)
     a = um.cpu().numpy()
-    d = u6.cpu().numpy()
+    d = ur.cpu().numpy()
     assert _certify(A, a, b)[0] <= 1e-6 * 1.01
-    assert _certify(A, d, b)[0] <= 1e-6 * 1.01
-    assert np.linalg.norm(a - d) / np.linalg.norm(d) < 1e-3
+    assert _certify(A, d, b)[0] <= 1e-11 * 1.01
+    err = np.linalg.norm(a - d) / np.linalg.norm(d)
+    print(f"mixed-precision 1e-6 solve: error against the certified FP64 solve {err:.2e}")
+    assert err < 1e-5
 
 
 def test_batch_equals_single(ctx, table):
@@ -223,3 +229,87 @@ def test_selective_second_pass_matches_full_cgs2(ctx, table, oracle_table):
     for k in range(2):
         assert np.linalg.norm(sols[0][k] - sols[1][k]) / np.linalg.norm(sols[1][k]) < 1e-6
 
+
+
+def test_givens_estimate_equals_true_residual(ctx, table):
+    """One FP64 refinement step (so u = 0 and the inner right-hand side is b)
+    with a few restarted GMRES(10) cycles stopped short of convergence: the
+    inner solve's Givens estimate of its residual -- built from the Arnoldi
+    Hessenberg columns and the rotations -- equals the true FP64 residual
+    ||b - A u|| / ||b|| recomputed afterwards, to rounding.  A broken Arnoldi
+    relation (a wrong Hessenberg entry or rotation) breaks the equality."""
+    dims, npml, f, h = (24, 20, 18), 4, 6.0, 25.0
+    c = synth.smooth_random_model(dims, h, seed=6)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    for max_inner in (7, 10, 25):
+        u, st = op.solve([(12, 10, 9), (9, 11, 8)], tol=1e-15, precision="fp64", max_outer=1, restart=10,
+                         max_inner=max_inner)
+        assert st["converged"] == 0 and st["outer_iters"] == 1 and st["inner_iters"] == max_inner
+        assert 1e-12 < st["max_relres"] < 1.0
+        assert abs(st["inner_est"] - st["max_relres"]) <= 1e-9 * st["max_relres"], (max_inner, st)
+
+
+def test_reciprocity_homogeneous_pml(ctx, table):
+    """Homogeneous medium with PML: the operator is complex symmetric, so the
+    field of a source at s observed at r equals the field of a source at r
+    observed at s (to the solve tolerance), for an off-centre pair."""
+    dims, npml, f, h = (40, 36, 32), 6, 7.0, 20.0
+    c = synth.homogeneous(dims, 2200.0)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    s, r = (12, 15, 10), (27, 20, 21)
+    u, st = op.solve([s, r], tol=1e-10)
+    assert st["converged"] == 1
+    ud = u.cpu().numpy()
+    lin = lambda p: p[0] + dims[0] * (p[1] + dims[1] * p[2])  # noqa: E731
+    a, b = ud[0][lin(r)], ud[1][lin(s)]
+    assert abs(a) > 1e-3 * np.abs(ud).max()
+    assert abs(a - b) <= 1e-7 * np.abs(ud).max()
+
+
+def test_end_to_end_with_library_table(ctx, oracle_table):
+    """The whole path with no injected weights: helm27_build_table (banded QR)
+    -> helm27_assemble -> apply / solve, against the oracle with its own
+    table (dense least squares).  The tables agree to 1e-9 (CPU test), which
+    moves a 27-term row by at most ~1e-9 times the sum of its terms'
+    magnitudes: FP64 apply <= 1e-8; the solve, certified by the oracle's own
+    operator, reaches 1e-7 + 1e-8."""
+    from paper_2108_08730_amd import api  # noqa: F401
+    dims, npml, f, h = (40, 34, 30), (5, 5, 4), 6.0, 25.0
+    c = synth.random_field_model(dims, h, seed=21)
+    tab = ctx.build_table(3.0, 20.0, 0.05, 1e-3)
+    op = ctx.assemble(tab, c, h, f, npml=npml)
+    A = _oracle_A(c, f, h, npml, oracle_table[2])
+    u = synth.random_vectors(int(np.prod(dims)), 2, seed=17)
+    y_ref = (A @ u.T).T
+    y = op.apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    for r in range(2):
+        assert np.linalg.norm(y[r] - y_ref[r]) / np.linalg.norm(y_ref[r]) <= 1e-8
+    src = [(20, 17, 8)]
+    us, st = op.solve(src, tol=1e-7)
+    assert st["converged"] == 1
+    b = S.point_source_rhs(dims, h, src)
+    assert _certify(A, us.cpu().numpy(), b)[0] <= 1e-7 + 1e-8
+
+
+@pytest.mark.parametrize("mode", ["GAm", "fixed"])
+def test_weight_modes_fp32_apply_and_solve(ctx, table, oracle_table, mode):
+    """The paper's other weight choices (Sec. 3.1: "GAm" neighbourhood-averaged,
+    and fixed "G4"-type weights) through the FP32 kernels: apply <= 1e-5 and
+    a mixed-precision solve certified by the oracle's FP64 residual."""
+    dims, npml, f, h = (40, 23, 18), (3, 3, 2), 6.0, 25.0
+    c = synth.smooth_random_model(dims, h, seed=5)
+    op = ctx.assemble(table, c, h, f, npml=npml, weights=mode)
+    idx, _ = O.select_index(c, f, h, 3.0, 0.05, 341)
+    W7 = oracle_table[2]
+    nz, ny, nx = c.shape
+    A = O.assemble(c, f, h, npml, O.row_weights(mode, idx, W7, fixed_w=W7[0], dims=(nx, ny, nz)))
+    u = synth.random_vectors(int(np.prod(dims)), 2, seed=8)
+    y_ref = (A @ u.T).T
+    y32 = op.apply(torch.from_numpy(u).cuda().to(torch.complex64)).cpu().numpy()
+    for r in range(2):
+        assert np.linalg.norm(y32[r] - y_ref[r]) / np.linalg.norm(y_ref[r]) <= 1e-5
+    src = [(20, 11, 8), (14, 12, 9)]
+    us, st = op.solve(src, tol=1e-8)
+    assert st["converged"] == 1
+    b = S.point_source_rhs(dims, h, src)
+    assert np.all(_certify(A, us.cpu().numpy(), b) <= 1.01e-8)
