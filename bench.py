@@ -241,6 +241,50 @@ def solve_steps(args, torch, api, synth, ctx):
             "phase_ms": {k: float(np.mean(v) * 1e3) for k, v in phases.items()}}
 
 
+def batched_small_grids(torch, api, synth, ctx, reps=50):
+    """Eight small grids of the serving mix (64^3, 96^3 and 128^2 x 64 models,
+    h = 1500 / (4 f), 4 right-hand sides each): eight helm27_apply launches
+    one after another against one helm27_apply_many, complex FP32, timed with
+    HIP events on the launching stream."""
+    specs = [((64, 64, 64), 10.0), ((96, 96, 96), 7.5), ((128, 128, 64), 5.0), ((64, 64, 64), 6.0),
+             ((96, 96, 96), 4.0), ((64, 64, 64), 8.0), ((128, 128, 64), 9.0), ((96, 96, 96), 3.0)]
+    tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
+    ops, us, ys = [], [], []
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for k, (dims, f) in enumerate(specs):
+        h = 1500.0 / (4.0 * f)
+        c = synth.random_field_model(dims, h, seed=100 + k)
+        op = ctx.assemble(tab, c, h, f, npml=8)
+        ops.append(op)
+        us.append(torch.randn((4, op.N), dtype=torch.complex64, device="cuda", generator=g))
+        ys.append(torch.empty_like(us[-1]))
+    stream = torch.cuda.current_stream()
+
+    def run(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    def singles():
+        for op, u, y in zip(ops, us, ys):
+            op.apply(u, y, stream=stream)
+
+    t_single = run(singles)
+    t_fused = run(lambda: api.apply_many(ops, us, ys, stream=stream))
+    pts = sum(op.N * 4 for op in ops)
+    return {"grids": [list(d) for d, _ in specs], "rhs_per_grid": 4,
+            "separate_launches_us": t_single * 1e6, "fused_launch_us": t_fused * 1e6,
+            "fused_gpts": pts / t_fused / 1e9, "speedup": t_single / t_fused}
+
+
 def serving(args, torch, api, synth):
     """Serving mix: Poisson arrivals of solve requests over seeded random-field
     models (frequencies 2.5-10 Hz, h = 1500 / (4 f) so the smallest G is about
@@ -486,6 +530,7 @@ def main():
         ext["stored_single_rhs"] = {"us": ss * 1e6, "gpts": N / ss / 1e9, "GBs": a_s / ss / 1e9,
                                     "frac": a_s / ss / 1e9 / HBM_PEAK_GBS, "alg_bytes": a_s}
         del op_s, u1, y1
+        ext["batched_small_grids"] = batched_small_grids(torch, api, synth, ctx)
         out["apply_variants"] = ext
     del op, u, y
     torch.cuda.empty_cache()

@@ -135,13 +135,19 @@ int helm27_table_from_weights(helm27_ctx* ctx, int spacing, double g_min, double
                               const double* w5, helm27_table** out);
 
 /* Non-adaptive weights (Sec. 2.2, joint misfit over several G with one weight
- * vector, e.g. G = 4 for "G4" and G = 4, 6, 8, 10 for "Gm"): the minimum-norm
- * least-squares solution (the system is rank deficient), computed by one-sided
- * Jacobi SVD in FP64 on the host.  Returns a one-entry table to be assembled
- * with HELM27_WEIGHTS_FIXED.  g_list: host [n_list].  Errors: EINVAL,
- * ENUMERIC, ENOMEM. */
+ * vector, e.g. G = 4 for "G4" and G = 4, 6, 8, 10 for "Gm"), computed by
+ * one-sided Jacobi SVD in FP64 on the host.  A single G gives a rank-3
+ * system whose least-squares solutions form a plane: w5_near (host [5], the
+ * free weights w_s1, w_s2, w_m0, w_m1, w_m2, or NULL) picks the one closest
+ * to it, NULL the minimum-norm one.  For G = 4 the minimum-norm stencil has
+ * spurious modes (its stiffness symbol changes sign at q h = (pi, pi, 0) and
+ * its mass symbol goes negative) and preconditioned iterative solves of it
+ * do not converge; the smoothed table's entry at G = 4 as w5_near gives a
+ * stencil with the same phase velocities at G = 4 and positive symbols.
+ * Returns a one-entry table to be assembled with HELM27_WEIGHTS_FIXED.
+ * g_list: host [n_list].  Errors: EINVAL, ENUMERIC, ENOMEM. */
 int helm27_fit_fixed(helm27_ctx* ctx, const double* g_list, int n_list, const helm27_table_opts* opts,
-                     helm27_table** out);
+                     const double* w5_near, helm27_table** out);
 
 /* Copy the table out: w7 (host, caller-owned, [n_g][7] or NULL) receives
  * (w_s1, w_s2, w_s3, w_m0, w_m1, w_m2, w_m3) per entry (per-point mass
@@ -248,6 +254,22 @@ int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t* indptr,
  * returns without synchronising.  Errors: EINVAL, EDEVICE. */
 int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int dtype, int variant,
                  void* stream);
+
+/* Batched apply of several operators (the same product y_i = A_i u_i as
+ * helm27_apply with HELM27_RECOMPUTE, Sec. 2.1) in fused launches: the small
+ * grids of concurrent requests share one launch of the stencil kernel (up to
+ * 8 operators per launch; operators that differ in attenuation, GAm per-row
+ * weights or mass form go in separate launches).  ops[n_ops]: operators of
+ * one device; u[i], y[i]: device pointers to [nrhs[i]][N_i] complex values
+ * of `dtype` (HELM27_C64 or HELM27_C128); nrhs[i] = 0 skips operator i; all
+ * arrays are host arrays owned by the caller.  Outputs must not overlap any
+ * input or each other.  The tile shape is the small-grid one (per-wavefront
+ * tiles, automatic z chunks) whatever helm27_set_tuning chose.  Enqueued on
+ * `stream`; returns without synchronising.  Errors: EINVAL (null pointers,
+ * n_ops < 0, nrhs[i] < 0, a grid too large for 32-bit vector offsets or
+ * whose table slice does not fit in LDS), EDEVICE. */
+int helm27_apply_many(helm27_op* const* ops, int n_ops, const void* const* u, void* const* y,
+                      const int* nrhs, int dtype, void* stream);
 
 /* Tuning of the recompute kernel's tile shape (output rows per wavefront in
  * the unstretched box, 1..4; more rows reuse more loaded data, fewer rows

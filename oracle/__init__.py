@@ -19,6 +19,9 @@ finite-difference stencil") and shares no code with the GPU path:
                    dense / sparse-direct solve of the assembled system.
 * ``analytic``  -- homogeneous-medium Green's function and the amplitude factor
                    of the discrete operator, used to pin the oracle.
+* ``accuracy``  -- the wavefield accuracy metric (Sec. 3.1, equation err) and
+                   the closed-form Green's function of the linear-velocity
+                   benchmark (Sec. 3.2).
 
 Every function cites the passage it follows; readings of points the paper
 leaves open are listed in each module docstring.

@@ -34,8 +34,14 @@ Readings of points the paper leaves open:
   so s = 0 (G infinite) is a regular point where every row vanishes (any
   consistent stencil is exact there) and only the smoothing term fixes the
   weights.
-* The fixed-weight problems ("G4": N_G = 1) are rank deficient; their
-  minimum-norm least-squares solution is used.
+* The fixed-weight problem "G4" (N_G = 1) is rank deficient.  Its
+  minimum-norm least-squares solution is a stencil with spurious modes: its
+  stiffness symbol changes sign at q h = (pi, pi, 0) and its mass symbol
+  goes negative, so a shifted-Laplacian preconditioned Krylov solve of it
+  does not converge.  The "G4" of the accuracy comparison is the
+  least-squares solution closest to the smoothed table's entry at G = 4
+  (identical phase velocities at G = 4, positive symbols, worst error at
+  G = 5.5 as the paper states); "Gm" (N_G = 4) is unique.
 """
 from __future__ import annotations
 
@@ -228,12 +234,16 @@ def table_normal_residual(Gs, W, lam, theta=None, phi=None, diff="first", spacin
     return float(np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs))
 
 
-def fit_fixed(G_list, theta=None, phi=None):
+def fit_fixed(G_list, theta=None, phi=None, near=None):
     """Non-adaptive weights (Sec. 2.2, joint misfit over several G with one
     weight vector): N_G = 1 with G = 4 gives "G4", G = 4, 6, 8, 10 gives "Gm".
-    Minimum-norm least-squares solution (the N_G = 1 problem is rank 4): the
-    pseudo-inverse with singular values below 1e-10 of the largest taken as
-    zero.  Returns the five free weights."""
+    The N_G = 1 problem has rank 3 (two of the five singular values vanish
+    for any single G on the 25-direction grid), so its least-squares
+    solutions form a plane.
+    Without ``near``: the minimum-norm one (the pseudo-inverse with singular
+    values below 1e-10 of the largest taken as zero).  With ``near`` (five
+    free weights): the least-squares solution closest to it,
+    near + pinv(H) (g - H near).  Returns the five free weights."""
     if theta is None:
         theta, phi = angle_grid()
     Hs, gs = [], []
@@ -243,8 +253,9 @@ def fit_fixed(G_list, theta=None, phi=None):
         gs.append(g)
     H = np.vstack(Hs)
     g = np.concatenate(gs)
-    w, *_ = scipy.linalg.lstsq(H, g, cond=1e-10, lapack_driver="gelsd")
-    return w
+    w0 = np.zeros(5) if near is None else np.asarray(near, dtype=np.float64)
+    dw, *_ = scipy.linalg.lstsq(H, g - H @ w0, cond=1e-10, lapack_driver="gelsd")
+    return w0 + dw
 
 
 def worst_phase_error(Gs, W, theta=None, phi=None):

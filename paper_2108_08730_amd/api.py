@@ -238,6 +238,32 @@ def solve_many(ops, sources, **opts):
     return outs, stats
 
 
+def apply_many(ops, us, ys=None, stream=None):
+    """helm27_apply_many: y_k = A_k u_k for every operator in fused launches.
+    us[k]: device tensor [nrhs_k, N_k] (or [N_k]), all complex64 or all
+    complex128; returns the list of outputs."""
+    torch = _torch()
+    n = len(ops)
+    us = [u.view(1, -1) if u.dim() == 1 else u for u in us]
+    if len(us) != n:
+        raise ValueError("one input per operator")
+    dts = {u.dtype for u in us}
+    if len(dts) != 1 or not dts <= {torch.complex64, torch.complex128}:
+        raise TypeError("inputs must all be complex64 or all complex128")
+    for op, u in zip(ops, us):
+        assert u.is_cuda and u.is_contiguous() and u.shape[1] == op.N
+    if ys is None:
+        ys = [torch.empty_like(u) for u in us]
+    dt = L.C64 if us[0].dtype == torch.complex64 else L.C128
+    P = C.c_void_p
+    h_ops = (P * n)(*[op.handle for op in ops])
+    h_u = (P * n)(*[P(u.data_ptr()) for u in us])
+    h_y = (P * n)(*[P(y.data_ptr()) for y in ys])
+    h_n = (C.c_int * n)(*[u.shape[0] for u in us])
+    L.check(L.lib.helm27_apply_many(h_ops, n, h_u, h_y, h_n, dt, _stream_handle(stream)), "apply_many")
+    return ys
+
+
 def _check_device_velocity(vel):
     """A device velocity is read in place as float32 [nz][ny][nx]."""
     torch = _torch()

@@ -35,7 +35,7 @@ EXTRA = {
 }
 SOURCES = [
     "table.cpp", "op.cpp", "solver.cpp", "serve.cpp",
-    "kernels_assemble.hip", "kernels_stencil.hip", "kernels_wave.hip", "kernels_wave_apply.hip",
+    "kernels_assemble.hip", "kernels_stencil.hip", "kernels_wave.hip", "kernels_wave_apply.hip", "kernels_wave_batch.hip",
     "kernels_wave_resid.hip", "kernels_wave_jacobi.hip", "kernels_wave_jacobi0.hip", "kernels_krylov.hip",
 ]
 

@@ -233,6 +233,11 @@ int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, dou
 template <typename R>
 int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, const void* u, void* y,
                    const void* b, double omega_j, int nrhs, hipStream_t s);
+// y_i = A_i u_i (physical operators) for n grids in fused launches; every
+// grid must be eligible for the wavefront kernel (EINVAL otherwise)
+template <typename R>
+int launch_stencil_batch(const GridOp* const* g, int n, const void* const* u, void* const* y, const int* nrhs,
+                         hipStream_t s);
 // whether launch_stencil runs the wavefront kernel on this grid (which also
 // provides the zero-iterate Jacobi mode)
 bool stencil_wave_path(const GridOp& g, bool fp64);

@@ -434,6 +434,142 @@ bool stencil_wave_path(const GridOp& g, bool fp64) {
 }
 
 template <typename R>
+static int build_wave_args(const GridOp& g, const GridData<R>& gd, const void* u, void* y, const void* b,
+                           double omega_j, int nrhs, bool batch, WaveArgs<R>& w, int& RY) {
+    const Tiling& t = g.tiling;
+    const int n_tab = g.idx_hi - g.idx_lo + 1;
+    w.g = gd;
+    constexpr bool fp64 = sizeof(R) == 8;
+    RY = g.plain_ry[fp64 ? 1 : 0];
+    int variant = g.kernel_variant, zc_set = g.wave_zchunk;
+    if (batch) {
+        // batched small grids: per-wavefront tiles (two rows in FP32, one
+        // in FP64 or with the first mass form), automatic z chunks
+        RY = fp64 ? 1 : 2;
+        variant = 0;
+        zc_set = 0;
+    } else if (g.auto_tile) {
+        // HBM-bound launches (2^23 or more point-RHS pairs): box rows shared
+        // across the block (variant 2), one row per wavefront in 32-plane
+        // chunks for one RHS, two rows in 16-plane chunks for several
+        // (400x400x200: 181 us against 185 us with 16-plane chunks and
+        // 203-213 us for variant 0; 201x201x101 x 16 RHS: 390 us against
+        // 431 us); smaller launches keep the latency-friendlier
+        // per-wavefront tiles with automatic chunks
+        const bool big = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23);
+        RY = fp64 ? g.plain_ry[1] : (big && nrhs >= 2 ? 2 : (big ? 1 : 2));
+        variant = 0;
+        zc_set = 0;
+        const size_t ring = wave_ring_bytes(g.mass_a ? 1 : RY, 1, fp64, g.mass_a != 0);
+        if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit()) {
+            variant = 2;
+            zc_set = nrhs == 1 ? 32 : 16;
+        }
+    }
+    const int RQ = frame_rows<R>();
+    w.n_items = 0;
+    // several right-hand sides per box wavefront (FP32 block tiles, one
+    // row per wavefront) when asked for (helm27_set_rhs_block or the
+    // tuner), the group's vectors are addressable with 32-bit buffer
+    // offsets and its row ring fits in LDS.  Automatic: one (measured on
+    // 400x400x200 x 16 and 201x201x101 x 64: groups of 2 or 4 change the
+    // time by -4 % to +4 %; the per-RHS cost is the row traffic of u
+    // and y, not the per-point data the groups share)
+    if (g.mass_a) {   // first mass form: one row per wavefront (two spill registers)
+        RY = 1;
+        if (variant == 1) variant = 0;
+    }
+    int NB = 1;
+    if (!fp64 && nrhs >= 2 && g.rhs_block > 1 && !g.mass_a && !batch) {
+        NB = g.rhs_block;
+        const bool fits = static_cast<int64_t>(g.N) * 8 * NB < (int64_t(1) << 31) &&
+                          wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + wave_ring_bytes(1, NB, fp64) <=
+                              lds_limit();
+        if (!fits) NB = 1;
+    }
+    if (NB > 1) {
+        variant = 2;
+        RY = 1;
+        if (g.auto_tile) zc_set = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23) ? 32 : 0;
+    }
+    w.nb = NB;
+    w.ngrp = (nrhs + NB - 1) / NB;
+    // multi-RHS item order: right-hand side slowest by default (each
+    // right-hand side's pass keeps its tiles' shared halo rows and planes
+    // close in time, as a single-RHS launch does; 201x201x101 x 64:
+    // 1.81 -> 1.52 ms), or fastest (the per-point data of a tile are
+    // shared by its right-hand sides in L2)
+    w.rhs_outer = g.rhs_order == 1 ? 0 : 1;
+    const int TC = kWaveCols;
+    w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
+    Rect fr[4] = {t.frame[0], t.frame[1], t.frame[2], t.frame[3]};
+    // The box is cut into 62-column tiles; a last partial tile costs as
+    // much as a full one.  When the left / right strips (14-column lane
+    // groups) have room for those leftover columns in the groups they
+    // already use, they take them (the general formula holds for
+    // unstretched columns too) and the box becomes whole tiles
+    // (400 wide with an 8-node PML: 6 tiles instead of 6 + 12 columns).
+    if (w.pw > TC && fr[2].w > 0 && fr[3].w > 0) {
+        const int left = w.pw % TC;
+        const int capl = 14 * ((fr[2].w + 13) / 14) - fr[2].w, capr = 14 * ((fr[3].w + 13) / 14) - fr[3].w;
+        if (left > 0 && left <= capl + capr) {
+            const int a = std::min(left, capl);
+            w.px0 += a;
+            w.pw -= left;
+            fr[2].w += a;
+            fr[3].x0 = w.px0 + w.pw;
+            fr[3].w = g.nx - fr[3].x0;
+        }
+    }
+    // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
+    w.blk = variant == 2 ? 1 : 0;
+    const int rows_per_tile = w.blk ? 4 * RY : RY;
+    w.ntx = w.pw > 0 ? (w.pw + TC - 1) / TC : 0;
+    w.nty = w.ph > 0 ? (w.ph + rows_per_tile - 1) / rows_per_tile : 0;
+    w.n_plain = w.ntx * w.nty;
+    int accf = 0;
+    for (int k = 0; k < 4; ++k) {
+        const Rect& r = fr[k];
+        w.fx0[k] = r.x0; w.fy0[k] = r.y0; w.fw[k] = r.w; w.fh[k] = r.h;
+        // lanes always run along x: whole-wave groups (62 columns) for strips
+        // spanning x (bottom / top, or the whole grid), 16-lane groups (14
+        // columns, 4 groups stacked along y) for the narrow left / right strips
+        const bool wide = !(k >= 2 && t.plain_w > 0);
+        w.flx[k] = wide ? 1 : 0;
+        const int cols = wide ? kWaveCols : 14, rows = wide ? RQ : 4 * RQ;
+        const bool empty = r.w <= 0 || r.h <= 0;
+        w.fnl[k] = empty ? 1 : (r.w + cols - 1) / cols;
+        w.fnq[k] = empty ? 0 : (r.h + rows - 1) / rows;
+        w.fstart[k] = accf;
+        accf += empty ? 0 : w.fnl[k] * w.fnq[k];
+    }
+    w.fstart[4] = accf;
+    w.n_frame = accf;
+    // work items: wavefront items (variant 0) or block items of 4 wavefronts (variant 2)
+    const int64_t tiles = static_cast<int64_t>(w.blk ? (w.n_frame + 3) / 4 + w.n_plain : w.n_plain + w.n_frame) *
+                          w.ngrp;
+    if (tiles <= 0) return HELM27_OK;   // nothing to do (n_items stays 0)
+    const int64_t target = w.blk ? 1024 : 4096;
+    int64_t nzc = (target + tiles - 1) / tiles;
+    int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
+    zc = std::max(2, std::min(16, zc));
+    if (zc_set > 0) zc = zc_set;
+    w.zchunk = std::min(zc, g.nz);
+    w.nzc = (g.nz + w.zchunk - 1) / w.zchunk;
+    w.nrhs = nrhs;
+    const int64_t items = tiles * w.nzc;
+    if (items > (int64_t(1) << 30)) return HELM27_EINVAL;
+    w.n_items = static_cast<int>(items);
+    w.tab_lo = g.idx_lo;
+    w.n_tab = n_tab;
+    w.u = static_cast<const typename V2<R>::T*>(u);
+    w.y = static_cast<typename V2<R>::T*>(y);
+    w.b = static_cast<const typename V2<R>::T*>(b);
+    w.omega_j = static_cast<R>(omega_j);
+    return HELM27_OK;
+}
+
+template <typename R>
 int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, const void* u, void* y, const void* b,
                    double omega_j, int nrhs, hipStream_t s) {
     if (nrhs <= 0) return HELM27_OK;
@@ -468,127 +604,10 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
     if ((mode == MODE_JACOBI0 || g.mass_a) && !use_wave) return HELM27_EINVAL;   // wavefront kernel only
     if (use_wave) {
         WaveArgs<R> w{};
-        w.g = a.g;
-        constexpr bool fp64 = sizeof(R) == 8;
-        int RY = g.plain_ry[fp64 ? 1 : 0], variant = g.kernel_variant, zc_set = g.wave_zchunk;
-        if (g.auto_tile) {
-            // HBM-bound launches (2^23 or more point-RHS pairs): box rows shared
-            // across the block (variant 2), one row per wavefront in 32-plane
-            // chunks for one RHS, two rows in 16-plane chunks for several
-            // (400x400x200: 181 us against 185 us with 16-plane chunks and
-            // 203-213 us for variant 0; 201x201x101 x 16 RHS: 390 us against
-            // 431 us); smaller launches keep the latency-friendlier
-            // per-wavefront tiles with automatic chunks
-            const bool big = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23);
-            RY = fp64 ? g.plain_ry[1] : (big && nrhs >= 2 ? 2 : (big ? 1 : 2));
-            variant = 0;
-            zc_set = 0;
-            const size_t ring = wave_ring_bytes(g.mass_a ? 1 : RY, 1, fp64, g.mass_a != 0);
-            if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit()) {
-                variant = 2;
-                zc_set = nrhs == 1 ? 32 : 16;
-            }
-        }
-        const int RQ = frame_rows<R>();
-        // several right-hand sides per box wavefront (FP32 block tiles, one
-        // row per wavefront) when asked for (helm27_set_rhs_block or the
-        // tuner), the group's vectors are addressable with 32-bit buffer
-        // offsets and its row ring fits in LDS.  Automatic: one (measured on
-        // 400x400x200 x 16 and 201x201x101 x 64: groups of 2 or 4 change the
-        // time by -4 % to +4 %; the per-RHS cost is the row traffic of u
-        // and y, not the per-point data the groups share)
-        if (g.mass_a) {   // first mass form: one row per wavefront (two spill registers)
-            RY = 1;
-            if (variant == 1) variant = 0;
-        }
-        int NB = 1;
-        if (!fp64 && nrhs >= 2 && g.rhs_block > 1 && !g.mass_a) {
-            NB = g.rhs_block;
-            const bool fits = static_cast<int64_t>(g.N) * 8 * NB < (int64_t(1) << 31) &&
-                              wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + wave_ring_bytes(1, NB, fp64) <=
-                                  lds_limit();
-            if (!fits) NB = 1;
-        }
-        if (NB > 1) {
-            variant = 2;
-            RY = 1;
-            if (g.auto_tile) zc_set = static_cast<int64_t>(g.N) * nrhs >= (int64_t(1) << 23) ? 32 : 0;
-        }
-        w.nb = NB;
-        w.ngrp = (nrhs + NB - 1) / NB;
-        // multi-RHS item order: right-hand side slowest by default (each
-        // right-hand side's pass keeps its tiles' shared halo rows and planes
-        // close in time, as a single-RHS launch does; 201x201x101 x 64:
-        // 1.81 -> 1.52 ms), or fastest (the per-point data of a tile are
-        // shared by its right-hand sides in L2)
-        w.rhs_outer = g.rhs_order == 1 ? 0 : 1;
-        const int TC = kWaveCols;
-        w.px0 = t.plain_x0; w.py0 = t.plain_y0; w.pw = t.plain_w; w.ph = t.plain_h;
-        Rect fr[4] = {t.frame[0], t.frame[1], t.frame[2], t.frame[3]};
-        // The box is cut into 62-column tiles; a last partial tile costs as
-        // much as a full one.  When the left / right strips (14-column lane
-        // groups) have room for those leftover columns in the groups they
-        // already use, they take them (the general formula holds for
-        // unstretched columns too) and the box becomes whole tiles
-        // (400 wide with an 8-node PML: 6 tiles instead of 6 + 12 columns).
-        if (w.pw > TC && fr[2].w > 0 && fr[3].w > 0) {
-            const int left = w.pw % TC;
-            const int capl = 14 * ((fr[2].w + 13) / 14) - fr[2].w, capr = 14 * ((fr[3].w + 13) / 14) - fr[3].w;
-            if (left > 0 && left <= capl + capr) {
-                const int a = std::min(left, capl);
-                w.px0 += a;
-                w.pw -= left;
-                fr[2].w += a;
-                fr[3].x0 = w.px0 + w.pw;
-                fr[3].w = g.nx - fr[3].x0;
-            }
-        }
-        // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
-        w.blk = variant == 2 ? 1 : 0;
-        const int rows_per_tile = w.blk ? 4 * RY : RY;
-        w.ntx = w.pw > 0 ? (w.pw + TC - 1) / TC : 0;
-        w.nty = w.ph > 0 ? (w.ph + rows_per_tile - 1) / rows_per_tile : 0;
-        w.n_plain = w.ntx * w.nty;
-        int accf = 0;
-        for (int k = 0; k < 4; ++k) {
-            const Rect& r = fr[k];
-            w.fx0[k] = r.x0; w.fy0[k] = r.y0; w.fw[k] = r.w; w.fh[k] = r.h;
-            // lanes always run along x: whole-wave groups (62 columns) for strips
-            // spanning x (bottom / top, or the whole grid), 16-lane groups (14
-            // columns, 4 groups stacked along y) for the narrow left / right strips
-            const bool wide = !(k >= 2 && t.plain_w > 0);
-            w.flx[k] = wide ? 1 : 0;
-            const int cols = wide ? kWaveCols : 14, rows = wide ? RQ : 4 * RQ;
-            const bool empty = r.w <= 0 || r.h <= 0;
-            w.fnl[k] = empty ? 1 : (r.w + cols - 1) / cols;
-            w.fnq[k] = empty ? 0 : (r.h + rows - 1) / rows;
-            w.fstart[k] = accf;
-            accf += empty ? 0 : w.fnl[k] * w.fnq[k];
-        }
-        w.fstart[4] = accf;
-        w.n_frame = accf;
-        // work items: wavefront items (variant 0) or block items of 4 wavefronts (variant 2)
-        const int64_t tiles = static_cast<int64_t>(w.blk ? (w.n_frame + 3) / 4 + w.n_plain : w.n_plain + w.n_frame) *
-                              w.ngrp;
-        if (tiles <= 0) return HELM27_OK;
-        const int64_t target = w.blk ? 1024 : 4096;
-        int64_t nzc = (target + tiles - 1) / tiles;
-        int zc = static_cast<int>((g.nz + nzc - 1) / nzc);
-        zc = std::max(2, std::min(16, zc));
-        if (zc_set > 0) zc = zc_set;
-        w.zchunk = std::min(zc, g.nz);
-        w.nzc = (g.nz + w.zchunk - 1) / w.zchunk;
-        w.nrhs = nrhs;
-        const int64_t items = tiles * w.nzc;
-        if (items > (int64_t(1) << 30)) return HELM27_EINVAL;
-        w.n_items = static_cast<int>(items);
-        w.tab_lo = g.idx_lo;
-        w.n_tab = n_tab;
-        w.u = a.u;
-        w.y = a.y;
-        w.b = a.b;
-        w.omega_j = a.omega_j;
-        return launch_wave<R>(w, mode, shifted, RY, RQ, s);
+        int RY = 1;
+        const int st = build_wave_args<R>(g, a.g, u, y, b, omega_j, nrhs, false, w, RY);
+        if (st != HELM27_OK || w.n_items == 0) return st;
+        return launch_wave<R>(w, mode, shifted, RY, frame_rows<R>(), s);
     }
     const int nblk = a.n_plain_blocks + t.n_frame_blocks;
     if (nblk == 0) return HELM27_OK;
@@ -610,6 +629,48 @@ int launch_stencil(const GridOp& g, int mode, double shift_re, double shift_im, 
             return HELM27_EINVAL;
     }
 }
+
+// y_i = A_i u_i for several grids: fused launches of the wavefront kernel,
+// grouped by kernel instance (attenuation, per-row coefficients, mass form)
+template <typename R>
+int launch_stencil_batch(const GridOp* const* g, int n, const void* const* u, void* const* y, const int* nrhs,
+                         hipStream_t s) {
+    constexpr bool fp64 = sizeof(R) == 8;
+    std::vector<WaveArgs<R>> w(static_cast<size_t>(n));
+    std::vector<int> key(static_cast<size_t>(n), -1);
+    for (int i = 0; i < n; ++i) {
+        const GridOp& G = *g[i];
+        if (nrhs[i] == 0) continue;
+        const int n_tab = G.idx_hi - G.idx_lo + 1;
+        if (n_tab <= 0 || static_cast<int64_t>(G.N) * (fp64 ? 16 : 8) >= (int64_t(1) << 31) ||
+            wave_ring_offset(G.d_row_f ? 0 : n_tab, G.nz, fp64) > lds_limit())
+            return HELM27_EINVAL;
+        const GridData<R> gd = grid_data<R>(G, 1.0, 0.0);
+        if (!gd.entry || !gd.ax || !gd.ay || !gd.az) return HELM27_EINVAL;
+        const bool shifted = !(G.att_re == 1.0 && G.att_im == 0.0);
+        int RY = 1;
+        const int st = build_wave_args<R>(G, gd, u[i], y[i], nullptr, 0.0, nrhs[i], true, w[i], RY);
+        if (st != HELM27_OK) return st;
+        if (w[i].n_items == 0) continue;
+        key[i] = (shifted ? 1 : 0) | (gd.rowcoef ? 2 : 0) | (G.mass_a ? 4 : 0);
+    }
+    std::vector<const WaveArgs<R>*> grp;
+    for (int k = 0; k < 8; ++k) {
+        grp.clear();
+        for (int i = 0; i < n; ++i)
+            if (key[i] == k) grp.push_back(&w[i]);
+        if (grp.empty()) continue;
+        const int st = launch_wave_batch<R>(grp.data(), static_cast<int>(grp.size()), (k & 1) != 0, (k & 2) != 0,
+                                            (k & 4) != 0, s);
+        if (st != HELM27_OK) return st;
+    }
+    return HELM27_OK;
+}
+
+template int launch_stencil_batch<float>(const GridOp* const*, int, const void* const*, void* const*, const int*,
+                                         hipStream_t);
+template int launch_stencil_batch<double>(const GridOp* const*, int, const void* const*, void* const*, const int*,
+                                          hipStream_t);
 
 template int launch_stencil<float>(const GridOp&, int, double, double, const void*, void*, const void*, double, int, hipStream_t);
 template int launch_stencil<double>(const GridOp&, int, double, double, const void*, void*, const void*, double, int, hipStream_t);

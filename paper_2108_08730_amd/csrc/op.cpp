@@ -541,6 +541,23 @@ extern "C" int helm27_apply(helm27_op* op, const void* u, void* y, int nrhs, int
     return HELM27_EINVAL;
 }
 
+extern "C" int helm27_apply_many(helm27_op* const* ops, int n_ops, const void* const* u, void* const* y,
+                                 const int* nrhs, int dtype, void* stream) {
+    if (n_ops < 0 || (n_ops > 0 && (!ops || !u || !y || !nrhs))) return HELM27_EINVAL;
+    if (dtype != HELM27_C64 && dtype != HELM27_C128) return HELM27_EINVAL;
+    std::vector<const GridOp*> g(static_cast<size_t>(n_ops));
+    for (int i = 0; i < n_ops; ++i) {
+        if (!ops[i] || nrhs[i] < 0) return HELM27_EINVAL;
+        if (nrhs[i] > 0 && (!u[i] || !y[i] || u[i] == y[i])) return HELM27_EINVAL;
+        if (i > 0 && ops[i]->ctx != ops[0]->ctx) return HELM27_EINVAL;
+        g[i] = &ops[i]->g;
+    }
+    if (n_ops == 0) return HELM27_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dtype == HELM27_C64 ? launch_stencil_batch<float>(g.data(), n_ops, u, y, nrhs, s)
+                               : launch_stencil_batch<double>(g.data(), n_ops, u, y, nrhs, s);
+}
+
 extern "C" int helm27_set_tuning(helm27_op* op, int dtype, int rows_per_wave) {
     if (!op || rows_per_wave < 1 || rows_per_wave > 4) return HELM27_EINVAL;
     if (dtype == HELM27_C64) op->g.plain_ry[0] = rows_per_wave;

@@ -86,6 +86,12 @@ template <typename R>
 int launch_wave(const WaveArgs<R>& a, int mode, bool shifted, int ry, int rq, hipStream_t s);
 template <typename R>
 int frame_rows();
+// apply (MODE_APPLY) of n grids in fused launches of up to 8 grids each; all
+// n share the kernel instance: mass scaled or not (attenuation), per-row
+// coefficients or the table in LDS, mass form.  Per-wavefront tiles, two box
+// rows per wavefront in FP32 (one in FP64 or with the first mass form).
+template <typename R>
+int launch_wave_batch(const WaveArgs<R>* const* w, int n, bool shifted, bool rowc, bool mass_a, hipStream_t s);
 // LDS bytes of the wavefront kernel: the staged weight-table slice (n_tab
 // entries; 0 with per-row coefficients) and the z-axis PML nodes
 size_t wave_lds_bytes(int n_tab, int nz, bool fp64);

@@ -455,7 +455,7 @@ extern "C" int helm27_table_axis(const helm27_table* t, int* spacing, double* v_
 extern "C" void helm27_table_destroy(helm27_table* t) { delete t; }
 
 extern "C" int helm27_fit_fixed(helm27_ctx* ctx, const double* g_list, int n_list, const helm27_table_opts* opts,
-                                helm27_table** out) {
+                                const double* w5_near, helm27_table** out) {
     (void)ctx;
     if (!out || !g_list || n_list <= 0) return HELM27_EINVAL;
     int n_ang = 5;
@@ -474,8 +474,19 @@ extern "C" int helm27_fit_fixed(helm27_ctx* ctx, const double* g_list, int n_lis
             for (int jt = 0; jt < n_ang; ++jt, ++r)
                 dispersion_rows(g_list[l], jt * step * pi / 180.0, jp * step * pi / 180.0, &A[5 * r], &b[r]);
     }
+    // least-squares solution closest to w5_near (minimum norm without it):
+    // near + the minimum-norm solution of A dw = b - A near
+    double w0[5] = {0, 0, 0, 0, 0};
+    if (w5_near)
+        for (int k = 0; k < 5; ++k) {
+            if (!std::isfinite(w5_near[k])) return HELM27_EINVAL;
+            w0[k] = w5_near[k];
+        }
+    for (int i = 0; i < m; ++i)
+        for (int k = 0; k < 5; ++k) b[i] -= A[5 * static_cast<size_t>(i) + k] * w0[k];
     double w5[5];
     if (!minnorm_ls(A, b, m, 5, w5)) return HELM27_ENUMERIC;
+    for (int k = 0; k < 5; ++k) w5[k] += w0[k];
     helm27_table* t = new (std::nothrow) helm27_table;
     if (!t) return HELM27_ENOMEM;
     t->g_min = g_list[0];

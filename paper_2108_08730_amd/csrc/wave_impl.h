@@ -1016,10 +1016,11 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
 // NB > 1 (FP32 block tiles, one row per wavefront): box items take NB
 // right-hand sides per wavefront (box_item_nb); frame items run their NB
 // right-hand sides one after another.
-template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
-void wave27_kernel(WaveArgs<R> a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+// The body of one block: stage the grid's table slice and z nodes, then
+// take work items lb, lb + nb, ... (block granularity; with !BLK each of the
+// block's wavefronts takes its own item of the block's group of four).
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA>
+__device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb, unsigned char* smem_raw) {
     const GridData<R>& g = a.g;
     const int n_tab = ROWC ? 0 : a.n_tab;
     TabEntry<R>* tab = reinterpret_cast<TabEntry<R>*>(smem_raw);
@@ -1041,12 +1042,6 @@ void wave27_kernel(WaveArgs<R> a) {
                              static_cast<size_t>(g.nz) * sizeof(AxisNode<R>) + 15) & ~static_cast<size_t>(15);
     typename V2<R>::T* ring = reinterpret_cast<typename V2<R>::T*>(smem_raw + ring_off);
     __syncthreads();
-    // XCD-contiguous block order: block b runs on XCD b % 8; the grid is at
-    // most one resident wave per slot and each wave strides over the items
-    const int nb = static_cast<int>(gridDim.x);
-    const int bx = static_cast<int>(blockIdx.x);
-    const int xcd = bx & 7, q8 = nb >> 3, r8 = nb & 7;
-    const int lb = xcd * q8 + min(xcd, r8) + (bx >> 3);
     const int wave = uni(static_cast<int>(threadIdx.x) >> 6);
     const int lane = static_cast<int>(threadIdx.x) & 63;
     if (!BLK) {
@@ -1106,6 +1101,43 @@ void wave27_kernel(WaveArgs<R> a) {
             }
         }
     }
+}
+
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+void wave27_kernel(WaveArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // XCD-contiguous block order: block b runs on XCD b % 8; the grid is at
+    // most one resident wave per slot and each wave strides over the items
+    const int nb = static_cast<int>(gridDim.x);
+    const int bx = static_cast<int>(blockIdx.x);
+    const int xcd = bx & 7, q8 = nb >> 3, r8 = nb & 7;
+    const int lb = xcd * q8 + min(xcd, r8) + (bx >> 3);
+    wave27_body<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA>(a, nb, lb, smem_raw);
+}
+
+// Several grids in one launch (batches of small grids): grid o owns blocks
+// [bstart[o], bstart[o + 1]); each block stages its own grid's table slice
+// and z nodes and runs the per-wavefront items of that grid.  The arguments
+// travel by value in the kernel-argument segment (kWaveBatch grids at most).
+constexpr int kWaveBatch = 8;
+template <typename R>
+struct WaveBatch {
+    WaveArgs<R> a[kWaveBatch];
+    int bstart[kWaveBatch + 1];
+    int n;
+};
+
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool MA>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+void wave27_batch_kernel(WaveBatch<R> B) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int bx = static_cast<int>(blockIdx.x);
+    int o = 0;
+    while (o + 1 < B.n && bx >= B.bstart[o + 1]) ++o;
+    o = uni(o);
+    wave27_body<R, MODE, SHIFTED, RY, RQ, ROWC, false, 1, MA>(B.a[o], B.bstart[o + 1] - B.bstart[o], bx - B.bstart[o],
+                                                              smem_raw);
 }
 
 template <typename R> struct FrameRows;

@@ -79,17 +79,24 @@ def test_table_matches_oracle_other_grids(gmin, gmax, dg, lam, order, tol):
                                        diff="first" if order == 1 else "second") < 1e-12
 
 
+@pytest.mark.parametrize("anchor", [False, True])
 @pytest.mark.parametrize("glist", [[4.0], [4.0, 6.0, 8.0, 10.0]])
-def test_fixed_weights_match_oracle(glist):
-    """G4 / Gm weights: minimum-norm least squares, library (Jacobi SVD) vs
-    oracle (LAPACK gelsd)."""
+def test_fixed_weights_match_oracle(glist, anchor):
+    """G4 / Gm weights, library (Jacobi SVD) vs oracle (LAPACK gelsd): the
+    minimum-norm least-squares solution, or the one closest to a given weight
+    vector (here the oracle table's entry at G = 4)."""
     g = np.array(glist, np.float64)
+    near = None
+    if anchor:
+        Gs, W = T.build_table(3.0, 6.0, 0.05, 1e-3)
+        near = np.ascontiguousarray(W[20])
     h = C.c_void_p()
-    L.check(L.lib.helm27_fit_fixed(None, g.ctypes.data_as(C.POINTER(C.c_double)), len(g), None, C.byref(h)))
+    L.check(L.lib.helm27_fit_fixed(None, g.ctypes.data_as(C.POINTER(C.c_double)), len(g), None,
+                                   near.ctypes.data_as(C.POINTER(C.c_double)) if anchor else None, C.byref(h)))
     w = np.zeros((1, 7))
     L.check(L.lib.helm27_table_weights(h, w.ctypes.data_as(C.POINTER(C.c_double)), None, None, None))
     L.lib.helm27_table_destroy(h)
-    w_or = T.complete_weights(T.fit_fixed(glist))
+    w_or = T.complete_weights(T.fit_fixed(glist, near=near))
     assert np.max(np.abs(w[0] - w_or)) < 1e-10
 
 

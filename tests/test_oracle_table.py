@@ -139,6 +139,44 @@ def test_g4_worst_error_near_5p5():
     assert e4 < 1e-4
 
 
+def _symbols(w7, n=33):
+    """Stiffness bracket Q and mass function J of Sec. 2.2 over the grid's
+    wavenumbers q h in [0, pi]^3."""
+    q = np.linspace(0.0, np.pi, n)
+    ca, cb, cc = np.meshgrid(np.cos(q), np.cos(q), np.cos(q), indexing="ij")
+    A, B, C = ca * cb * cc, ca * cb + ca * cc + cb * cc, ca + cb + cc
+    ws1, ws2, ws3, wm0, wm1, wm2, wm3 = w7
+    Q = ws1 * (3 - C) + ws2 / 3 * (6 - C - B) + 2 * ws3 / 4 * (3 - 3 * A + B - C)
+    J = wm0 + 2 * wm1 * C + 4 * wm2 * B + 8 * wm3 * A
+    return Q.ravel()[1:], J.ravel()
+
+
+def test_g4_null_space_and_anchored_solution():
+    """The N_G = 1 problem at G = 4 has rank 3: a plane of least-squares
+    solutions.  The minimum-norm member has a stiffness symbol
+    that changes sign and a negative mass symbol (spurious grid modes); the
+    member closest to the smoothed table's entry at G = 4 fits G = 4 exactly
+    as well, keeps both symbols positive, and has its worst error for G > 4
+    at G ~ 5.5 (Sec. 2.2)."""
+    th, ph = T.angle_grid()
+    H, g = T.dispersion_rows(4.0, th, ph)
+    assert np.linalg.matrix_rank(H, tol=1e-10 * np.linalg.norm(H, 2)) == 3
+    Gs, W = T.build_table(3.0, 6.0, 0.05, 1e-3)
+    w_min = T.fit_fixed([4.0])
+    w_anc = T.fit_fixed([4.0], near=W[20])
+    r_min = np.linalg.norm(H @ w_min - g)
+    r_anc = np.linalg.norm(H @ w_anc - g)
+    assert abs(r_anc - r_min) <= 1e-9 * r_min
+    Qm, Jm = _symbols(T.complete_weights(w_min))
+    Qa, Ja = _symbols(T.complete_weights(w_anc))
+    assert Qm.min() < 0 and Jm.min() < 0
+    assert Qa.min() > 0 and Ja.min() > 0
+    w7 = T.complete_weights(w_anc)
+    Gf = np.linspace(4.2, 20.0, 791)
+    e = np.array([np.max(np.abs(T.phase_velocity(x, th, ph, w7) - 1)) for x in Gf])
+    assert 5.0 <= Gf[np.argmax(e)] <= 6.0
+
+
 def test_gm_trades_accuracy_at_g4():
     """Weights fitted jointly for G = 4, 6, 8, 10 are less accurate at G = 4
     than the G4 weights but better balanced over 4..10 (Sec. 2.2)."""
