@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhelm27.so")
+# HELM27_LIB names another build of the same library (e.g. the host-sanitizer
+# build written by build.py --sanitize)
+LIB_PATH = os.environ.get("HELM27_LIB") or os.path.join(_HERE, "libhelm27.so")
 
 OK, EINVAL, ENOMEM, EADMIT, ENOCONV, ENUMERIC, EDEVICE, ERANGE, ENOTFOUND, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 C64, C128 = 1, 2
@@ -97,7 +99,8 @@ def _load():
         "helm27_table_axis": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_int)]),
         "helm27_op_table_weights": (C.c_int, [P, C.POINTER(C.c_double)]),
-        "helm27_fit_fixed": (C.c_int, [P, C.POINTER(C.c_double), C.c_int, C.POINTER(TableOpts), C.POINTER(P)]),
+        "helm27_fit_fixed": (C.c_int, [P, C.POINTER(C.c_double), C.c_int, C.POINTER(TableOpts),
+                                       C.POINTER(C.c_double), C.POINTER(P)]),
         "helm27_table_weights": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "helm27_table_destroy": (None, [P]),
@@ -110,6 +113,8 @@ def _load():
                                                   C.c_void_p, C.POINTER(IndexStats), C.c_void_p]),
         "helm27_export_csr": (C.c_int, [P, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p, C.c_void_p]),
         "helm27_apply": (C.c_int, [P, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+        "helm27_apply_many": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_int),
+                                        C.c_int, C.c_void_p]),
         "helm27_set_tuning": (C.c_int, [P, C.c_int, C.c_int]),
         "helm27_set_kernel_variant": (C.c_int, [P, C.c_int]),
         "helm27_set_zchunk": (C.c_int, [P, C.c_int]),
