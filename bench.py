@@ -340,6 +340,99 @@ def serving(args, torch, api, synth):
     }
 
 
+def serving_config4(args, torch, api, synth):
+    """The serving-mix configuration at full shape: seeded random-field models,
+    frequencies uniform in 2.5-10 Hz, h = 1500 / (4 f) (smallest G = 4), grids
+    64^3, 96^3, 128^3, 192^2 x 96 and 256^2 x 128, 1-128 surface sources per
+    request (log-uniform).  Pass 1 submits every request at once and measures
+    the capacity (requests/s); pass 2 replays the same requests with Poisson
+    arrivals at `--serve-load` (0.7) of that capacity and reports p50/p99
+    latency (submit to done).  Requests too large for half the HBM budget
+    are solved in chunks of right-hand sides.  The FP64 single-RHS baseline
+    solves the first source of the first `--serve-fp64-sample` requests one
+    at a time."""
+    n = args.serve_requests
+    dims_choices = ((64, 64, 64), (96, 96, 96), (128, 128, 128), (192, 192, 96), (256, 256, 128))
+    reqs = synth.serving_requests(n, seed=21, rate_hz=1.0, dims_choices=dims_choices, nrhs_max=128)
+    models = []
+    for k, r in enumerate(reqs):
+        models.append(synth.random_field_model(r["dims"], r["h"], seed=r["model_seed"] % 1000003))
+        print(f"serving: model {k + 1}/{n} {r['dims']}", file=sys.stderr, flush=True)
+    srcs = [synth.surface_sources(r["dims"], r["nrhs"], 9, 10) for r in reqs]
+    table = (2.5, 60.0, 0.05, 1e-3)
+    # admission budget 200 GiB: the outputs (complex128 [nrhs][N] per request,
+    # allocated at submission) live outside it
+    ctx = api.Context(0, hbm_budget=200 << 30)
+
+    def run(arrivals):
+        srv = api.Server(ctx, max_slots=4, table=table, tol=1e-6)
+        t0 = time.perf_counter()
+        tickets = []
+        for r, v, sr, ta in zip(reqs, models, srcs, arrivals):
+            wait = t0 + ta - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(v, r["h"], r["freq"], sr, npml=8, model_key=0))
+        res = []
+        for k, (t, out) in enumerate(tickets):
+            res.append(srv.wait(t, timeout=3600.0))
+            del out
+            print(f"serving: request {k + 1}/{n} done after {time.perf_counter() - t0:.1f} s "
+                  f"(status {res[-1]['status']}, {res[-1]['inner_iters']} steps)", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        srv.stop()
+        torch.cuda.empty_cache()
+        lat = np.array([(x["t_done"] - x["t_submit"]) * 1e3 for x in res])
+        return wall, lat, res
+
+    nrhs_tot = int(sum(r["nrhs"] for r in reqs))
+    wall1, lat1, res1 = run([0.0] * n)
+    cap = n / wall1
+    rate = args.serve_load * cap
+    rng = np.random.Generator(np.random.PCG64(22))
+    arr = np.cumsum(rng.exponential(1.0 / rate, n))
+    wall2, lat2, res2 = run(list(arr))
+    ok = all(x["status"] == 0 and x["converged"] == 1 for x in res1 + res2)
+    # FP64 single-RHS baseline on a sample
+    tab = ctx.build_table(*table)
+    t64, n64, worst = 0.0, 0, 0.0
+    for r, v, sr in list(zip(reqs, models, srcs))[:args.serve_fp64_sample]:
+        op = ctx.assemble(tab, v, r["h"], r["freq"], npml=8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = op.solve([sr[0]], tol=1e-6, precision="fp64", max_inner=6000)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t1
+        print(f"serving: fp64 sample {n64 + 1} {r['dims']} {time.perf_counter() - t1:.1f} s", file=sys.stderr,
+              flush=True)
+        n64 += 1
+        worst = max(worst, st["max_relres"])
+        del op
+    # the mixed-precision single-RHS solve of the same sample, for the like-for-like per-RHS ratio
+    t32 = 0.0
+    for r, v, sr in list(zip(reqs, models, srcs))[:args.serve_fp64_sample]:
+        op = ctx.assemble(tab, v, r["h"], r["freq"], npml=8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        op.solve([sr[0]], tol=1e-6)
+        torch.cuda.synchronize()
+        t32 += time.perf_counter() - t1
+        del op
+    return {
+        "requests": n, "rhs": nrhs_tot, "grids": [list(d) for d in dims_choices],
+        "nrhs_per_request": [r["nrhs"] for r in reqs], "grid_points": [int(np.prod(r["dims"])) for r in reqs],
+        "capacity_pass": {"wall_s": wall1, "requests_per_s": cap, "rhs_per_s": nrhs_tot / wall1,
+                          "p50_ms": float(np.percentile(lat1, 50)), "p99_ms": float(np.percentile(lat1, 99))},
+        "poisson_pass": {"load": args.serve_load, "rate_hz": rate, "wall_s": wall2, "requests_per_s": n / wall2,
+                         "rhs_per_s": nrhs_tot / wall2, "p50_ms": float(np.percentile(lat2, 50)),
+                         "p99_ms": float(np.percentile(lat2, 99)), "max_ms": float(lat2.max())},
+        "all_converged": ok, "max_relres": max(x["max_relres"] for x in res1 + res2),
+        "fp64_single_rhs_sample": {"solves": n64, "s_per_rhs": t64 / max(1, n64), "max_relres": worst},
+        "mixed_single_rhs_sample": {"solves": n64, "s_per_rhs": t32 / max(1, n64)},
+        "served_rhs_per_s_over_fp64_single": (nrhs_tot / wall1) * (t64 / max(1, n64)),
+    }
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -420,6 +513,11 @@ def main():
                     help="--solve-only: 1 = coarse levels take tables widened for their own G range")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving-mix requests (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="serving-mix Poisson arrival rate (1/s)")
+    ap.add_argument("--serve-config4", action="store_true",
+                    help="only the full-shape serving mix: grids to 256^2 x 128, 1-128 sources, capacity pass "
+                         "then Poisson arrivals at --serve-load of capacity (use --serve-requests 32)")
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-fp64-sample", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no multi-GPU "
@@ -436,6 +534,9 @@ def main():
         return
     if args.solve_only:
         solve_only(args, torch, api, synth)
+        return
+    if args.serve_config4:
+        print(json.dumps({"serving_config4": serving_config4(args, torch, api, synth)}), flush=True)
         return
 
     wl = LARGE

@@ -427,7 +427,11 @@ int helm27_solve_rhs(helm27_op* op, const void* b, void* u, int nrhs,
  * workspace) fits in the context's HBM budget next to the requests already
  * running.  Admitted requests run concurrently, each on its own HIP stream, so
  * their kernels overlap on the device; all right-hand sides of a request are
- * solved together by the multi-RHS kernels.  Operators and their multigrid
+ * solved together by the multi-RHS kernels, unless together they would need
+ * more than half the budget: then the request is solved in chunks of the
+ * largest right-hand-side count that fits in half the budget, one after
+ * another on one operator (its stats: the chunks' total steps and seconds,
+ * the worst residual, converged only if every chunk did).  Operators and their multigrid
  * hierarchies stay resident in a cache keyed by (model_key, grid, h, f, PML)
  * for later requests on the same model.  Timestamps are seconds on the host's
  * steady clock. */
@@ -436,6 +440,7 @@ typedef struct {
     helm27_solve_opts solve;     /* solver options of every request */
     double table_gmin, table_gmax, table_dg, table_lambda;   /* table built at start (2.5, 60, 0.05, 1e-3) */
     int    max_cached_ops;       /* resident operators kept for reuse (default 8) */
+    int    max_chunk_rhs;        /* cap on right-hand sides per solve (0: by footprint only) */
 } helm27_serve_opts;
 
 typedef struct {
@@ -460,8 +465,8 @@ void helm27_serve_opts_default(helm27_serve_opts* opts);
  * started, bad options), ENOMEM. */
 int helm27_serve_start(helm27_ctx* ctx, const helm27_serve_opts* opts);
 /* Queue a request; returns a ticket.  Errors: EINVAL (bad request or not
- * started), EADMIT (the request alone exceeds the HBM budget), ERANGE (a
- * source outside the grid or in the PML). */
+ * started), EADMIT (even one right-hand side exceeds the HBM budget), ERANGE
+ * (a source outside the grid or in the PML). */
 int helm27_serve_submit(helm27_ctx* ctx, const helm27_request* req, uint64_t* ticket);
 /* Result of a ticket: HELM27_OK with *res filled when done, HELM27_EAGAIN while
  * queued or running, HELM27_ENOTFOUND for an unknown ticket. */

@@ -68,7 +68,7 @@ class SolveStats(C.Structure):
 class ServeOpts(C.Structure):
     _fields_ = [("max_slots", C.c_int), ("solve", SolveOpts), ("table_gmin", C.c_double),
                 ("table_gmax", C.c_double), ("table_dg", C.c_double), ("table_lambda", C.c_double),
-                ("max_cached_ops", C.c_int)]
+                ("max_cached_ops", C.c_int), ("max_chunk_rhs", C.c_int)]
 
 
 class Request(C.Structure):

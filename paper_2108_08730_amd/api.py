@@ -353,12 +353,14 @@ class Server:
     """Request loop over a context (helm27_serve_*): submit solves at any time,
     poll or wait for their results."""
 
-    def __init__(self, ctx: Context, max_slots=4, table=(2.5, 60.0, 0.05, 1e-3), max_cached_ops=8, **solve):
+    def __init__(self, ctx: Context, max_slots=4, table=(2.5, 60.0, 0.05, 1e-3), max_cached_ops=8, max_chunk_rhs=0,
+                 **solve):
         o = L.ServeOpts()
         L.lib.helm27_serve_opts_default(C.byref(o))
         o.max_slots = max_slots
         o.table_gmin, o.table_gmax, o.table_dg, o.table_lambda = table
         o.max_cached_ops = max_cached_ops
+        o.max_chunk_rhs = max_chunk_rhs
         so = solve_opts(**solve)
         o.solve = so
         self._ctx = ctx

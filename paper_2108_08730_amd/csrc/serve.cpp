@@ -4,7 +4,9 @@
 // non-blocking HIP stream) takes the first queued request whose estimated
 // device footprint fits in the free part of the HBM budget, so requests that
 // arrive while others run start as soon as a slot and memory free up, and
-// their kernels overlap on the device.  Operators (with their multigrid
+// their kernels overlap on the device.  A request whose right-hand sides
+// together would need more than half the budget is solved in chunks of
+// right-hand sides, one after another on one operator.  Operators (with their multigrid
 // hierarchies) stay resident in a cache keyed by the model and the
 // discretisation; cached operators count against the budget and are evicted
 // least-recently-used when an admission needs the memory.
@@ -55,6 +57,7 @@ struct Job {
     helm27_pml pml;
     std::vector<double> src;
     int nrhs;
+    int chunk;                   // right-hand sides per solve (all of them unless the request is split)
     uint64_t model_key;
     void* out;
     size_t footprint;
@@ -84,6 +87,39 @@ static size_t op_estimate(int64_t N) {
 
 static size_t job_footprint(const helm27_serve_opts& o, int64_t N, int nrhs) {
     return op_estimate(N) + solve_footprint(N, nrhs, o.solve.restart, o.solve.precision, o.solve.mg_levels);
+}
+
+// Right-hand sides per solve: all of them when the request needs at most half
+// the budget, else the largest count that does (at least one), so a request
+// too large to share the device is solved in chunks, one after another, on
+// one operator, leaving room for other requests.
+static int job_chunk(const helm27_serve_opts& o, int64_t N, int nrhs, size_t budget) {
+    if (o.max_chunk_rhs > 0 && nrhs > o.max_chunk_rhs) nrhs = o.max_chunk_rhs;
+    if (job_footprint(o, N, nrhs) <= budget / 2) return nrhs;
+    int lo = 1, hi = nrhs;   // largest c with footprint(c) <= budget / 2 (footprint grows with c)
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (job_footprint(o, N, mid) <= budget / 2) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// statistics of a request solved in chunks: totals of the work, worst of the accuracy
+static void merge_stats(helm27_solve_stats* a, const helm27_solve_stats& b, bool first) {
+    if (first) {
+        *a = b;
+        return;
+    }
+    a->outer_iters = std::max(a->outer_iters, b.outer_iters);
+    a->inner_iters += b.inner_iters;
+    a->converged = a->converged && b.converged;
+    a->max_relres = std::max(a->max_relres, b.max_relres);
+    a->seconds += b.seconds;
+    a->mg_levels = b.mg_levels;
+    a->coarse_clamped = std::max(a->coarse_clamped, b.coarse_clamped);
+    a->coarse_tables = std::max(a->coarse_tables, b.coarse_tables);
+    a->inner_est = std::max(a->inner_est, b.inner_est);
 }
 
 // Evict least-recently-used cached operators until `need` bytes fit (lock held).
@@ -164,8 +200,24 @@ static void worker_main(Server* S) {
                            stream, &op);
         }
         helm27_solve_stats stats{};
-        if (st == HELM27_OK)
-            st = helm27_solve(op, job->src.data(), job->out, job->nrhs, &S->opts.solve, &stats, stream);
+        if (st == HELM27_OK) {
+            const int64_t N = static_cast<int64_t>(job->nx) * job->ny * job->nz;
+            int agg = HELM27_OK;
+            for (int r0 = 0; r0 < job->nrhs; r0 += job->chunk) {
+                const int nc = std::min(job->chunk, job->nrhs - r0);
+                helm27_solve_stats s1{};
+                void* out = static_cast<char*>(job->out) + static_cast<size_t>(r0) * N * 16;
+                const int s = helm27_solve(op, job->src.data() + 5 * static_cast<size_t>(r0), out, nc, &S->opts.solve,
+                                           &s1, stream);
+                merge_stats(&stats, s1, r0 == 0);
+                if (s == HELM27_ENOCONV) agg = HELM27_ENOCONV;   // keep solving the other chunks
+                else if (s != HELM27_OK) {
+                    agg = s;
+                    break;
+                }
+            }
+            st = agg;
+        }
         hipStreamSynchronize(stream);
         if (op) solver_trim(op);
         {
@@ -214,6 +266,7 @@ extern "C" void helm27_serve_opts_default(helm27_serve_opts* o) {
     o->table_dg = 0.05;
     o->table_lambda = 1e-3;
     o->max_cached_ops = 8;
+    o->max_chunk_rhs = 0;
 }
 
 extern "C" int helm27_serve_start(helm27_ctx* ctx, const helm27_serve_opts* opts) {
@@ -223,7 +276,7 @@ extern "C" int helm27_serve_start(helm27_ctx* ctx, const helm27_serve_opts* opts
     helm27_serve_opts o;
     if (opts) o = *opts;
     else helm27_serve_opts_default(&o);
-    if (o.max_slots < 1 || o.max_slots > 16 || o.max_cached_ops < 0) return HELM27_EINVAL;
+    if (o.max_slots < 1 || o.max_slots > 16 || o.max_cached_ops < 0 || o.max_chunk_rhs < 0) return HELM27_EINVAL;
     Server* S = new (std::nothrow) Server;
     if (!S) return HELM27_ENOMEM;
     S->ctx = ctx;
@@ -252,7 +305,8 @@ extern "C" int helm27_serve_submit(helm27_ctx* ctx, const helm27_request* r, uin
         }
     const int64_t N = static_cast<int64_t>(r->nx) * r->ny * r->nz;
     auto job = std::make_shared<Job>();
-    job->footprint = job_footprint(S->opts, N, r->nrhs);
+    job->chunk = job_chunk(S->opts, N, r->nrhs, ctx->hbm_budget);
+    job->footprint = job_footprint(S->opts, N, job->chunk);
     if (job->footprint > ctx->hbm_budget) return HELM27_EADMIT;
     job->vel.resize(N);
     hipPointerAttribute_t attr;
