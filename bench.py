@@ -232,12 +232,21 @@ def solve_steps(args, torch, api, synth, ctx):
         lat.append(time.perf_counter() - t0)
     total = time.perf_counter() - t_start
     lat_ms = np.array(lat) * 1e3
+    # error of the timed (mixed-precision, 1e-6) solution against an FP64 solve
+    # of the same system to 1e-11 (untimed)
+    tab = ctx.build_table(*wl["table"])
+    op = ctx.assemble(tab, c_dev, h, f, npml=npml)
+    um, _ = op.solve([wl["src"]], tol=wl["tol"])
+    ur, st_r = op.solve([wl["src"]], tol=1e-11, precision="fp64", max_inner=3000)
+    err = float(torch.linalg.vector_norm(um - ur) / torch.linalg.vector_norm(ur))
+    del op, um, ur
     return {"workload": "gradz101: 101^3 grid, c(z)=1500+0.7z m/s, h=25 m, f=5 Hz (G 12..26), 10-node PML, "
                         "1 point source at (50,50,11), rel. residual 1e-6; step = table + assembly + solve",
             "solves_per_s": args.solve_steps / total, "steps": args.solve_steps,
             "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
             "inner_iters": st["inner_iters"], "outer_iters": st["outer_iters"], "relres": st["max_relres"],
             "converged": bool(st["converged"]),
+            "error_vs_fp64_solve": err, "fp64_reference_relres": st_r["max_relres"],
             "phase_ms": {k: float(np.mean(v) * 1e3) for k, v in phases.items()}}
 
 
