@@ -79,9 +79,6 @@ struct WaveArgs {
 
 constexpr int kWaveCols = 62;      // output columns per wavefront (lanes 1..62)
 
-// which work items a launch covers
-enum WaveWhich { WAVE_BOTH = 0, WAVE_PLAIN = 1, WAVE_FRAME = 2 };
-
 template <typename R>
 int launch_wave(const WaveArgs<R>& a, int mode, bool shifted, int ry, int rq, hipStream_t s);
 template <typename R>
