@@ -353,7 +353,7 @@ typedef struct {
                             same kernels as the eager launches, so the same
                             results); 0 = eager launches (default 1) */
     int    verbose;
-    double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0.4) */
+    double mg_shift_re;  /* real part a of the preconditioner's mass factor (default 0) */
     int    reorth_always;/* 1: second classical Gram-Schmidt pass at every Arnoldi step;
                             0 (default): per right-hand side only when the first pass
                             leaves less than 1/sqrt(2) of the vector's norm */

@@ -46,5 +46,28 @@ template <typename R> __device__ __forceinline__ void st(typename V2<R>::T* p, C
     v.y = a.im;
     *p = v;
 }
+// streaming (non-temporal) access for data touched once: it does not evict
+// reused data from the caches
+template <typename R> using NtV2 = R __attribute__((ext_vector_type(2)));
+template <typename R> __device__ __forceinline__ Cx<R> ld_nt(const typename V2<R>::T* p) {
+    const NtV2<R> v = __builtin_nontemporal_load(reinterpret_cast<const NtV2<R>*>(p));
+    return {v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void st_nt(typename V2<R>::T* p, Cx<R> a) {
+    NtV2<R> v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<NtV2<R>*>(p));
+}
+// XCD-contiguous block order for a grid of one point per thread: block b runs
+// on XCD b % 8 (blocks are dispatched round robin over the eight XCDs), so
+// logical block xcd * (nb / 8) + ... gives each XCD a contiguous range of
+// points and the neighbouring rows and planes a block reads are ones its own
+// XCD's L2 has just fetched
+__device__ __forceinline__ int64_t xcd_block() {
+    const int nb = static_cast<int>(gridDim.x), bx = static_cast<int>(blockIdx.x);
+    const int xcd = bx & 7, q8 = nb >> 3, r8 = nb & 7;
+    return static_cast<int64_t>(xcd) * q8 + (xcd < r8 ? xcd : r8) + (bx >> 3);
+}
 
 }  // namespace h27

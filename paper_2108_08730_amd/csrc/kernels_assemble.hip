@@ -5,6 +5,7 @@
 // same binary64 result as the same formula evaluated anywhere else.
 #include "stencil.h"
 
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -204,7 +205,7 @@ int launch_select_index(const float* c, uint16_t* idx, int64_t N, double fh, dou
 }
 
 // ---------------------------------------------------------------------------
-// 27 coefficients of one row, written to coef[s * N + i] (s = (dz+1)*9 +
+// 27 coefficients of one row, written to coef_at(i, s) (s = (dz+1)*9 +
 // (dy+1)*3 + (dx+1)); zero where the neighbour lies outside the grid.
 template <typename R>
 __global__ void fill_stored_kernel(GridData<R> g, typename V2<R>::T* __restrict__ coef) {
@@ -271,7 +272,7 @@ __global__ void fill_stored_kernel(GridData<R> g, typename V2<R>::T* __restrict_
                             val = sig * stiff + kc * mass;
                         }
                     }
-                    st<R>(coef + static_cast<int64_t>(s) * N + i, val);
+                    st<R>(coef + coef_at(i, s), val);
                 }
     }
 }
@@ -326,22 +327,24 @@ template int launch_fill_stored<float>(const GridOp&, void*, double, double, hip
 template int launch_fill_stored<double>(const GridOp&, void*, double, double, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Stored-coefficient apply: y_i = sum_s coef[s][i] u[i + off_s].  The 27
-// coefficients of a row are streamed once (coalesced, structure of arrays) and
-// reused for every right-hand side; u neighbours come through the caches.
+// Stored-coefficient apply: y_i = sum_s A_is u[i + off_s].  One point per
+// thread, blocks in XCD-contiguous order.  The 27 coefficients of a row are
+// streamed once (coalesced 64-row blocks, non-temporal so they do not evict u
+// from L2) and reused for every right-hand side; u neighbours come through
+// the caches; y is written non-temporally.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void apply_stored_kernel(GridData<R> g, const typename V2<R>::T* __restrict__ coef,
                                                               const typename V2<R>::T* __restrict__ u,
                                                               typename V2<R>::T* __restrict__ y, int nrhs) {
     const int64_t N = g.N;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i = xcd_block() * kBlock + threadIdx.x;
+    if (i < N) {
         const int x = static_cast<int>(i % g.nx);
         const int yy = static_cast<int>((i / g.nx) % g.ny);
         const int z = static_cast<int>(i / g.plane);
         Cx<R> cf[27];
 #pragma unroll
-        for (int s = 0; s < 27; ++s) cf[s] = ld<R>(coef + static_cast<int64_t>(s) * N + i);
+        for (int s = 0; s < 27; ++s) cf[s] = ld_nt<R>(coef + coef_at(i, s));
         const bool xm = x > 0, xp = x < g.nx - 1, ym = yy > 0, yp = yy < g.ny - 1, zm = z > 0, zp = z < g.nz - 1;
         for (int r = 0; r < nrhs; ++r) {
             const typename V2<R>::T* ur = u + static_cast<int64_t>(r) * N;
@@ -353,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void apply_stored_kernel(GridData<R> g, con
                                 (dz < 0 ? zm : (dz > 0 ? zp : true));
                 if (ok) cmac(acc, cf[s], ld<R>(ur + i + dx + static_cast<int64_t>(g.nx) * dy + g.plane * dz));
             }
-            st<R>(y + static_cast<int64_t>(r) * N + i, acc);
+            st_nt<R>(y + static_cast<int64_t>(r) * N + i, acc);
         }
     }
 }
@@ -361,7 +364,8 @@ __global__ __launch_bounds__(kBlock) void apply_stored_kernel(GridData<R> g, con
 template <typename R>
 int launch_apply_stored(const GridOp& g, const void* coef, const void* u, void* y, int nrhs, hipStream_t s) {
     GridData<R> d = make_grid_data<R>(g, 1.0, 0.0);
-    const int64_t blocks = (g.N + kBlock - 1) / kBlock;
+    const int64_t blocks = (g.N + kBlock - 1) / kBlock;   // one point per thread
+    if (blocks > INT_MAX) return HELM27_EINVAL;
     hipLaunchKernelGGL(apply_stored_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
                        static_cast<const typename V2<R>::T*>(coef), static_cast<const typename V2<R>::T*>(u),
                        static_cast<typename V2<R>::T*>(y), nrhs);
@@ -372,9 +376,10 @@ template int launch_apply_stored<float>(const GridOp&, const void*, const void*,
 template int launch_apply_stored<double>(const GridOp&, const void*, const void*, void*, int, hipStream_t);
 
 // Transposed stored-coefficient apply: y_i = sum_s A[i + off_s][i] u[i + off_s]
-// = sum_s coef[26 - s][i + off_s] u[i + off_s] (the entry of row j = i + off_s
+// = sum_s A_{j, 26 - s} u[j] with j = i + off_s (the entry of row j
 // towards i sits at the opposite offset), or with b: y = b - A^T u.  The
-// coefficients are read at the neighbour's index, as coalesced as u.
+// coefficients are read at the neighbour's index, as coalesced as u.  Block
+// order and caching as the stored apply.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void apply_stored_t_kernel(GridData<R> g,
                                                                 const typename V2<R>::T* __restrict__ coef,
@@ -382,8 +387,8 @@ __global__ __launch_bounds__(kBlock) void apply_stored_t_kernel(GridData<R> g,
                                                                 const typename V2<R>::T* __restrict__ b,
                                                                 typename V2<R>::T* __restrict__ y, int nrhs) {
     const int64_t N = g.N;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i = xcd_block() * kBlock + threadIdx.x;
+    if (i < N) {
         const int x = static_cast<int>(i % g.nx);
         const int yy = static_cast<int>((i / g.nx) % g.ny);
         const int z = static_cast<int>(i / g.plane);
@@ -398,11 +403,11 @@ __global__ __launch_bounds__(kBlock) void apply_stored_t_kernel(GridData<R> g,
                                 (dz < 0 ? zm : (dz > 0 ? zp : true));
                 if (ok) {
                     const int64_t j = i + dx + static_cast<int64_t>(g.nx) * dy + g.plane * dz;
-                    cmac(acc, ld<R>(coef + static_cast<int64_t>(26 - s) * N + j), ld<R>(ur + j));
+                    cmac(acc, ld_nt<R>(coef + coef_at(j, 26 - s)), ld<R>(ur + j));
                 }
             }
-            if (b) acc = ld<R>(b + static_cast<int64_t>(r) * N + i) - acc;
-            st<R>(y + static_cast<int64_t>(r) * N + i, acc);
+            if (b) acc = ld_nt<R>(b + static_cast<int64_t>(r) * N + i) - acc;
+            st_nt<R>(y + static_cast<int64_t>(r) * N + i, acc);
         }
     }
 }
@@ -411,7 +416,8 @@ template <typename R>
 int launch_apply_stored_t(const GridOp& g, const void* coef, const void* u, void* y, const void* b, int nrhs,
                           hipStream_t s) {
     GridData<R> d = make_grid_data<R>(g, 1.0, 0.0);
-    const int64_t blocks = (g.N + kBlock - 1) / kBlock;
+    const int64_t blocks = (g.N + kBlock - 1) / kBlock;   // one point per thread
+    if (blocks > INT_MAX) return HELM27_EINVAL;
     hipLaunchKernelGGL(apply_stored_t_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, d,
                        static_cast<const typename V2<R>::T*>(coef), static_cast<const typename V2<R>::T*>(u),
                        static_cast<const typename V2<R>::T*>(b), static_cast<typename V2<R>::T*>(y), nrhs);

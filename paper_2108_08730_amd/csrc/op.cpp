@@ -401,13 +401,13 @@ int op_create(helm27_ctx* ctx, const helm27_table* t, const float* vel, int nx, 
         if ((st = launch_gam_average<double>(g, g.d_row_d, stream))) return fail(st);
     }
     if (flags & HELM27_STORE_C64) {
-        if (hipMalloc(&op->d_coef_f, 27 * N * sizeof(float2)) != hipSuccess) return fail(HELM27_ENOMEM);
-        g.bytes += 27 * N * sizeof(float2);
+        if (hipMalloc(&op->d_coef_f, coef_elems(N) * sizeof(float2)) != hipSuccess) return fail(HELM27_ENOMEM);
+        g.bytes += coef_elems(N) * sizeof(float2);
         if ((st = launch_fill_stored<float>(g, op->d_coef_f, 1.0, 0.0, stream))) return fail(st);
     }
     if (flags & HELM27_STORE_C128) {
-        if (hipMalloc(&op->d_coef_d, 27 * N * sizeof(double2)) != hipSuccess) return fail(HELM27_ENOMEM);
-        g.bytes += 27 * N * sizeof(double2);
+        if (hipMalloc(&op->d_coef_d, coef_elems(N) * sizeof(double2)) != hipSuccess) return fail(HELM27_ENOMEM);
+        g.bytes += coef_elems(N) * sizeof(double2);
         if ((st = launch_fill_stored<double>(g, op->d_coef_d, 1.0, 0.0, stream))) return fail(st);
     }
     if (hipStreamSynchronize(stream) != hipSuccess) return fail(HELM27_EDEVICE);
@@ -479,11 +479,11 @@ extern "C" int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t*
     if (!indptr) return HELM27_OK;
     if (!indices || !vals) return HELM27_EINVAL;
     void* d_coef = nullptr;
-    if (hipMalloc(&d_coef, 27 * g.N * sizeof(double2)) != hipSuccess) return HELM27_ENOMEM;
+    if (hipMalloc(&d_coef, coef_elems(g.N) * sizeof(double2)) != hipSuccess) return HELM27_ENOMEM;
     int st = launch_fill_stored<double>(g, d_coef, 1.0, 0.0, nullptr);
     std::vector<double> hco;
     if (st == HELM27_OK) {
-        hco.resize(static_cast<size_t>(27) * g.N * 2);
+        hco.resize(static_cast<size_t>(coef_elems(g.N)) * 2);
         if (hipMemcpy(hco.data(), d_coef, hco.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
             st = HELM27_EDEVICE;
     }
@@ -500,8 +500,8 @@ extern "C" int helm27_export_csr(const helm27_op* op, int64_t* nnz_out, int64_t*
             if (x + dx < 0 || x + dx >= g.nx || y + dy < 0 || y + dy >= g.ny || z + dz < 0 || z + dz >= g.nz)
                 continue;
             indices[k] = i + dx + static_cast<int64_t>(g.nx) * dy + plane * dz;
-            vals[2 * k] = hco[2 * (static_cast<size_t>(s) * g.N + i)];
-            vals[2 * k + 1] = hco[2 * (static_cast<size_t>(s) * g.N + i) + 1];
+            vals[2 * k] = hco[2 * static_cast<size_t>(coef_at(i, s))];
+            vals[2 * k + 1] = hco[2 * static_cast<size_t>(coef_at(i, s)) + 1];
             ++k;
         }
         indptr[i + 1] = k;

@@ -826,7 +826,7 @@ extern "C" void helm27_solve_opts_default(helm27_solve_opts* o) {
     o->precision = HELM27_C64;
     o->mg_levels = -1;
     o->mg_shift = 1.0;
-    o->mg_shift_re = 0.4;
+    o->mg_shift_re = 0.0;
     o->mg_pre = 2;
     o->mg_post = 1;
     o->mg_omega = 0.6;

@@ -33,6 +33,16 @@ struct GridData {
     int mass_a;                    // 1: first consistent-mass form (bulk modulus of each neighbour)
 };
 
+// Stored coefficients in blocks of 64 rows: entry s of row i sits at
+// coef[(i / 64) * 27 * 64 + s * 64 + i % 64], so a wavefront's 64 rows read
+// each s as one coalesced 512-byte (FP32) segment and the 27 segments of a
+// block are one contiguous stretch of memory; coef_elems(N) entries (N
+// rounded up to whole blocks).
+__host__ __device__ inline int64_t coef_at(int64_t i, int s) {
+    return (i >> 6) * (27 * 64) + static_cast<int64_t>(s) * 64 + (i & 63);
+}
+inline int64_t coef_elems(int64_t N) { return 27 * ((N + 63) / 64 * 64); }
+
 template <typename R>
 struct StencilArgs {
     GridData<R> g;
