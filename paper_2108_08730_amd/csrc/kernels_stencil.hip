@@ -562,6 +562,15 @@ static int build_wave_args(const GridOp& g, const GridData<R>& gd, const void* u
     w.n_items = static_cast<int>(items);
     w.tab_lo = g.idx_lo;
     w.n_tab = n_tab;
+    // launches whose input and output vectors together exceed the 256 MiB
+    // last-level cache store an apply's output non-temporally and read their
+    // per-point data non-temporally when every point is visited by one
+    // right-hand-side group only (several groups re-read them; smaller
+    // launches keep everything cached for the solver's next kernel).  Only
+    // unshifted block-tile applies have the non-temporal instances.
+    const bool big = 2.0 * static_cast<double>(g.N) * nrhs * sizeof(typename V2<R>::T) >= 256.0 * (1 << 20);
+    w.nt_store = big && !batch ? 1 : 0;
+    w.nt_meta = big && w.ngrp == 1 ? 1 : 0;
     w.u = static_cast<const typename V2<R>::T*>(u);
     w.y = static_cast<typename V2<R>::T*>(y);
     w.b = static_cast<const typename V2<R>::T*>(b);

@@ -81,6 +81,8 @@ struct WaveArgs {
     int ngrp;                      // right-hand-side groups per tile in the item order (nrhs / nb rounded up)
     int rhs_outer;                 // 1: items ordered tile, z chunk, then right-hand-side group
     int tab_lo, n_tab;             // table slice [tab_lo, tab_lo + n_tab)
+    int nt_store;                  // 1: apply output stored non-temporally (vectors larger than the last-level cache)
+    int nt_meta;                   // 1: and per-point data (index, velocity) read non-temporally (read once)
     const typename V2<R>::T* u;
     typename V2<R>::T* y;
     const typename V2<R>::T* b;

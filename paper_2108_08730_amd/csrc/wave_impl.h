@@ -148,25 +148,36 @@ __device__ __forceinline__ void bld(double2& v, Rsrc r, unsigned vo, unsigned so
     v.x = __hiloint2double(static_cast<int>(w.y), static_cast<int>(w.x));
     v.y = __hiloint2double(static_cast<int>(w.w), static_cast<int>(w.z));
 }
+// Non-temporal cache policy (bit 1 of the buffer instruction's cache-policy
+// operand) for data touched once, so it does not evict the rows neighbouring
+// tiles still read: the output stores of applies too large for the
+// last-level cache (NT, a kernel instance of its own) and (nt, wave-uniform)
+// the per-point data of launches that read them once.  Outputs of smaller
+// launches stay cached for the kernel that reads them next.
+constexpr int kNt = 2;
+template <bool NT>
 __device__ __forceinline__ void bst(Cx<float> v, Rsrc r, unsigned vo, unsigned so) {
     u32x2 w;
     w.x = __float_as_uint(v.re);
     w.y = __float_as_uint(v.im);
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(vo), static_cast<int>(so), 0);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(vo), static_cast<int>(so), NT ? kNt : 0);
 }
+template <bool NT>
 __device__ __forceinline__ void bst(Cx<double> v, Rsrc r, unsigned vo, unsigned so) {
     u32x4 w;
     w.x = static_cast<unsigned>(__double2loint(v.re));
     w.y = static_cast<unsigned>(__double2hiint(v.re));
     w.z = static_cast<unsigned>(__double2loint(v.im));
     w.w = static_cast<unsigned>(__double2hiint(v.im));
-    __builtin_amdgcn_raw_buffer_store_b128(w, r, static_cast<int>(vo), static_cast<int>(so), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, static_cast<int>(vo), static_cast<int>(so), NT ? kNt : 0);
 }
-__device__ __forceinline__ int bld_u16(Rsrc r, unsigned vo, unsigned so) {
-    return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), 0));
+__device__ __forceinline__ int bld_u16(Rsrc r, unsigned vo, unsigned so, bool nt = false) {
+    return static_cast<int>(nt ? __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), kNt)
+                               : __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), 0));
 }
-__device__ __forceinline__ float bld_f32(Rsrc r, unsigned vo, unsigned so) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo), static_cast<int>(so), 0));
+__device__ __forceinline__ float bld_f32(Rsrc r, unsigned vo, unsigned so, bool nt = false) {
+    return __uint_as_float(nt ? __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo), static_cast<int>(so), kNt)
+                              : __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(vo), static_cast<int>(so), 0));
 }
 
 // table entry reads from LDS as 16-byte loads
@@ -264,14 +275,15 @@ struct ItemBuf {
 #pragma unroll
         for (int k = 0; k < NK; ++k) bld(L[k], r, ofs[k], so);
     }
-    // per-point data of plane q (0 <= q < nz); mo = element offsets of the rows
-    template <int NR, bool ROWC>
+    // per-point data of plane q (0 <= q < nz); mo = element offsets of the
+    // rows; NTM: non-temporal (each point's data read once by the launch)
+    template <int NR, bool ROWC, bool NTM>
     __device__ __forceinline__ void load_meta(int q, const unsigned (&mo)[NR], Meta<R, NR>& M) const {
         const unsigned pe = static_cast<unsigned>(q) * plane;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            if (!ROWC) M.idx[r] = bld_u16(ri, mo[r] * 2u, pe * 2u);
-            M.c[r] = bld_f32(rc, mo[r] * 4u, pe * 4u);
+            if (!ROWC) M.idx[r] = bld_u16(ri, mo[r] * 2u, pe * 2u, NTM);
+            M.c[r] = bld_f32(rc, mo[r] * 4u, pe * 4u, NTM);
             if (MODE != MODE_APPLY)
                 bld(M.b[r], rb, mo[r] * static_cast<unsigned>(sizeof(typename V2<R>::T)), q * plane_b);
         }
@@ -291,7 +303,7 @@ struct ItemBuf {
 // on v = k^2 u with k^2 = omega^2 / c_j^2 taken at each loaded point, while
 // the stiffness acts on u; the rows' velocities are loaded with u (and v
 // shared through the ring beside u).
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, bool MA = false>
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, bool MA = false, int NT = 0>
 __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                          typename V2<R>::T* ring, int tile, int zc, int rhs, int wave, int lane) {
     using V = typename V2<R>::T;
@@ -454,7 +466,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
             }
             V bb{};
             if (MODE != MODE_APPLY) bb = M.b[r];
-            bst(finish<R, MODE>(a.omega_j, acc, diag, B.c[r], bb), B_.ry, so[r], pso);
+            bst<NT != 0>(finish<R, MODE>(a.omega_j, acc, diag, B.c[r], bb), B_.ry, so[r], pso);
         }
     };
     // one z step: plane q enters, output plane q - 1 leaves.  Plane q + 2 and
@@ -488,7 +500,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     auto step = [&](int q, bool out, const Slot& Lc, Slot& Ln, const Plane& A, const Plane& B, Plane& C,
                     const Meta<R, RY>& Mc, Meta<R, RY>& Mn) __attribute__((always_inline)) {
         load(min(q + 2, z1), Ln);
-        B_.template load_meta<RY, ROWC>(min(q + 1, z1 - 1), mo, Mn);
+        B_.template load_meta<RY, ROWC, NT == 2>(min(q + 1, z1 - 1), mo, Mn);
         Cx<R> U[RY + 2];
         Cx<R> Vv[MA ? RY + 2 : 1];
         if constexpr (BLK) {
@@ -626,7 +638,7 @@ __device__ __forceinline__ Cx<R> dot3(const Cx<R> (&k)[3], Cx<R> c, Cx<R> f, Cx<
     return r;
 }
 
-template <typename R, int MODE, bool SHIFTED, bool ROWC, int NB>
+template <typename R, int MODE, bool SHIFTED, bool ROWC, int NB, int NT = 0>
 __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                             typename V2<R>::T* ring, int tile, int zc, int rhs, int wave, int lane) {
     using V = typename V2<R>::T;
@@ -684,8 +696,8 @@ __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry
     };
     auto load_meta = [&](int q, PMeta& M) __attribute__((always_inline)) {
         const unsigned pe = static_cast<unsigned>(q) * plane;
-        if (!ROWC) M.idx = bld_u16(ri, mo * 2u, pe * 2u);
-        M.c = bld_f32(rc, mo * 4u, pe * 4u);
+        if (!ROWC) M.idx = bld_u16(ri, mo * 2u, pe * 2u, NT == 2);
+        M.c = bld_f32(rc, mo * 4u, pe * 4u, NT == 2);
     };
     auto load_b = [&](int q, V (&Bv)[NB]) __attribute__((always_inline)) {
         if (MODE == MODE_APPLY) return;
@@ -760,7 +772,7 @@ __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry
             if (fin) {
                 Cx<R> acc = P[v] + (realp ? dot3<R, true>(KCp, c, f, e) : dot3<R, false>(KCp, c, f, e));
                 if (v < nvec)
-                    bst(finish<R, MODE>(a.omega_j, acc, diag_p, Sc[v], Bp[v]), ry,
+                    bst<NT != 0>(finish<R, MODE>(a.omega_j, acc, diag_p, Sc[v], Bp[v]), ry,
                         so + static_cast<unsigned>(v) * vbytes, pso);
             }
             if (start) {
@@ -824,7 +836,7 @@ struct FramePlane {
     Cx<R> av[MA ? NR : 1];
 };
 
-template <typename R, int MODE, bool SHIFTED, int RQ, int LW, bool ROWC, bool MA = false>
+template <typename R, int MODE, bool SHIFTED, int RQ, int LW, bool ROWC, bool MA = false, int NT = 0>
 __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<R>* tab, const AxisNode<R>* zn,
                                            int fr, int ft, int zc, int rhs, int lane) {
     using Plane = FramePlane<R, RQ, MA>;
@@ -936,7 +948,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
             }
             V bb{};
             if (MODE != MODE_APPLY) bb = M.b[r];
-            bst(finish<R, MODE>(a.omega_j, acc, diag, B.u[r], bb), B_.ry, so[r], pso);
+            bst<NT != 0>(finish<R, MODE>(a.omega_j, acc, diag, B.u[r], bb), B_.ry, so[r], pso);
         }
     };
     using Slot = RowSlot<R, RQ + 2, MA>;
@@ -953,7 +965,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
     auto step = [&](int q, bool out, const Slot& Lc, Slot& Ln, const Plane& A, const Plane& B, Plane& C,
                     const Meta<R, RQ>& Mc, Meta<R, RQ>& Mn) __attribute__((always_inline)) {
         load(min(q + 2, z1), Ln);
-        B_.template load_meta<RQ, ROWC>(min(q + 1, z1 - 1), mo, Mn);
+        B_.template load_meta<RQ, ROWC, NT == 2>(min(q + 1, z1 - 1), mo, Mn);
         Cx<R> U[RQ + 2];
 #pragma unroll
         for (int k = 0; k < RQ + 2; ++k) U[k] = Cx<R>{Lc.u[k].x, Lc.u[k].y};
@@ -1019,7 +1031,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
 // The body of one block: stage the grid's table slice and z nodes, then
 // take work items lb, lb + nb, ... (block granularity; with !BLK each of the
 // block's wavefronts takes its own item of the block's group of four).
-template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA>
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA, int NT>
 __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb, unsigned char* smem_raw) {
     const GridData<R>& g = a.g;
     const int n_tab = ROWC ? 0 : a.n_tab;
@@ -1058,11 +1070,11 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
                 int k = 0;
                 while (k < 3 && tile >= a.fstart[k + 1]) ++k;
                 if (a.flx[k])
-                    frame_item<R, MODE, SHIFTED, RQ, 64, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                    frame_item<R, MODE, SHIFTED, RQ, 64, ROWC, MA, NT>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
                 else
-                    frame_item<R, MODE, SHIFTED, RQ, 16, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
+                    frame_item<R, MODE, SHIFTED, RQ, 16, ROWC, MA, NT>(a, tab, zn, k, tile - a.fstart[k], zc, rhs, lane);
             } else {
-                box_item<R, MODE, SHIFTED, RY, ROWC, false, MA>(a, tab, zn, ring, tile - a.n_frame, zc, rhs, wave,
+                box_item<R, MODE, SHIFTED, RY, ROWC, false, MA, NT>(a, tab, zn, ring, tile - a.n_frame, zc, rhs, wave,
                                                                 lane);
             }
         }
@@ -1087,23 +1099,24 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
                     const int nv = min(NB, a.nrhs - rhs);
                     for (int v = 0; v < nv; ++v) {
                         if (a.flx[k])
-                            frame_item<R, MODE, SHIFTED, RQ, 64, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
+                            frame_item<R, MODE, SHIFTED, RQ, 64, ROWC, MA, NT>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
                                                                        lane);
                         else
-                            frame_item<R, MODE, SHIFTED, RQ, 16, ROWC, MA>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
+                            frame_item<R, MODE, SHIFTED, RQ, 16, ROWC, MA, NT>(a, tab, zn, k, tile - a.fstart[k], zc, rhs + v,
                                                                        lane);
                     }
                 }
             } else if constexpr (NB > 1) {
-                box_item_nb<R, MODE, SHIFTED, ROWC, NB>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
+                box_item_nb<R, MODE, SHIFTED, ROWC, NB, NT>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
             } else {
-                box_item<R, MODE, SHIFTED, RY, ROWC, true, MA>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
+                box_item<R, MODE, SHIFTED, RY, ROWC, true, MA, NT>(a, tab, zn, ring, bt - nfb, zc, rhs, wave, lane);
             }
         }
     }
 }
 
-template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA = false>
+template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA = false,
+          int NT = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 void wave27_kernel(WaveArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1113,7 +1126,7 @@ void wave27_kernel(WaveArgs<R> a) {
     const int bx = static_cast<int>(blockIdx.x);
     const int xcd = bx & 7, q8 = nb >> 3, r8 = nb & 7;
     const int lb = xcd * q8 + min(xcd, r8) + (bx >> 3);
-    wave27_body<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA>(a, nb, lb, smem_raw);
+    wave27_body<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA, NT>(a, nb, lb, smem_raw);
 }
 
 // Several grids in one launch (batches of small grids): grid o owns blocks
@@ -1136,7 +1149,8 @@ void wave27_batch_kernel(WaveBatch<R> B) {
     int o = 0;
     while (o + 1 < B.n && bx >= B.bstart[o + 1]) ++o;
     o = uni(o);
-    wave27_body<R, MODE, SHIFTED, RY, RQ, ROWC, false, 1, MA>(B.a[o], B.bstart[o + 1] - B.bstart[o], bx - B.bstart[o],
+    wave27_body<R, MODE, SHIFTED, RY, RQ, ROWC, false, 1, MA, 0>(B.a[o], B.bstart[o + 1] - B.bstart[o],
+                                                                     bx - B.bstart[o],
                                                               smem_raw);
 }
 
@@ -1164,10 +1178,10 @@ inline int resident_blocks(const void* fn, size_t lds) {
     return blocks;
 }
 
-template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, int NB, bool MA = false>
-inline int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, int NB, bool MA, int NT>
+inline int launch_wave_kn(const WaveArgs<R>& a, hipStream_t s) {
     constexpr int RQ = FrameRows<R>::value;
-    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA>);
+    const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA, NT>);
     const int n_tab = ROWC ? 0 : a.n_tab;
     const size_t lds = wave_ring_offset(n_tab, a.g.nz, sizeof(R) == 8) +
                        (BLK ? wave_ring_bytes(RY, NB, sizeof(R) == 8, MA) : 0);
@@ -1175,9 +1189,23 @@ inline int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
     const int cap = resident_blocks(fn, lds);
     if (cap <= 0) return HELM27_EDEVICE;
     if (blocks > cap) blocks = cap;
-    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA>, dim3(blocks), dim3(kBlock), lds, s,
-                         a));
+    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA, NT>, dim3(blocks), dim3(kBlock), lds,
+                         s, a));
     return HELM27_OK;
+}
+
+// Block-tile applies too large for the last-level cache store their output
+// non-temporally, and read their per-point data non-temporally too when
+// every point is visited once (NT = 1, 2: kernel instances of their own, so
+// the cache policy costs no registers); the other modes' outputs are read
+// again by the solver's next kernel
+template <typename R, int MODE, bool SHIFTED, int RY, bool ROWC, bool BLK, int NB, bool MA = false>
+inline int launch_wave_k(const WaveArgs<R>& a, hipStream_t s) {
+    if constexpr (MODE == MODE_APPLY && BLK && !SHIFTED) {
+        if (a.nt_store && a.nt_meta) return launch_wave_kn<R, MODE, SHIFTED, RY, ROWC, BLK, NB, MA, 2>(a, s);
+        if (a.nt_store) return launch_wave_kn<R, MODE, SHIFTED, RY, ROWC, BLK, NB, MA, 1>(a, s);
+    }
+    return launch_wave_kn<R, MODE, SHIFTED, RY, ROWC, BLK, NB, MA, 0>(a, s);
 }
 
 template <typename R, int MODE, bool SHIFTED, int RY>
