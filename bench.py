@@ -53,7 +53,8 @@ def measured_traffic(key, shape=None):
     """HBM bytes per launch of the apply kernel from the committed
     hardware-counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy
     of known size), or None when the kernel sources changed since the
-    counters were taken or the launch runs another tile shape."""
+    counters were taken or the launch runs a tile shape that was not
+    profiled (an entry holds one shape, or several under "by_shape")."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "wave27_apply_traffic.json")
     try:
@@ -64,9 +65,10 @@ def measured_traffic(key, shape=None):
                 if hashlib.sha256(fh.read()).hexdigest() != digest:
                     return None
         entry = rec[key]
-        if shape is not None and entry.get("shape") not in (None, shape):
-            return None
-        return float(entry["traffic_bytes"])
+        for e in entry.get("by_shape", [entry]):
+            if shape is None or e.get("shape") in (None, shape):
+                return float(e["traffic_bytes"])
+        return None
     except (OSError, KeyError, ValueError):
         return None
 
