@@ -152,6 +152,7 @@ struct GridOp {
     EntryCoef<double>* d_row_d = nullptr;
     AxisNode<float>* d_ax_f[3] = {nullptr, nullptr, nullptr};
     AxisNode<double>* d_ax_d[3] = {nullptr, nullptr, nullptr};
+    int zp_lo = 0, zp_hi = 0;                  // unstretched z planes [zp_lo, zp_hi) (identical nodes)
     Tiling tiling;
     int plain_ry[2] = {2, 1};                  // box rows per wavefront: [fp32, fp64] (1..4)
     int kernel_variant = 0;                    // 0: wavefront-per-tile kernel, 1: LDS-tiled kernel

@@ -294,6 +294,8 @@ GridData<float> make_grid_data<float>(const GridOp& g, double shift_re, double s
     d.shift_re = static_cast<float>(shift_re * g.att_re - shift_im * g.att_im);
     d.shift_im = static_cast<float>(shift_re * g.att_im + shift_im * g.att_re);
     d.mass_a = g.mass_a;
+    d.zlo = g.zp_lo;
+    d.zhi = g.zp_hi;
     return d;
 }
 
@@ -310,6 +312,8 @@ GridData<double> make_grid_data<double>(const GridOp& g, double shift_re, double
     d.shift_re = shift_re * g.att_re - shift_im * g.att_im;
     d.shift_im = shift_re * g.att_im + shift_im * g.att_re;
     d.mass_a = g.mass_a;
+    d.zlo = g.zp_lo;
+    d.zhi = g.zp_hi;
     return d;
 }
 

@@ -378,6 +378,8 @@ GridData<float> grid_data<float>(const GridOp& g, double shift_re, double shift_
     d.shift_re = static_cast<float>(shift_re * g.att_re - shift_im * g.att_im);
     d.shift_im = static_cast<float>(shift_re * g.att_im + shift_im * g.att_re);
     d.mass_a = g.mass_a;
+    d.zlo = g.zp_lo;
+    d.zhi = g.zp_hi;
     return d;
 }
 
@@ -394,6 +396,8 @@ GridData<double> grid_data<double>(const GridOp& g, double shift_re, double shif
     d.shift_re = shift_re * g.att_re - shift_im * g.att_im;
     d.shift_im = shift_re * g.att_im + shift_im * g.att_re;
     d.mass_a = g.mass_a;
+    d.zlo = g.zp_lo;
+    d.zhi = g.zp_hi;
     return d;
 }
 
@@ -430,7 +434,7 @@ bool stencil_wave_path(const GridOp& g, bool fp64) {
     // the first mass form runs on the wavefront kernels only
     return (g.kernel_variant == 0 || g.kernel_variant == 2 || g.mass_a) && n_tab > 0 &&
            static_cast<int64_t>(g.N) * (fp64 ? 16 : 8) < (int64_t(1) << 31) &&
-           wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit();
+           wave_ring_offset(g.d_row_f ? 0 : n_tab, z_lds_nodes(g.nz, g.zp_lo, g.zp_hi), fp64) + ring <= lds_limit();
 }
 
 template <typename R>
@@ -461,7 +465,7 @@ static int build_wave_args(const GridOp& g, const GridData<R>& gd, const void* u
         variant = 0;
         zc_set = 0;
         const size_t ring = wave_ring_bytes(g.mass_a ? 1 : RY, 1, fp64, g.mass_a != 0);
-        if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + ring <= lds_limit()) {
+        if (big && wave_ring_offset(g.d_row_f ? 0 : n_tab, z_lds_nodes(g.nz, g.zp_lo, g.zp_hi), fp64) + ring <= lds_limit()) {
             variant = 2;
             zc_set = nrhs == 1 ? 32 : 16;
         }
@@ -483,7 +487,7 @@ static int build_wave_args(const GridOp& g, const GridData<R>& gd, const void* u
     if (!fp64 && nrhs >= 2 && g.rhs_block > 1 && !g.mass_a && !batch) {
         NB = g.rhs_block;
         const bool fits = static_cast<int64_t>(g.N) * 8 * NB < (int64_t(1) << 31) &&
-                          wave_ring_offset(g.d_row_f ? 0 : n_tab, g.nz, fp64) + wave_ring_bytes(1, NB, fp64) <=
+                          wave_ring_offset(g.d_row_f ? 0 : n_tab, z_lds_nodes(g.nz, g.zp_lo, g.zp_hi), fp64) + wave_ring_bytes(1, NB, fp64) <=
                               lds_limit();
         if (!fits) NB = 1;
     }
@@ -652,7 +656,7 @@ int launch_stencil_batch(const GridOp* const* g, int n, const void* const* u, vo
         if (nrhs[i] == 0) continue;
         const int n_tab = G.idx_hi - G.idx_lo + 1;
         if (n_tab <= 0 || static_cast<int64_t>(G.N) * (fp64 ? 16 : 8) >= (int64_t(1) << 31) ||
-            wave_ring_offset(G.d_row_f ? 0 : n_tab, G.nz, fp64) > lds_limit())
+            wave_ring_offset(G.d_row_f ? 0 : n_tab, z_lds_nodes(G.nz, G.zp_lo, G.zp_hi), fp64) > lds_limit())
             return HELM27_EINVAL;
         const GridData<R> gd = grid_data<R>(G, 1.0, 0.0);
         if (!gd.entry || !gd.ax || !gd.ay || !gd.az) return HELM27_EINVAL;

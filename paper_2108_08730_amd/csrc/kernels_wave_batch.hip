@@ -27,7 +27,8 @@ static int batch_launch(const WaveArgs<R>* const* w, int n, hipStream_t s) {
             B.bstart[j] = static_cast<int>(blocks);
             blocks += (a.n_items + waves - 1) / waves;   // one work item per wavefront
             if (blocks > INT_MAX) return HELM27_EINVAL;
-            lds = std::max(lds, wave_ring_offset(ROWC ? 0 : a.n_tab, a.g.nz, sizeof(R) == 8));
+            lds = std::max(lds, wave_ring_offset(ROWC ? 0 : a.n_tab, z_lds_nodes(a.g.nz, a.g.zlo, a.g.zhi),
+                                                 sizeof(R) == 8));
         }
         for (int j = m; j <= kWaveBatch; ++j) B.bstart[j] = static_cast<int>(blocks);
         if (blocks == 0) continue;

@@ -219,6 +219,8 @@ int grid_setup(GridOp* g, const double* w7, int n_g, int fixed) {
         g->d_ax_d[a] = reinterpret_cast<AxisNode<double>*>(base + o_axd[a]);
         g->d_ax_f[a] = reinterpret_cast<AxisNode<float>*>(base + o_axf[a]);
     }
+    g->zp_lo = lo[2];
+    g->zp_hi = hi[2];
     make_tiling(g->nx, g->ny, lo, hi, &g->tiling, 0, g->nz);
     return HELM27_OK;
 }

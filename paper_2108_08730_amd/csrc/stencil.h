@@ -31,7 +31,22 @@ struct GridData {
     R inv_h2;                      // 1 / h^2
     R shift_re, shift_im;          // mass scaled by (shift_re + i shift_im); (1, 0) = physical
     int mass_a;                    // 1: first consistent-mass form (bulk modulus of each neighbour)
+    int zlo, zhi;                  // unstretched z planes [zlo, zhi): their nodes are identical
 };
+
+// The wavefront kernels stage the z-axis nodes in LDS with the unstretched
+// planes' (identical) nodes stored once: nodes 0 .. zlo - 1, one plain node,
+// then the planes zhi .. nz - 1.  z_lds_nodes: how many; z_slot: the LDS
+// slot of plane q; z_plane: the plane whose node slot t holds.
+__host__ __device__ inline int z_lds_nodes(int nz, int zlo, int zhi) {
+    return zhi > zlo ? nz - (zhi - zlo - 1) : nz;
+}
+__host__ __device__ inline int z_slot(int q, int zlo, int zhi) {
+    return q < zlo ? q : (q < zhi ? zlo : q - zhi + zlo + (zhi > zlo ? 1 : 0));
+}
+__host__ __device__ inline int z_plane(int t, int zlo, int zhi) {
+    return t < zlo ? t : (zhi > zlo && t == zlo ? zlo : t - zlo - (zhi > zlo ? 1 : 0) + zhi);
+}
 
 // Stored coefficients in blocks of 64 rows: entry s of row i sits at
 // coef[(i / 64) * 27 * 64 + s * 64 + i % 64], so a wavefront's 64 rows read

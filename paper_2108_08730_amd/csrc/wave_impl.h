@@ -351,7 +351,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
 
     auto output = [&](int zo, const Meta<R, RY>& M, const Plane& A, const Plane& B, const Plane& C)
                       __attribute__((always_inline)) {
-        const AxisNode<R> Z = zn[zo];
+        const AxisNode<R> Z = zn[z_slot(zo, g.zlo, g.zhi)];
         const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -720,7 +720,7 @@ __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry
         const R cvr = static_cast<R>(M.c);
         const R kap = g.omega2 * rcp_of(cvr * cvr);
         const Cx<R> kc = SHIFTED ? Cx<R>{kap * g.shift_re, kap * g.shift_im} : Cx<R>{kap, R(0)};
-        const AxisNode<R>& Z = zn[q];
+        const AxisNode<R>& Z = zn[z_slot(q, g.zlo, g.zhi)];
         real = real_ok && Z.plain;
         if (real) zcoef<R, true>(s, m, sig, kc, Z, K);
         else zcoef<R, false>(s, m, sig, kc, Z, K);
@@ -881,7 +881,7 @@ __device__ __forceinline__ void frame_item(const WaveArgs<R>& a, const TabEntry<
 
     auto output = [&](int zo, const Meta<R, RQ>& M, const Plane& A, const Plane& B, const Plane& C)
                       __attribute__((always_inline)) {
-        const AxisNode<R> Z = zn[zo];
+        const AxisNode<R> Z = zn[z_slot(zo, g.zlo, g.zhi)];
         const bool plainz = Z.plain != 0;
         const Factors<R> FZ = factors<R>(Z);
         const unsigned pso = static_cast<unsigned>(zo) * B_.plane_b;
@@ -1048,10 +1048,11 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
         e.pad0 = e.pad1 = R(0);
         tab[t] = e;
     }
-    for (int t = threadIdx.x; t < g.nz; t += kBlock) zn[t] = g.az[t];
+    const int nzl = z_lds_nodes(g.nz, g.zlo, g.zhi);
+    for (int t = threadIdx.x; t < nzl; t += kBlock) zn[t] = g.az[z_plane(t, g.zlo, g.zhi)];
     // row ring after the table slice and the z nodes, 16-byte aligned (as wave_ring_offset)
     const size_t ring_off = (static_cast<size_t>(n_tab) * sizeof(TabEntry<R>) +
-                             static_cast<size_t>(g.nz) * sizeof(AxisNode<R>) + 15) & ~static_cast<size_t>(15);
+                             static_cast<size_t>(nzl) * sizeof(AxisNode<R>) + 15) & ~static_cast<size_t>(15);
     typename V2<R>::T* ring = reinterpret_cast<typename V2<R>::T*>(smem_raw + ring_off);
     __syncthreads();
     const int wave = uni(static_cast<int>(threadIdx.x) >> 6);
@@ -1183,7 +1184,7 @@ inline int launch_wave_kn(const WaveArgs<R>& a, hipStream_t s) {
     constexpr int RQ = FrameRows<R>::value;
     const void* fn = reinterpret_cast<const void*>(&wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA, NT>);
     const int n_tab = ROWC ? 0 : a.n_tab;
-    const size_t lds = wave_ring_offset(n_tab, a.g.nz, sizeof(R) == 8) +
+    const size_t lds = wave_ring_offset(n_tab, z_lds_nodes(a.g.nz, a.g.zlo, a.g.zhi), sizeof(R) == 8) +
                        (BLK ? wave_ring_bytes(RY, NB, sizeof(R) == 8, MA) : 0);
     int blocks = BLK ? a.n_items : (a.n_items + (kBlock / 64) - 1) / (kBlock / 64);
     const int cap = resident_blocks(fn, lds);

@@ -229,6 +229,38 @@ def test_apply_large_single_rhs_sampled(ctx, table, oracle_table):
     assert _relerr(y32[0], y_ref[0]) <= 1e-5
 
 
+def test_apply_non_temporal_instances_sampled(ctx, table, oracle_table):
+    """Launches whose vectors exceed the last-level cache run the kernel
+    instances with non-temporal stores (several RHS groups) or non-temporal
+    stores and per-point data (one group): 320 x 320 x 170 random field
+    (17.4 M points), one RHS in FP32 and FP64, four RHS one per wavefront and
+    four per wavefront; sampled rows against the oracle, and every RHS equal
+    to its single-RHS launch to rounding."""
+    dims, npml, f, h = (320, 320, 170), 8, 8.0, 25.0
+    c = synth.random_field_model(dims, h, seed=43)
+    op = ctx.assemble(table, c, h, f, npml=npml)
+    N = int(np.prod(dims))
+    assert 2 * N * 8 >= 256 << 20
+    idx_o, _ = O.select_index(c, f, h, 3.0, 0.05, 341)
+    rows = np.unique(np.random.default_rng(8).integers(0, N, 1500))
+    w = O.row_weights("GA", idx_o, oracle_table[2])
+    A = O.assemble_rows(c, f, h, npml, w[rows], rows)
+    u = synth.random_vectors(N, 4, seed=15)
+    y_ref = (A @ u.T).T
+    ud = torch.from_numpy(u).cuda()
+    u32 = ud.to(torch.complex64)
+    y64 = op.apply(ud[:1].contiguous()).cpu().numpy()[0, rows]
+    assert _relerr(y64, y_ref[0]) <= 1e-12
+    y1 = op.apply(u32[:1].contiguous()).cpu().numpy()[0]
+    assert _relerr(y1[rows], y_ref[0]) <= 1e-5
+    for nb in (1, 4):
+        op.set_rhs_block(nb)
+        y4 = op.apply(u32).cpu().numpy()
+        for r in range(4):
+            assert _relerr(y4[r, rows], y_ref[r]) <= 1e-5
+        assert _relerr(y4[0], y1) <= 1e-6
+
+
 def test_apply_large_random_field_sampled(ctx, table, oracle_table):
     """201 x 201 x 101 heterogeneous model, 8-node PML, f = 8 Hz, 4 right-hand
     sides: sampled rows against the oracle."""
