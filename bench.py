@@ -175,7 +175,7 @@ def solve_only(args, torch, api, synth):
     ctx = api.Context(0)
     tv = tuple(float(v) for v in args.table.split(","))
     tab = ctx.build_table(tv[0], tv[1], tv[2], tv[3], spacing=args.table_spacing)
-    c = synth.random_field_model(dims, h, seed=1)
+    c = synth.random_field_model(dims, h, seed=args.model_seed)
     op = ctx.assemble(tab, torch.from_numpy(c).cuda(), h, args.freq, npml=npml, extend_table=args.extend_table)
     info = op.info()
     xs = np.linspace(npml + 2, dims[0] - npml - 3, args.nrhs).astype(int)
@@ -184,6 +184,10 @@ def solve_only(args, torch, api, synth):
     t0 = time.perf_counter()
     extra = {} if args.mg_levels is None else {"mg_levels": args.mg_levels}
     extra["mg_coarse_table"] = args.mg_coarse_table
+    if args.max_outer is not None:
+        extra["max_outer"] = args.max_outer
+    if args.restart is not None:
+        extra["restart"] = args.restart
     u, st = op.solve(src, tol=1e-6, max_inner=args.max_inner, verbose=1, **extra)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
@@ -514,9 +518,13 @@ def main():
                     help="one multi-RHS solve on --grid with --nrhs surface sources at --freq")
     ap.add_argument("--freq", type=float, default=10.0)
     ap.add_argument("--max-inner", type=int, default=3000)
+    ap.add_argument("--max-outer", type=int, default=None,
+                    help="--solve-only: refinement steps (with a small --max-inner: a truncated solve to profile)")
+    ap.add_argument("--restart", type=int, default=None, help="--solve-only: GMRES restart length")
     ap.add_argument("--table", type=str, default="2.5,60,0.05,1e-3",
                     help="--solve-only: table v_min,v_max,dv,lambda (G, or s = 1/G with --table-spacing invG)")
     ap.add_argument("--table-spacing", choices=("G", "invG"), default="G")
+    ap.add_argument("--model-seed", type=int, default=1, help="--solve-only: random-field model seed")
     ap.add_argument("--extend-table", action="store_true",
                     help="--solve-only: widen the table (and the coarse levels' tables) to the model's G range")
     ap.add_argument("--mg-levels", type=int, default=None)
