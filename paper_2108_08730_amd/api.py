@@ -299,6 +299,22 @@ class Context:
         L.check(L.lib.helm27_build_table(self._h, g_min, g_max, dg, lam, C.byref(opts), C.byref(h)), "build_table")
         return Table(h)
 
+    def fit_fixed(self, g_list, near=None, n_angles=5, angle_step_deg=10.0) -> Table:
+        """Non-adaptive weights fitted jointly over g_list (helm27_fit_fixed):
+        a one-entry table for assemble(weights="fixed").  near (five free
+        weights) picks the least-squares solution closest to it when the fit
+        is rank deficient (a single G), else the minimum-norm one."""
+        g = np.ascontiguousarray(np.asarray(g_list, np.float64).ravel())
+        opts = L.TableOpts(n_angles, angle_step_deg, 1, 0)
+        nr = None
+        if near is not None:
+            nr = np.ascontiguousarray(np.asarray(near, np.float64).ravel()[:5])
+        h = C.c_void_p()
+        L.check(L.lib.helm27_fit_fixed(self._h, g.ctypes.data_as(C.POINTER(C.c_double)), g.size, C.byref(opts),
+                                       nr.ctypes.data_as(C.POINTER(C.c_double)) if nr is not None else None,
+                                       C.byref(h)), "fit_fixed")
+        return Table(h)
+
     def table_from_weights(self, g_min, dg, w5, spacing="G") -> Table:
         w5 = np.ascontiguousarray(np.asarray(w5, np.float64).reshape(-1, 5))
         h = C.c_void_p()

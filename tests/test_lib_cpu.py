@@ -155,3 +155,16 @@ def test_inverse_axis_table_matches_oracle():
     L.lib.helm27_table_destroy(h)
     ref = T.complete_weights(W)
     assert np.max(np.abs(w - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_fit_fixed_binding():
+    """The binding's fit_fixed passes the anchor through: the one-entry table
+    equals the oracle's anchored fit."""
+    from paper_2108_08730_amd import api
+    Gs, W = T.build_table(3.0, 6.0, 0.05, 1e-3)
+    ctx = api.Context.__new__(api.Context)
+    ctx._h = None
+    t = api.Context.fit_fixed(ctx, [4.0], near=W[20])
+    w7, g0, dg = t.weights()
+    assert w7.shape == (1, 7) and g0 == 4.0
+    assert np.max(np.abs(w7[0] - T.complete_weights(T.fit_fixed([4.0], near=W[20])))) < 1e-10
