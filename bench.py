@@ -306,28 +306,37 @@ def serving(args, torch, api, synth):
     4, grids 64^3 / 96^3 / 128^2 x 64, 1-16 surface sources each), served by
     the request loop (mixed precision, all of a request's sources as one
     multi-RHS solve, up to 4 requests on the device at once, admission by
-    HBM footprint); then the same requests as plain FP64 single-RHS solves
-    one after another.  Both reach relative residual 1e-6."""
+    HBM footprint); first all submitted at once (the loop's capacity, the
+    like-for-like throughput), then with the Poisson arrivals (latency under
+    load); then the same requests as plain FP64 single-RHS solves one after
+    another.  All reach relative residual 1e-6."""
     reqs = synth.serving_requests(args.serve_requests, seed=11, rate_hz=args.serve_rate,
                                   dims_choices=((64, 64, 64), (96, 96, 96), (128, 128, 64)), nrhs_max=16)
     models = [synth.random_field_model(r["dims"], r["h"], seed=r["model_seed"] % 1000003) for r in reqs]
     srcs = [synth.surface_sources(r["dims"], r["nrhs"], 9, 10) for r in reqs]
     table = (2.5, 60.0, 0.05, 1e-3)
     ctx = api.Context(0)
-    srv = api.Server(ctx, max_slots=4, table=table, tol=1e-6)
-    t0 = time.perf_counter()
-    tickets = []
-    for r, v, sr in zip(reqs, models, srcs):
-        wait = t0 + r["t_arrival"] - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
-        tickets.append(srv.submit(v, r["h"], r["freq"], sr, npml=8, model_key=r["id"] + 1)[0])
-    res = [srv.wait(t) for t in tickets]
-    wall = time.perf_counter() - t0
-    srv.stop()
+
+    def run(arrivals):
+        srv = api.Server(ctx, max_slots=4, table=table, tol=1e-6)
+        t0 = time.perf_counter()
+        tickets = []
+        for r, v, sr, ta in zip(reqs, models, srcs, arrivals):
+            wait = t0 + ta - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(v, r["h"], r["freq"], sr, npml=8, model_key=r["id"] + 1)[0])
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        srv.stop()
+        return wall, res
+
+    wall_cap, res_cap = run([0.0] * len(reqs))
+    wall, res = run([r["t_arrival"] for r in reqs])
     lat = np.array([(x["t_done"] - x["t_submit"]) * 1e3 for x in res])
+    lat_cap = np.array([(x["t_done"] - x["t_submit"]) * 1e3 for x in res_cap])
     nrhs_tot = int(sum(r["nrhs"] for r in reqs))
-    ok = all(x["status"] == 0 and x["converged"] == 1 for x in res)
+    ok = all(x["status"] == 0 and x["converged"] == 1 for x in res + res_cap)
     tab = ctx.build_table(*table)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -344,14 +353,18 @@ def serving(args, torch, api, synth):
     wall64 = time.perf_counter() - t1
     return {
         "requests": len(reqs), "rhs": nrhs_tot, "arrival_rate_hz": args.serve_rate,
+        "mixed_multi_rhs_capacity": {"rhs_per_s": nrhs_tot / wall_cap, "requests_per_s": len(reqs) / wall_cap,
+                                     "wall_s": wall_cap, "p50_ms": float(np.percentile(lat_cap, 50)),
+                                     "p99_ms": float(np.percentile(lat_cap, 99))},
         "mixed_multi_rhs_serving": {"rhs_per_s": nrhs_tot / wall, "requests_per_s": len(reqs) / wall,
                                     "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
                                     "p99_ms": float(np.percentile(lat, 99)), "all_converged": ok,
-                                    "max_relres": max(x["max_relres"] for x in res)},
+                                    "max_relres": max(x["max_relres"] for x in res + res_cap)},
         "fp64_single_rhs": {"rhs_per_s": nrhs_tot / wall64, "wall_s": wall64, "all_converged": ok64,
                             "max_relres": worst},
-        "speedup_rhs_per_s": (nrhs_tot / wall) / (nrhs_tot / wall64),
-        "note": "serving wall time includes waiting for Poisson arrivals; FP64 baseline runs back to back",
+        "speedup_rhs_per_s": (nrhs_tot / wall_cap) / (nrhs_tot / wall64),
+        "note": "speedup: the loop's capacity pass (all requests submitted at once) against the FP64 "
+                "single-RHS solves back to back; the Poisson pass's wall time includes waiting for arrivals",
     }
 
 
