@@ -201,6 +201,29 @@ def solve_only(args, torch, api, synth):
                       "mg_coarse_table": args.mg_coarse_table}), flush=True)
 
 
+def solve_large(torch, api, synth, ctx, c_dev):
+    """The large single-frequency configuration solved once: the 400x400x200
+    random-field model at 10 Hz with 16 surface sources as one multi-RHS
+    batch, mixed precision to relative residual 1e-6 (FP64 residual on the
+    device), table G in [2.5, 60]."""
+    wl = LARGE
+    tab = ctx.build_table(2.5, 60.0, 0.05, 1e-3)
+    op = ctx.assemble(tab, c_dev, wl["h"], wl["freq"], npml=wl["npml"])
+    src = synth.surface_sources(wl["dims"], wl["nrhs"], 9, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, st = op.solve(src, tol=1e-6, max_inner=6000)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    del u, op
+    torch.cuda.empty_cache()
+    return {"workload": "rf400x16 solve: 400x400x200 random field, f=10 Hz, 16 surface sources in one batch, "
+                        "GMRES(28) + shifted-Laplacian multigrid, FP64 refinement, rel. residual 1e-6",
+            "seconds": sec, "rhs_per_s": wl["nrhs"] / sec, "inner_iters": st["inner_iters"],
+            "outer_iters": st["outer_iters"], "max_relres": st["max_relres"], "converged": bool(st["converged"]),
+            "mg_levels": st["mg_levels"]}
+
+
 def solve_steps(args, torch, api, synth, ctx):
     """The whole path on the 101^3 vertical gradient: table build (host FP64),
     assembly from the device-resident velocity, solve for one source to
@@ -461,6 +484,41 @@ def serving_config4(args, torch, api, synth):
     }
 
 
+HOMOG_SMALL = dict(n=25, c=2000.0, h=20.0, freq=10.0, npml=6, table=(3.0, 20.0, 0.05, 1e-3))
+
+
+def synth_homogeneous(n, c):
+    import synth
+    return synth.homogeneous((n, n, n), c)
+
+
+def solve_homog_small(torch, api, ctx, reps=20):
+    """The small homogeneous point-source problem of the oracle's direct-solve
+    baseline, solved on the GPU (mixed precision to relative residual 1e-8,
+    table build and assembly included in each step)."""
+    w = HOMOG_SMALL
+    n = w["n"]
+    c = synth_homogeneous(n, w["c"])
+    src = [(n // 2,) * 3]
+
+    def step():
+        tab = ctx.build_table(*w["table"])
+        op = ctx.assemble(tab, c, w["h"], w["freq"], npml=w["npml"])
+        _, st = op.solve(src, tol=1e-8)
+        return st
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    return {"workload": f"{n}^3 homogeneous, f={w['freq']:.0f} Hz, centre source, rel. residual 1e-8",
+            "seconds": sec, "solves_per_s": 1.0 / sec, "inner_iters": st["inner_iters"],
+            "max_relres": st["max_relres"]}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -499,7 +557,24 @@ def cpu_baseline(c_large, seconds=10.0, planes=6):
         A @ U
         n += 1
     dt = (time.perf_counter() - t0) / n
+    # the oracle's direct solve (SuperLU, single-threaded) of a small
+    # homogeneous point-source problem, the GPU leg "solve_homog25" solves
+    # the same system
+    from oracle import solve as S
+    n3, hs, fs = HOMOG_SMALL["n"], HOMOG_SMALL["h"], HOMOG_SMALL["freq"]
+    cs3 = synth_homogeneous(n3, HOMOG_SMALL["c"])
+    Gs3, Wt3 = T.build_table(*HOMOG_SMALL["table"])
+    idx3, _ = O.select_index(cs3, fs, hs, HOMOG_SMALL["table"][0], HOMOG_SMALL["table"][2], len(Gs3))
+    A3 = O.assemble(cs3, fs, hs, HOMOG_SMALL["npml"], O.row_weights("GA", idx3, T.complete_weights(Wt3)))
+    b3 = S.point_source_rhs((n3, n3, n3), hs, [(n3 // 2,) * 3])
+    t1 = time.perf_counter()
+    S.solve(A3, b3)
+    t_solve = time.perf_counter() - t1
     return dict(value=A.shape[0] * wl["nrhs"] / dt / 1e9, unit="Gpts/s", cores=1, kind="oracle",
+                solve={"workload": f"{n3}^3 homogeneous c={HOMOG_SMALL['c']:.0f} m/s, h={hs:.0f} m, f={fs:.0f} Hz, "
+                                   f"{HOMOG_SMALL['npml']}-node PML, centre source (N = {len(Gs3)}-entry table)",
+                       "method": "oracle sparse direct solve (scipy SuperLU, single-threaded)",
+                       "seconds": t_solve, "solves_per_s": 1.0 / t_solve, "cores": 1},
                 sample=f"oracle CSR SpMV (scipy, complex128, single-threaded) of its own assembly of a "
                        f"{cs.shape[2]}x{cs.shape[1]}x{planes} slab (z-planes {z0}..{z0 + planes - 1}) of the "
                        f"400x400x200 model with its own table, 16 right-hand sides, {n} repeats in "
@@ -513,6 +588,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50, help="timed 16-RHS applies")
     ap.add_argument("--warmup", type=int, default=5, help="untimed applies before the timed ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large-solve", action="store_true",
+                    help="skip the 400x400x200 x 16 solve (about a minute)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--solve-steps", type=int, default=10, help="timed 101^3 solve steps (0: skip)")
     ap.add_argument("--no-extras", action="store_true",
@@ -571,6 +648,7 @@ def main():
         print(json.dumps({"serving_config4": serving_config4(args, torch, api, synth)}), flush=True)
         return
 
+    t_bench = time.perf_counter()
     wl = LARGE
     nrhs = wl["nrhs"]
     c_host = large_model(synth)
@@ -667,11 +745,23 @@ def main():
         out["apply_variants"] = ext
     del op, u, y
     torch.cuda.empty_cache()
+
+    def leg(name):
+        print(f"bench: {name} ({time.perf_counter() - t_bench:.0f} s)", file=sys.stderr, flush=True)
+
     if args.solve_steps > 0:
+        leg("101^3 solve steps")
         out["solve_gradz101"] = solve_steps(args, torch, api, synth, ctx)
+    leg("25^3 solve")
+    out["solve_homog25"] = solve_homog_small(torch, api, ctx)
+    if not args.no_large_solve:
+        leg("400x400x200 x 16 solve")
+        out["solve_rf400x16"] = solve_large(torch, api, synth, ctx, c_dev)
     if args.serve_requests > 0:
+        leg("serving mix")
         out["serving"] = serving(args, torch, api, synth)
     if not args.no_cpu_baseline:
+        leg("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(c_host, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
