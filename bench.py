@@ -741,6 +741,15 @@ def main():
         ext["stored_single_rhs"] = {"us": ss * 1e6, "gpts": N / ss / 1e9, "GBs": a_s / ss / 1e9,
                                     "frac": a_s / ss / 1e9 / HBM_PEAK_GBS, "alg_bytes": a_s}
         del op_s, u1, y1
+        # complex-FP64 recompute apply, one right-hand side (6 + 32 B per point)
+        op_d = ctx.assemble(tab, c_dev, wl["h"], wl["freq"], npml=wl["npml"])
+        ud = u[:1].to(torch.complex128).contiguous()
+        yd = torch.empty_like(ud)
+        sd = timed_applies(op_d, torch, ud, yd, 4 * args.steps)
+        a_d = alg_bytes(N, 1, vb=16)
+        ext["fp64_single_rhs"] = {"us": sd * 1e6, "gpts": N / sd / 1e9, "GBs": a_d / sd / 1e9,
+                                  "frac": a_d / sd / 1e9 / HBM_PEAK_GBS, "alg_bytes": a_d}
+        del op_d, ud, yd
         ext["batched_small_grids"] = batched_small_grids(torch, api, synth, ctx)
         out["apply_variants"] = ext
     del op, u, y
