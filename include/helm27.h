@@ -310,7 +310,7 @@ int helm27_set_kernel_variant(helm27_op* op, int variant);
 int helm27_set_attenuation(helm27_op* op, double Q);
 /* Right-hand sides per box wavefront of the FP32 recompute kernels: with
  * nb = 2 or 4 a wavefront computes one output row (62 columns) of nb
- * consecutive right-hand sides at once (block tiles of four wavefronts that
+ * consecutive right-hand sides at once (block tiles of 16 wavefronts that
  * share plane rows through LDS), so a point's table index, velocity and
  * coefficients are read and formed once per nb right-hand sides; nb = 1 or
  * 0 (default) keep one right-hand side per wavefront.  Used by every mode

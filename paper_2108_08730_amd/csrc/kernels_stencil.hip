@@ -525,9 +525,10 @@ static int build_wave_args(const GridOp& g, const GridData<R>& gd, const void* u
             fr[3].w = g.nx - fr[3].x0;
         }
     }
-    // variant 2: box tiles grouped 4 along y per block item (rows shared in LDS)
+    // variant 2: box tiles grouped blk_waves along y per block item (rows shared in LDS)
     w.blk = variant == 2 ? 1 : 0;
-    const int rows_per_tile = w.blk ? 4 * RY : RY;
+    const int BW = blk_waves(fp64);
+    const int rows_per_tile = w.blk ? BW * RY : RY;
     w.ntx = w.pw > 0 ? (w.pw + TC - 1) / TC : 0;
     w.nty = w.ph > 0 ? (w.ph + rows_per_tile - 1) / rows_per_tile : 0;
     w.n_plain = w.ntx * w.nty;
@@ -549,8 +550,8 @@ static int build_wave_args(const GridOp& g, const GridData<R>& gd, const void* u
     }
     w.fstart[4] = accf;
     w.n_frame = accf;
-    // work items: wavefront items (variant 0) or block items of 4 wavefronts (variant 2)
-    const int64_t tiles = static_cast<int64_t>(w.blk ? (w.n_frame + 3) / 4 + w.n_plain : w.n_plain + w.n_frame) *
+    // work items: wavefront items (variant 0) or block items of BW wavefronts (variant 2)
+    const int64_t tiles = static_cast<int64_t>(w.blk ? (w.n_frame + BW - 1) / BW + w.n_plain : w.n_plain + w.n_frame) *
                           w.ngrp;
     if (tiles <= 0) return HELM27_OK;   // nothing to do (n_items stays 0)
     const int64_t target = w.blk ? 1024 : 4096;

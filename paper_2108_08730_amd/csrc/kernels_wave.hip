@@ -31,7 +31,8 @@ size_t wave_ring_offset(int n_tab, int nz, bool fp64) {
 }
 
 size_t wave_ring_bytes(int ry, int nb, bool fp64, bool mass_a) {
-    const size_t rows = nb > 1 ? static_cast<size_t>(nb) * 6 : static_cast<size_t>(4 * ry + 2);
+    const size_t bw = static_cast<size_t>(blk_waves(fp64));
+    const size_t rows = nb > 1 ? static_cast<size_t>(nb) * (bw + 2) : bw * static_cast<size_t>(ry) + 2;
     return 2 * rows * 64 * (fp64 ? 16 : 8) * (mass_a ? 2 : 1);
 }
 

@@ -13,6 +13,11 @@ constexpr int kPlainTX = 64;   // plain tile width (one wavefront row along x)
 constexpr int kPlainTY = 4;    // thread rows per block
 constexpr int kFrameT = 16;    // frame tile edge
 constexpr int kBlock = 256;
+// wavefronts per block of the block-tile kernels (variant 2): 16 in FP32
+// (the kernels fit 128 registers, so four wavefronts per SIMD and 1024
+// threads per block), 8 in FP64 (their 200-odd registers allow two per SIMD);
+// taller blocks re-read fewer halo rows (1 + 2 / (waves * RY) loads per row)
+constexpr int blk_waves(bool fp64) { return fp64 ? 8 : 16; }
 constexpr int kRows = 2;      // plain rows per thread (tile height = kPlainTY * kRows)
 
 template <typename R>
@@ -91,7 +96,7 @@ struct WaveArgs {
     int fnl[4], fnq[4];            // tiles along x and along y
     int fstart[5], n_frame;        // prefix sums of frame tiles
     int nzc, zchunk, nrhs, n_items;
-    int blk;                       // 1: box tiles in block items of 4 stacked tiles (LDS row ring)
+    int blk;                       // 1: box tiles in block items of blk_waves stacked tiles (LDS row ring)
     int nb;                        // right-hand sides per box wavefront (1; 2 or 4 with block tiles, one row)
     int ngrp;                      // right-hand-side groups per tile in the item order (nrhs / nb rounded up)
     int rhs_outer;                 // 1: items ordered tile, z chunk, then right-hand-side group

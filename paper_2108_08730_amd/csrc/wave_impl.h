@@ -292,12 +292,13 @@ struct ItemBuf {
 
 // ---------------------------------------------------------------------------
 // unstretched-box tile.  BLK = false: one wavefront per tile of RY rows, which
-// loads its RY + 2 rows per plane.  BLK = true: the block's 4 wavefronts take
-// 4 stacked tiles of RY rows; each loads its own RY rows (wavefront 0 also the
-// row below the block, wavefront 3 the row above) and passes them to the
-// others through a two-plane LDS ring, so each row is read from memory once
-// per block instead of once per tile that needs it (1 + 2/(4 RY) instead of
-// 1 + 2/RY loads per output row), at one barrier per plane.
+// loads its RY + 2 rows per plane.  BLK = true: the block's BW wavefronts
+// (blk_waves) take BW stacked tiles of RY rows; each loads its own RY rows
+// (wavefront 0 also the row below the block, the last wavefront the row above)
+// and passes them to the others through a two-plane LDS ring, so each row is
+// read from memory once per block instead of once per tile that needs it
+// (1 + 2/(BW RY) instead of 1 + 2/RY loads per output row), at one barrier per
+// plane.
 // MA: first consistent-mass form (Sec. 2.1, eq. 8): the mass term of row i
 // weighs neighbour j by its own bulk modulus, i.e. the row's mass stencil acts
 // on v = k^2 u with k^2 = omega^2 / c_j^2 taken at each loaded point, while
@@ -310,14 +311,15 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     constexpr unsigned SV = sizeof(V);
     using Plane = BoxPlane<R, RY, MA>;
     constexpr int NL = BLK ? RY + 1 : RY + 2;   // rows this wavefront loads per plane
-    constexpr int KB = 4 * RY + 2;              // rows of a block plane in the ring
+    constexpr int BW = blk_waves(sizeof(R) == 8);
+    constexpr int KB = BW * RY + 2;             // rows of a block plane in the ring
     const GridData<R>& g = a.g;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx = a.px0 + tx * kWaveCols - 1 + lane;
     const bool inx = gx >= 0 && gx < g.nx;
     const bool outx = lane >= 1 && lane <= kWaveCols && gx < a.px0 + a.pw;
     const int gxc = min(max(gx, 0), g.nx - 1);
-    const int yb = a.py0 + ty * (BLK ? 4 * RY : RY);   // first output row of the tile (block)
+    const int yb = a.py0 + ty * (BLK ? BW * RY : RY);   // first output row of the tile (block)
     const int y0 = yb + (BLK ? wave * RY : 0);          // first output row of this wavefront
     const int z0 = zc * a.zchunk;
     const int z1 = min(z0 + a.zchunk, g.nz);
@@ -330,9 +332,9 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
     for (int k = 0; k < NL; ++k) {
         int yy;
         bool use = true;
-        if (BLK) {   // own rows, then the block's halo row (wavefronts 0 and 3)
-            yy = k < RY ? y0 + k : (wave == 0 ? yb - 1 : yb + 4 * RY);
-            use = k < RY || wave == 0 || wave == 3;
+        if (BLK) {   // own rows, then the block's halo row (first and last wavefront)
+            yy = k < RY ? y0 + k : (wave == 0 ? yb - 1 : yb + BW * RY);
+            use = k < RY || wave == 0 || wave == BW - 1;
         } else {
             yy = y0 - 1 + k;
         }
@@ -510,7 +512,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
 #pragma unroll
             for (int k = 0; k < RY; ++k) pl[(1 + wave * RY + k) * 64 + lane] = Lc.u[k];
             if (wave == 0) pl[lane] = Lc.u[RY];
-            if (wave == 3) pl[(KB - 1) * 64 + lane] = Lc.u[RY];
+            if (wave == BW - 1) pl[(KB - 1) * 64 + lane] = Lc.u[RY];
             if constexpr (MA) {
                 V* pv = pl + KB * 64;
                 auto kv = [&](int k) {
@@ -523,7 +525,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
 #pragma unroll
                 for (int k = 0; k < RY; ++k) pv[(1 + wave * RY + k) * 64 + lane] = kv(k);
                 if (wave == 0) pv[lane] = kv(RY);
-                if (wave == 3) pv[(KB - 1) * 64 + lane] = kv(RY);
+                if (wave == BW - 1) pv[(KB - 1) * 64 + lane] = kv(RY);
             }
             __syncthreads();
 #pragma unroll
@@ -571,7 +573,7 @@ __device__ __forceinline__ void box_item(const WaveArgs<R>& a, const TabEntry<R>
 
 // ---------------------------------------------------------------------------
 // Unstretched-box block tile with NB right-hand sides per wavefront (FP32):
-// the block's four wavefronts take one output row each (62 columns, lanes
+// the block's 16 wavefronts take one output row each (62 columns, lanes
 // along x) of NB consecutive right-hand sides rhs .. rhs + NB - 1, and share
 // their plane rows through a two-plane LDS ring as in box_item<BLK>.  The
 // table entry, velocity and coefficients of a point are formed once per
@@ -643,7 +645,8 @@ __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry
                                             typename V2<R>::T* ring, int tile, int zc, int rhs, int wave, int lane) {
     using V = typename V2<R>::T;
     constexpr unsigned SV = sizeof(V);
-    constexpr int KB = 6;                      // rows of a block plane in the ring (4 own + 2 halo)
+    constexpr int BW = blk_waves(sizeof(R) == 8);
+    constexpr int KB = BW + 2;                 // rows of a block plane in the ring (BW own + 2 halo)
     const GridData<R>& g = a.g;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int nvec = min(NB, a.nrhs - rhs);    // right-hand sides of this item (wave-uniform)
@@ -651,13 +654,13 @@ __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry
     const bool inx = gx >= 0 && gx < g.nx;
     const bool outx = lane >= 1 && lane <= kWaveCols && gx < a.px0 + a.pw;
     const int gxc = min(max(gx, 0), g.nx - 1);
-    const int yb = a.py0 + ty * 4;             // first output row of the block
+    const int yb = a.py0 + ty * BW;            // first output row of the block
     const int y0 = yb + wave;                  // this wavefront's output row
-    const int yh = wave == 0 ? yb - 1 : yb + 4;   // halo row (wavefronts 0 and 3)
+    const int yh = wave == 0 ? yb - 1 : yb + BW;   // halo row (first and last wavefront)
     const int z0 = zc * a.zchunk;
     const int z1 = min(z0 + a.zchunk, g.nz);
     const unsigned lo0 = (inx && y0 < g.ny) ? static_cast<unsigned>(y0 * g.nx + gx) * SV : kOff;
-    const unsigned lo1 = ((wave == 0 || wave == 3) && inx && yh >= 0 && yh < g.ny)
+    const unsigned lo1 = ((wave == 0 || wave == BW - 1) && inx && yh >= 0 && yh < g.ny)
                              ? static_cast<unsigned>(yh * g.nx + gx) * SV : kOff;
     const unsigned so = (outx && y0 < a.py0 + a.ph) ? static_cast<unsigned>(y0 * g.nx + gx) * SV : kOff;
     const unsigned mo = static_cast<unsigned>(min(y0, g.ny - 1) * g.nx + gxc);
@@ -752,7 +755,7 @@ __device__ __forceinline__ void box_item_nb(const WaveArgs<R>& a, const TabEntry
             V* pv = pl + v * (KB * 64);
             pv[(1 + wave) * 64 + lane] = Lc[v][0];
             if (wave == 0) pv[lane] = Lc[v][1];
-            if (wave == 3) pv[(KB - 1) * 64 + lane] = Lc[v][1];
+            if (wave == BW - 1) pv[(KB - 1) * 64 + lane] = Lc[v][1];
         }
         __syncthreads();
         const unsigned pso = static_cast<unsigned>(q - 1) * plane_b;
@@ -1038,7 +1041,7 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
     TabEntry<R>* tab = reinterpret_cast<TabEntry<R>*>(smem_raw);
     AxisNode<R>* zn = reinterpret_cast<AxisNode<R>*>(smem_raw + static_cast<size_t>(n_tab) * sizeof(TabEntry<R>));
     const R sig = g.inv_h2;
-    for (int t = threadIdx.x; t < n_tab; t += kBlock) {
+    for (int t = threadIdx.x; t < n_tab; t += static_cast<int>(blockDim.x)) {
         const EntryCoef<R> E = g.entry[g.fixed ? 0 : a.tab_lo + t];   // fixed weights: one entry everywhere
         TabEntry<R> e;
         e.s[0] = sig * E.s0; e.s[1] = sig * E.s1; e.s[2] = sig * E.s2; e.s[3] = sig * E.s3;
@@ -1049,7 +1052,7 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
         tab[t] = e;
     }
     const int nzl = z_lds_nodes(g.nz, g.zlo, g.zhi);
-    for (int t = threadIdx.x; t < nzl; t += kBlock) zn[t] = g.az[z_plane(t, g.zlo, g.zhi)];
+    for (int t = threadIdx.x; t < nzl; t += static_cast<int>(blockDim.x)) zn[t] = g.az[z_plane(t, g.zlo, g.zhi)];
     // row ring after the table slice and the z nodes, 16-byte aligned (as wave_ring_offset)
     const size_t ring_off = (static_cast<size_t>(n_tab) * sizeof(TabEntry<R>) +
                              static_cast<size_t>(nzl) * sizeof(AxisNode<R>) + 15) & ~static_cast<size_t>(15);
@@ -1080,9 +1083,10 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
             }
         }
     } else {
-        // block items: 4 frame tiles (one per wavefront) or one box block
-        // tile (4 stacked tiles sharing rows through the LDS ring)
-        const int nfb = (a.n_frame + 3) / 4;
+        // block items: BW frame tiles (one per wavefront) or one box block
+        // tile (BW stacked tiles sharing rows through the LDS ring)
+        constexpr int BW = blk_waves(sizeof(R) == 8);
+        const int nfb = (a.n_frame + BW - 1) / BW;
         const int nbt = nfb + a.n_plain;   // n_plain counts box block tiles here
         for (int bi = lb; bi < a.n_items; bi += nb) {
             // item order: right-hand-side group fastest, then block tile, then z chunk
@@ -1093,7 +1097,7 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
             const int bt = t % nbt;
             const int zc = t / nbt;
             if (bt < nfb) {
-                const int tile = bt * 4 + wave;
+                const int tile = bt * BW + wave;
                 if (tile < a.n_frame) {
                     int k = 0;
                     while (k < 3 && tile >= a.fstart[k + 1]) ++k;
@@ -1118,7 +1122,8 @@ __device__ __forceinline__ void wave27_body(const WaveArgs<R>& a, int nb, int lb
 
 template <typename R, int MODE, bool SHIFTED, int RY, int RQ, bool ROWC, bool BLK, int NB, bool MA = false,
           int NT = 0>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+__global__ __launch_bounds__(BLK ? 64 * blk_waves(sizeof(R) == 8) : kBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 void wave27_kernel(WaveArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // XCD-contiguous block order: block b runs on XCD b % 8; the grid is at
@@ -1161,7 +1166,7 @@ template <> struct FrameRows<double> { static constexpr int value = 1; };
 
 // blocks of one kernel that fit on the device at once (cached per kernel and
 // LDS size; queried on the current device)
-inline int resident_blocks(const void* fn, size_t lds) {
+inline int resident_blocks(const void* fn, size_t lds, int threads) {
     struct Entry { const void* fn; size_t lds; int dev; int blocks; };
     static thread_local Entry cache[64] = {};
     static thread_local int next = 0;
@@ -1170,7 +1175,7 @@ inline int resident_blocks(const void* fn, size_t lds) {
     for (const Entry& e : cache)
         if (e.fn == fn && e.lds == lds && e.dev == dev) return e.blocks;
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     const int blocks = per_cu * cus;
@@ -1187,10 +1192,11 @@ inline int launch_wave_kn(const WaveArgs<R>& a, hipStream_t s) {
     const size_t lds = wave_ring_offset(n_tab, z_lds_nodes(a.g.nz, a.g.zlo, a.g.zhi), sizeof(R) == 8) +
                        (BLK ? wave_ring_bytes(RY, NB, sizeof(R) == 8, MA) : 0);
     int blocks = BLK ? a.n_items : (a.n_items + (kBlock / 64) - 1) / (kBlock / 64);
-    const int cap = resident_blocks(fn, lds);
+    constexpr int threads = BLK ? 64 * blk_waves(sizeof(R) == 8) : kBlock;
+    const int cap = resident_blocks(fn, lds, threads);
     if (cap <= 0) return HELM27_EDEVICE;
     if (blocks > cap) blocks = cap;
-    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA, NT>, dim3(blocks), dim3(kBlock), lds,
+    H27_CHECK_HIP(launch(wave27_kernel<R, MODE, SHIFTED, RY, RQ, ROWC, BLK, NB, MA, NT>, dim3(blocks), dim3(threads), lds,
                          s, a));
     return HELM27_OK;
 }
