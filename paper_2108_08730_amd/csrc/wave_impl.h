@@ -155,12 +155,17 @@ __device__ __forceinline__ void bld(double2& v, Rsrc r, unsigned vo, unsigned so
 // the per-point data of launches that read them once.  Outputs of smaller
 // launches stay cached for the kernel that reads them next.
 constexpr int kNt = 2;
+// Stores take their whole offset in the vector operand (vo + so, below 2^32:
+// a lane's offset kOff = 2^31 plus a plane offset below 2^31 stays beyond
+// every buffer, a valid one stays inside): the compiler keeps the z loop's
+// plane offset in a vector register, and as the scalar operand it would wrap
+// every store in a loop over the lanes' distinct values.
 template <bool NT>
 __device__ __forceinline__ void bst(Cx<float> v, Rsrc r, unsigned vo, unsigned so) {
     u32x2 w;
     w.x = __float_as_uint(v.re);
     w.y = __float_as_uint(v.im);
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(vo), static_cast<int>(so), NT ? kNt : 0);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(vo + so), 0, NT ? kNt : 0);
 }
 template <bool NT>
 __device__ __forceinline__ void bst(Cx<double> v, Rsrc r, unsigned vo, unsigned so) {
@@ -169,7 +174,7 @@ __device__ __forceinline__ void bst(Cx<double> v, Rsrc r, unsigned vo, unsigned 
     w.y = static_cast<unsigned>(__double2hiint(v.re));
     w.z = static_cast<unsigned>(__double2loint(v.im));
     w.w = static_cast<unsigned>(__double2hiint(v.im));
-    __builtin_amdgcn_raw_buffer_store_b128(w, r, static_cast<int>(vo), static_cast<int>(so), NT ? kNt : 0);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, static_cast<int>(vo + so), 0, NT ? kNt : 0);
 }
 __device__ __forceinline__ int bld_u16(Rsrc r, unsigned vo, unsigned so, bool nt = false) {
     return static_cast<int>(nt ? __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(vo), static_cast<int>(so), kNt)
