@@ -297,7 +297,8 @@ int helm27_tune(helm27_op* op, int nrhs, int dtype, void* stream, int* best_rows
 /* Kernel family of the recompute stencil: 0 = one wavefront per tile, box and
  * PML frame in one launch (default); 1 = LDS-tiled blocks (one block per
  * 64 x 8 or 16 x 16 column tile); 2 = as 0, with the box tiles in groups of
- * four stacked tiles per block that share their plane rows through LDS.
+ * 16 (FP32) or 8 (FP64) stacked tiles per block, one per wavefront, that
+ * share their plane rows through LDS.
  * All compute the same operator.  Switches off the per-launch choice (see
  * helm27_tune).  Errors: EINVAL. */
 int helm27_set_kernel_variant(helm27_op* op, int variant);
